@@ -1,0 +1,175 @@
+"""Split-step throughput of the two-component GPE solver on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload: 1024 x 1024 grid, two components, complex64 state resident in HBM; g_uu = g_dd = g_ud
+= 10, k_L = 2, uniform Raman Omega = 1, detuning 0.2, harmonic trap, Thomas-Fermi start (seed 0).
+A step is one imaginary-time Strang step K(dt/2) R(dt) K(dt/2) with renormalisation (every stage of
+the hot path); real-time steps are reported beside it.  K steps are timed in batches of 100
+(one step_imag(100) call each) with HIP events; value = K / total time.
+
+Prints one JSON line.  Also reports the dominant kernel's HBM roofline fraction (algorithmic
+bytes over its mean launch time, measured with HIP events around every launch) and the FP64
+oracle's throughput on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_POINT_PASS = 32      # one pass reads and writes both complex64 components
+BYTES_PER_POINT_STEP = 64      # two passes per step
+
+
+def median_mad(xs):
+    import numpy as np
+    a = np.asarray(xs, dtype=float)
+    med = float(np.median(a))
+    return med, float(np.median(np.abs(a - med)))
+
+
+def _traffic_record(kernel_name, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (matched by source hash); else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        from paper_2010_15069_amd.build import source_hash
+        if rec.get("source_hash") != source_hash() or rec.get("workload") != workload:
+            return None
+        return rec.get("kernels", {}).get(kernel_name)
+    except Exception:
+        return None
+
+
+def cpu_baseline(p, psi0, seconds):
+    from oracle import OracleGPE
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    o = OracleGPE(p, workers=cores)
+    o.set_psi(psi0)
+    o.step_imag(1)  # warm-up (plans, caches)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.step_imag(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": n / el, "unit": "split-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} imaginary-time steps of the 1024^2 x 2 workload in complex128 "
+                      f"({el:.1f} s, scipy.fft workers={cores})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="metric_1024")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs one instance on one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_15069_amd import Solver
+    from workloads import initial_state, preset
+
+    p = preset(args.workload)
+    psi0 = initial_state(p, "tf", seed=0)
+    npts = p.nx * p.ny
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    s = Solver(p, stream=stream.cuda_stream)
+    s.set_psi(psi0)
+
+    def timed(step, k, batch):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(k // batch + 1)]
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        done = 0
+        i = 1
+        while done < k:
+            b = min(batch, k - done)
+            step(b)
+            evs[i].record(stream)
+            i += 1
+            done += b
+        torch.cuda.synchronize()
+        per = [evs[j - 1].elapsed_time(evs[j]) / batch for j in range(1, i)]
+        total_ms = evs[0].elapsed_time(evs[i - 1])
+        return total_ms, per
+
+    # imaginary time (headline)
+    s.step_imag(args.warmup)
+    total_ms, per = timed(s.step_imag, args.steps, args.batch)
+    med, mad = median_mad(per)
+    value = args.steps / (total_ms * 1e-3)
+    e_final = s.energy()
+
+    # real time, same workload
+    s.set_psi(psi0)
+    s.step_real(args.warmup)
+    total_r, per_r = timed(s.step_real, args.steps, args.batch)
+    med_r, mad_r = median_mad(per_r)
+
+    # per-kernel launch times (HIP events around every launch) -> roofline of the dominant kernel
+    s.set_psi(psi0)
+    row_ms, col_ms = s.profile_steps(200, imag=True)
+    dom_name, dom_ms = ("col_pass", col_ms) if col_ms >= row_ms else ("row_pass", row_ms)
+    alg_bytes = BYTES_PER_POINT_PASS * npts
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = _traffic_record(dom_name, args.workload)
+
+    out = {
+        "metric": "split-steps/s at 1024^2x2 c64 (%HBM roofline); ground-state time-to-1e-6 E",
+        "value": value,
+        "unit": "split-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {p.nx}x{p.ny} grid x 2 components, complex64 state, "
+                        f"imaginary-time Strang split steps with renormalisation, g=10 (all), k_L=2, "
+                        f"Omega=1 (k-space), delta=0.2, harmonic trap, Thomas-Fermi start",
+            "grid": [p.ny, p.nx], "components": 2, "dt": p.dt, "batch": args.batch,
+        },
+        "step_ms_median": med, "step_ms_mad": mad,
+        "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts * value / (HBM_PEAK_GBS * 1e9),
+        "real_time": {"value": args.steps / (total_r * 1e-3), "unit": "split-steps/s",
+                      "step_ms_median": med_r, "step_ms_mad": mad_r},
+        "kernels_ms": {"row_pass": row_ms, "col_pass": col_ms},
+        "energy_after_timed_steps": e_final,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

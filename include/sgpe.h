@@ -1,0 +1,135 @@
+/*
+ * sgpe.h -- C ABI of the MI355X (gfx950) split-step solver for the two-component quasi-2D
+ * Gross-Pitaevskii equation.
+ *
+ * Method (Smith, Cooke & LeBlanc, "GPU-accelerated solutions of the nonlinear Schroedinger
+ * equation for simulating 2D spinor BECs"):
+ *   - model: Sec. 3.1, Eq. (GPEcomponent) with the Hamiltonian pieces of Eqs. (H1)-(H4);
+ *   - grids and propagators: Sec. 3.2, Eq. (TEOp);
+ *   - time-splitting spectral (TSSP) step with Strang splitting, real and imaginary time, and
+ *     renormalisation to the atom number after each imaginary-time step: Sec. 3.2.
+ * Dimensionless harmonic-oscillator units (Sec. 6): hbar = m = omega_perp = 1.
+ *
+ * Conventions that the paper leaves open and this library fixes:
+ *   - i d/dt psi = H psi; real-time propagators exp(-i H dt), imaginary-time exp(-H dtau);
+ *   - H_K(k) = |k|^2/2 * 1 + k_L k_x sigma_z + (Omega/2) sigma_x  (k-space 2x2, uniform Omega);
+ *   - H_R(r) = V(r) 1 + (delta/2) sigma_z + diag(g_uu n_u + g_ud n_d, g_dd n_d + g_ud n_u)
+ *              + (Omega(x)/2) sigma_x,  V = (wx^2 x^2 + wy^2 y^2)/2, Omega(x) = omega_r0 tanh(x/omega_rw);
+ *   - one step = K(dt/2) R(dt) K(dt/2); R exponentiates H_R with the densities of its input;
+ *   - imaginary time rescales the total (both components) to norm0 after every step;
+ *   - grid x_j = -xmax + j*dx, dx = 2*xmax/nx (periodic, endpoint excluded), k_x in FFT order
+ *     with the Nyquist bin at -pi/dx; the same along y;
+ *   - energy per particle: the Gross-Pitaevskii functional with 1/2 on the interaction terms,
+ *     divided by the norm.
+ *
+ * Threading: a context is not thread-safe; distinct contexts are independent.
+ * Errors: every call returns a status; nothing aborts and no C++ exception crosses the ABI.
+ * Validation errors are returned before any device work.  A non-finite norm found during
+ * imaginary-time stepping is latched in the context and reported by the next synchronising call
+ * (sgpe_get_psi, sgpe_norm, sgpe_energy, sgpe_synchronize) as SGPE_ENONFINITE.
+ */
+#ifndef SGPE_H
+#define SGPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGPE_OK = 0,
+  SGPE_EINVAL = 1,      /* invalid argument or parameter (reported before any device work) */
+  SGPE_ENOMEM = 2,      /* device allocation failed, or the grid exceeds the supported size */
+  SGPE_EDEVICE = 3,     /* no usable gfx950 device, or a HIP runtime error */
+  SGPE_ENONFINITE = 4,  /* NaN/Inf in an input state, or a non-finite norm during stepping */
+  SGPE_ESTATE = 5       /* call not valid in the current state (e.g. stepping before set_psi) */
+} sgpe_status;
+
+/* Problem parameters.  Plain data; the same fields as the Python dataclass workloads.Params. */
+typedef struct {
+  int32_t nx, ny;         /* grid points, powers of two in [16, 4096]                  (Sec. 3.2) */
+  double xmax, ymax;      /* box [-xmax, xmax) x [-ymax, ymax), both > 0               (Sec. 3.2) */
+  double g_uu, g_dd, g_ud;/* mean-field couplings g_{up up}, g_{dn dn}, g_{up dn}       (Eq. H3)  */
+  double k_l;             /* spin-momentum coefficient: + k_l k_x sigma_z in H_K        (Eq. H1)  */
+  double omega;           /* spatially uniform Raman coupling, (omega/2) sigma_x in H_K (Eq. H4)  */
+  double delta;           /* uniform detuning, (delta/2) sigma_z in H_R                 (Eq. H2)  */
+  double wx, wy;          /* trap V = (wx^2 x^2 + wy^2 y^2)/2, both >= 0               (Eq. H2)  */
+  double omega_r0;        /* spatial Raman coupling Omega(x) = omega_r0 tanh(x/omega_rw) in H_R;  */
+  double omega_rw;        /*   omega_r0 = 0 disables it; omega_rw > 0 when enabled     (Eq. H4)  */
+  double dt;              /* time step (> 0), used for real and imaginary steps        (Eq. TEOp) */
+  double norm0;           /* imaginary-time target norm dx dy sum |psi|^2 (> 0)        (Sec. 3.2) */
+} sgpe_params;
+
+typedef struct sgpe_ctx sgpe_ctx;
+
+/* Check a parameter set on the host (no device calls).  SGPE_OK or SGPE_EINVAL. */
+sgpe_status sgpe_validate_params(const sgpe_params* p);
+
+/* Number of visible HIP devices, or a negative value if the runtime reports none/an error.
+ * Host-side query; never fails with an exception. */
+int32_t sgpe_device_count(void);
+
+/* Create a solver context on the current HIP device.
+ *   hip_stream: a hipStream_t to enqueue all work on, or NULL for the null stream.  Borrowed.
+ *   psi_dev:    NULL to let the context allocate the state (16*nx*ny bytes), or a device pointer
+ *               of at least 16*nx*ny bytes, 16-byte aligned, which the context borrows and which
+ *               must outlive it.  The device layout is [ny][nx] of {re_up, im_up, re_dn, im_dn}
+ *               (float32).
+ * On success *out receives the context; on failure *out is set to NULL.  The state is
+ * undefined until sgpe_set_psi; stepping before that returns SGPE_ESTATE.
+ * Errors: SGPE_EINVAL (bad params or NULL out), SGPE_EDEVICE (no device / not gfx950 /
+ * runtime error), SGPE_ENOMEM. */
+sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, sgpe_ctx** out);
+
+/* Release the context and everything it allocated (not a borrowed state).  NULL is a no-op. */
+void sgpe_destroy(sgpe_ctx* ctx);
+
+/* Copy a host state in: psi_host is complex128, shape (2, ny, nx), C order, re/im interleaved
+ * (component 0 = up).  It is rounded once to complex64.  Synchronous.
+ * Errors: SGPE_EINVAL (NULL), SGPE_ENONFINITE (NaN/Inf in the input; the state is unchanged). */
+sgpe_status sgpe_set_psi(sgpe_ctx* ctx, const double* psi_host);
+
+/* Copy the state out in the same complex128 layout.  Synchronises the stream. */
+sgpe_status sgpe_get_psi(sgpe_ctx* ctx, double* psi_host);
+
+/* Advance n >= 0 real-time steps (Sec. 3.2).  Asynchronous on the context's stream.  The
+ * fused schedule is K(dt/2) [R(dt) K(dt)]^(n-1) R(dt) K(dt/2); its result equals n separate
+ * K(dt/2) R(dt) K(dt/2) steps up to rounding.  Errors: SGPE_EINVAL (n < 0), SGPE_ESTATE. */
+sgpe_status sgpe_step_real(sgpe_ctx* ctx, int64_t n);
+
+/* Advance n >= 0 imaginary-time steps, rescaling the total norm to norm0 after each one
+ * (Sec. 3.2).  Asynchronous.  Errors as sgpe_step_real. */
+sgpe_status sgpe_step_imag(sgpe_ctx* ctx, int64_t n);
+
+/* Energy per particle of the current state (Gross-Pitaevskii functional, Eqs. (H1)-(H4) with
+ * 1/2 on the interaction terms, divided by the norm).  Accumulated in fp64.  Synchronises. */
+sgpe_status sgpe_energy(sgpe_ctx* ctx, double* e_per_particle);
+
+/* Norm dx dy sum |psi|^2 of the current state (both components), accumulated in fp64.
+ * Synchronises. */
+sgpe_status sgpe_norm(sgpe_ctx* ctx, double* norm);
+
+/* Wait for all work enqueued by the context; reports a latched error. */
+sgpe_status sgpe_synchronize(sgpe_ctx* ctx);
+
+/* Measurement helper: run n real-time (imag = 0) or imaginary-time (imag = 1) steady-state
+ * steps with a HIP event pair around every kernel launch, and return the mean duration in
+ * milliseconds of the row pass (x transforms + real-space exponential) and of the column pass
+ * (y transforms + k-space propagator).  The state advances exactly as with sgpe_step_*(n).
+ * Synchronises.  Either output pointer may be NULL. */
+sgpe_status sgpe_profile_steps(sgpe_ctx* ctx, int32_t imag, int64_t n,
+                               double* row_ms, double* col_ms);
+
+/* Static description of a status code.  Never NULL. */
+const char* sgpe_strerror(sgpe_status s);
+
+/* Tuning knob: columns per workgroup of the column pass (0 = default).  Values are powers of
+ * two in [1, 8] subject to the device's LDS limit; an unsupported value returns SGPE_EINVAL. */
+sgpe_status sgpe_set_col_tile(sgpe_ctx* ctx, int32_t columns);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGPE_H */

@@ -1,0 +1,10 @@
+"""MI355X (gfx950) split-step solver for the two-component quasi-2D Gross-Pitaevskii equation.
+
+The compute path is the HIP library libsgpe.so (C ABI in include/sgpe.h); this package is its
+thin Python binding.  Build it with ``python -m paper_2010_15069_amd.build``.
+"""
+from ._lib import LIB_PATH, SgpeError, SgpeParams, STATUS_NAMES
+from .solver import Solver, device_count, validate_params
+
+__all__ = ["Solver", "SgpeError", "SgpeParams", "STATUS_NAMES", "LIB_PATH", "device_count",
+           "validate_params"]

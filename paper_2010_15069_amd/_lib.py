@@ -1,0 +1,117 @@
+"""ctypes binding of libsgpe.so (include/sgpe.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import importlib.util
+import os
+
+_PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG_DIR, "libsgpe.so")
+
+SGPE_OK, SGPE_EINVAL, SGPE_ENOMEM, SGPE_EDEVICE, SGPE_ENONFINITE, SGPE_ESTATE = range(6)
+STATUS_NAMES = {0: "SGPE_OK", 1: "SGPE_EINVAL", 2: "SGPE_ENOMEM", 3: "SGPE_EDEVICE",
+                4: "SGPE_ENONFINITE", 5: "SGPE_ESTATE"}
+
+
+class SgpeParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("xmax", ctypes.c_double), ("ymax", ctypes.c_double),
+        ("g_uu", ctypes.c_double), ("g_dd", ctypes.c_double), ("g_ud", ctypes.c_double),
+        ("k_l", ctypes.c_double), ("omega", ctypes.c_double), ("delta", ctypes.c_double),
+        ("wx", ctypes.c_double), ("wy", ctypes.c_double),
+        ("omega_r0", ctypes.c_double), ("omega_rw", ctypes.c_double),
+        ("dt", ctypes.c_double), ("norm0", ctypes.c_double),
+    ]
+
+    @classmethod
+    def from_obj(cls, p) -> "SgpeParams":
+        """From any object (or dict) with the fields of workloads.Params."""
+        get = (lambda k: p[k]) if isinstance(p, dict) else (lambda k: getattr(p, k))
+        out = cls()
+        for name, ctype in cls._fields_:
+            v = get(name)
+            setattr(out, name, int(v) if ctype is ctypes.c_int32 else float(v))
+        return out
+
+
+class SgpeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        msg = _lib().sgpe_strerror(self.status).decode() if _LIB is not None else ""
+        super().__init__(f"{where}: {STATUS_NAMES.get(self.status, self.status)} ({msg})")
+
+
+_LIB = None
+
+EXPORTS = [
+    "sgpe_validate_params", "sgpe_device_count", "sgpe_create", "sgpe_destroy", "sgpe_set_psi",
+    "sgpe_get_psi", "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
+    "sgpe_synchronize", "sgpe_profile_steps", "sgpe_strerror", "sgpe_set_col_tile",
+]
+
+
+def _preload_hip_runtime():
+    """PyTorch ships its own HIP runtime (SONAME libamdhip64.so.7, file libamdhip64.so).  Load
+    that file first so that libsgpe's dependency resolves to it whether or not torch is imported
+    before or after us: one process must never hold two HIP runtimes."""
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return
+    path = os.path.join(list(spec.submodule_search_locations)[0], "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+
+
+def _lib():
+    """Load libsgpe.so; raises if it has not been built (there is no fallback path)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_15069_amd.build`")
+    _preload_hip_runtime()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    st = ctypes.c_int
+    lib.sgpe_validate_params.argtypes = [P(SgpeParams)]
+    lib.sgpe_validate_params.restype = st
+    lib.sgpe_device_count.argtypes = []
+    lib.sgpe_device_count.restype = ctypes.c_int32
+    lib.sgpe_create.argtypes = [P(SgpeParams), vp, vp, P(vp)]
+    lib.sgpe_create.restype = st
+    lib.sgpe_destroy.argtypes = [vp]
+    lib.sgpe_destroy.restype = None
+    lib.sgpe_set_psi.argtypes = [vp, vp]
+    lib.sgpe_set_psi.restype = st
+    lib.sgpe_get_psi.argtypes = [vp, vp]
+    lib.sgpe_get_psi.restype = st
+    lib.sgpe_step_real.argtypes = [vp, ctypes.c_int64]
+    lib.sgpe_step_real.restype = st
+    lib.sgpe_step_imag.argtypes = [vp, ctypes.c_int64]
+    lib.sgpe_step_imag.restype = st
+    lib.sgpe_energy.argtypes = [vp, P(ctypes.c_double)]
+    lib.sgpe_energy.restype = st
+    lib.sgpe_norm.argtypes = [vp, P(ctypes.c_double)]
+    lib.sgpe_norm.restype = st
+    lib.sgpe_synchronize.argtypes = [vp]
+    lib.sgpe_synchronize.restype = st
+    lib.sgpe_profile_steps.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double),
+                                       P(ctypes.c_double)]
+    lib.sgpe_profile_steps.restype = st
+    lib.sgpe_strerror.argtypes = [ctypes.c_int]
+    lib.sgpe_strerror.restype = ctypes.c_char_p
+    lib.sgpe_set_col_tile.argtypes = [vp, ctypes.c_int32]
+    lib.sgpe_set_col_tile.restype = st
+    _LIB = lib
+    return lib
+
+
+def lib():
+    return _lib()
+
+
+def check(status: int, where: str) -> None:
+    if status != SGPE_OK:
+        raise SgpeError(status, where)

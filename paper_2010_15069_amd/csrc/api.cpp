@@ -1,0 +1,576 @@
+// Host side of the split-step solver: parameter validation, fp64 construction of the operator
+// and twiddle tables, the fused step schedule, and the C ABI declared in include/sgpe.h.
+#include "sgpe.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sgpe_internal.hpp"
+
+using sgpe::ColArgs;
+using sgpe::EnergyArgs;
+using sgpe::RowArgs;
+
+namespace {
+
+constexpr int kMinN = 16;
+constexpr int kMaxN = 4096;
+constexpr int kMaxPartials = 4096;
+
+bool is_pow2(int32_t n) { return n > 0 && (n & (n - 1)) == 0; }
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct sgpe_ctx {
+  sgpe_params p{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  float4* psi = nullptr;
+  bool own_psi = false;
+  float4* scratch = nullptr;
+  float4* tw_x = nullptr;
+  float4* tw_y = nullptr;
+  // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
+  float4* kx_tab[4] = {nullptr, nullptr, nullptr, nullptr};
+  float2* ky_tab[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* hbx = nullptr;  // dt * Omega(x_j) / 2, only with a spatial Raman coupling
+  double* partials = nullptr;
+  double* epart = nullptr;  // energy partials (row: 2 per block, then col: 1 per block)
+  double* npart = nullptr;  // norm partials
+  size_t max_lds = 0;       // dynamic LDS bytes available per workgroup
+  int rows = 1;             // rows per row-pass workgroup
+  int cols = 1;             // columns per column-pass workgroup
+  bool full2x2 = false;
+  bool has_state = false;
+  sgpe_status latched = SGPE_OK;
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+sgpe_status dev_alloc(sgpe_ctx* c, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return SGPE_ENOMEM;
+  }
+  c->allocations.push_back(*ptr);
+  return SGPE_OK;
+}
+
+template <class T>
+sgpe_status upload(sgpe_ctx* c, T** dst, const std::vector<T>& host) {
+  void* p = nullptr;
+  sgpe_status st = dev_alloc(c, &p, host.size() * sizeof(T));
+  if (st != SGPE_OK) return st;
+  if (hipMemcpy(p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  *dst = static_cast<T*>(p);
+  return SGPE_OK;
+}
+
+// Forward roots exp(-2 pi i j / n), each as an fp32 hi part and the fp32 rounding of the rest.
+std::vector<float4> twiddles(int n) {
+  std::vector<float4> t(n);
+  for (int j = 0; j < n; ++j) {
+    const double a = -2.0 * M_PI * double(j) / double(n);
+    const double c = std::cos(a), s = std::sin(a);
+    const float ch = float(c), sh = float(s);
+    t[j] = make_float4(ch, sh, float(c - double(ch)), float(s - double(sh)));
+  }
+  return t;
+}
+
+// FFT-ordered angular wave numbers: 2 pi fftfreq(n, d).
+double kval(int j, int n, double d) {
+  const int m = j < n / 2 ? j : j - n;
+  return 2.0 * M_PI * double(m) / (double(n) * d);
+}
+
+// k-space 2x2 propagator factored as P(k_y) M'(k_x) with
+//   M'(k_x) = e^{-h kx^2/2 (i)} [ c 1 - s (b . sigma) ],  b = (omega/2, k_l k_x),
+//   P(k_y)  = e^{-h ky^2/2 (i)};
+// stored as M' - 1 (four complex entries) and P - 1, to fp32 relative accuracy.
+void k_tables(const sgpe_params& p, bool imag, double h, std::vector<float4>& kx_out,
+              std::vector<float2>& ky_out) {
+  const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
+  kx_out.assign(2 * size_t(p.nx), make_float4(0, 0, 0, 0));
+  ky_out.assign(size_t(p.ny), make_float2(0, 0));
+  for (int j = 0; j < p.nx; ++j) {
+    const double kx = kval(j, p.nx, dx);
+    const double bx = 0.5 * p.omega, bz = p.k_l * kx;
+    const double bm = std::hypot(bx, bz);
+    const double al = 0.5 * h * kx * kx;
+    double m11r, m11i, m12r, m12i, m22r, m22i;
+    if (!imag) {
+      const double c = std::cos(h * bm);
+      const double s = bm > 0.0 ? std::sin(h * bm) / bm : h;
+      const double pr = std::cos(al), pi = -std::sin(al);
+      // pref * (c - i s bz), pref * (-i s bx), pref * (c + i s bz)
+      m11r = pr * c + pi * s * bz;  m11i = pi * c - pr * s * bz;
+      m12r = pi * s * bx;           m12i = -pr * s * bx;
+      m22r = pr * c - pi * s * bz;  m22i = pi * c + pr * s * bz;
+    } else {
+      const double ch = std::cosh(h * bm);
+      const double sh = bm > 0.0 ? std::sinh(h * bm) / bm : h;
+      const double pr = std::exp(-al);
+      m11r = pr * (ch - sh * bz);  m11i = 0.0;
+      m12r = -pr * sh * bx;        m12i = 0.0;
+      m22r = pr * (ch + sh * bz);  m22i = 0.0;
+    }
+    kx_out[2 * size_t(j)] = make_float4(float(m11r - 1.0), float(m11i), float(m12r), float(m12i));
+    kx_out[2 * size_t(j) + 1] = make_float4(float(m12r), float(m12i), float(m22r - 1.0), float(m22i));
+  }
+  for (int i = 0; i < p.ny; ++i) {
+    const double ky = kval(i, p.ny, dy);
+    const double be = 0.5 * h * ky * ky;
+    if (!imag) {
+      const double sh = std::sin(0.5 * be);
+      ky_out[i] = make_float2(float(-2.0 * sh * sh), float(-std::sin(be)));
+    } else {
+      ky_out[i] = make_float2(float(std::expm1(-be)), 0.0f);
+    }
+  }
+}
+
+sgpe_status status_of(hipError_t e) {
+  if (e == hipSuccess) return SGPE_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SGPE_ENOMEM;
+  return SGPE_EDEVICE;
+}
+
+RowArgs row_args(const sgpe_ctx* c) {
+  const sgpe_params& p = c->p;
+  RowArgs a{};
+  a.psi = c->psi;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.rows_per_block = c->rows;
+  a.tw = c->tw_x;
+  a.scale = 1.0f;
+  a.partials = nullptr;
+  a.n_partials = 0;
+  const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
+  const double npts = double(p.nx) * double(p.ny);
+  a.norm0 = p.norm0;
+  a.parseval_w = dx * dy / npts;
+  a.inv_npts = 1.0 / npts;
+  a.x0 = float(-p.xmax);
+  a.dx = float(dx);
+  a.y0 = float(-p.ymax);
+  a.dy = float(dy);
+  const double h = p.dt;
+  a.hvx = float(0.5 * h * p.wx * p.wx);
+  a.hvy = float(0.5 * h * p.wy * p.wy);
+  a.hdelta2 = float(0.5 * h * p.delta);
+  a.hg_uu = float(h * p.g_uu);
+  a.hg_dd = float(h * p.g_dd);
+  a.hg_ud = float(h * p.g_ud);
+  a.hbx = c->hbx;
+  return a;
+}
+
+ColArgs col_args(const sgpe_ctx* c, bool imag, bool half) {
+  ColArgs a{};
+  a.psi = c->psi;
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.cols = c->cols;
+  a.tw = c->tw_y;
+  const int idx = 2 * (imag ? 1 : 0) + (half ? 1 : 0);
+  a.kx_tab = c->kx_tab[idx];
+  a.ky_tab = c->ky_tab[idx];
+  a.partials = c->partials;
+  return a;
+}
+
+// The fused schedule of n steps: K(dt/2) [R K(dt)]^(n-1) R K(dt/2), with the normalisation of
+// step i applied (as a scale) at the start of the next row pass.
+sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev) {
+  if (n == 0) return SGPE_OK;
+  const double npts = double(c->p.nx) * double(c->p.ny);
+  const float inv_n = float(1.0 / npts);  // exact: a power of two
+  hipStream_t s = c->stream;
+  hipError_t e;
+  RowArgs ra = row_args(c);
+  e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, s);
+  if (e != hipSuccess) return status_of(e);
+  e = sgpe::launch_col(col_args(c, imag, true), sgpe::NORM_NONE, s);
+  if (e != hipSuccess) return status_of(e);
+  size_t evi = 0;
+  for (int64_t i = 1; i <= n; ++i) {
+    RowArgs r = ra;
+    r.scale = inv_n;
+    if (imag && i > 1) {
+      r.partials = c->partials;
+      r.n_partials = c->p.nx / c->cols;
+    }
+    if (ev) (void)hipEventRecord((*ev)[evi++], s);
+    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, s);
+    if (e != hipSuccess) return status_of(e);
+    if (ev) (void)hipEventRecord((*ev)[evi++], s);
+    const bool last = (i == n);
+    const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
+    e = sgpe::launch_col(col_args(c, imag, last), nm, s);
+    if (e != hipSuccess) return status_of(e);
+    if (ev) (void)hipEventRecord((*ev)[evi++], s);
+  }
+  RowArgs r = ra;
+  r.scale = inv_n;
+  if (imag) {
+    r.partials = c->partials;
+    r.n_partials = c->p.nx / c->cols;
+  }
+  e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, s);
+  return status_of(e);
+}
+
+sgpe_status check_ctx(sgpe_ctx* c) {
+  if (!c) return SGPE_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  return SGPE_OK;
+}
+
+sgpe_status sync_and_latch(sgpe_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  return c->latched;
+}
+
+}  // namespace
+
+extern "C" {
+
+sgpe_status sgpe_validate_params(const sgpe_params* p) {
+  if (!p) return SGPE_EINVAL;
+  if (!is_pow2(p->nx) || !is_pow2(p->ny)) return SGPE_EINVAL;
+  if (p->nx < kMinN || p->ny < kMinN || p->nx > kMaxN || p->ny > kMaxN) return SGPE_EINVAL;
+  const double vals[] = {p->xmax, p->ymax, p->g_uu, p->g_dd, p->g_ud, p->k_l, p->omega, p->delta,
+                         p->wx, p->wy, p->omega_r0, p->omega_rw, p->dt, p->norm0};
+  for (double v : vals)
+    if (!is_finite(v)) return SGPE_EINVAL;
+  if (!(p->xmax > 0.0) || !(p->ymax > 0.0)) return SGPE_EINVAL;
+  if (!(p->dt > 0.0) || !(p->norm0 > 0.0)) return SGPE_EINVAL;
+  if (p->wx < 0.0 || p->wy < 0.0) return SGPE_EINVAL;
+  if (p->omega_r0 != 0.0 && !(p->omega_rw > 0.0)) return SGPE_EINVAL;
+  return SGPE_OK;
+}
+
+int32_t sgpe_device_count(void) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return -int32_t(e);
+  }
+  return n;
+}
+
+const char* sgpe_strerror(sgpe_status s) {
+  switch (s) {
+    case SGPE_OK: return "success";
+    case SGPE_EINVAL: return "invalid argument";
+    case SGPE_ENOMEM: return "out of device memory or grid too large";
+    case SGPE_EDEVICE: return "no usable gfx950 device or HIP runtime error";
+    case SGPE_ENONFINITE: return "non-finite value in the state";
+    case SGPE_ESTATE: return "call not valid in the current state";
+  }
+  return "unknown status";
+}
+
+sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, sgpe_ctx** out) {
+  if (!out) return SGPE_EINVAL;
+  *out = nullptr;
+  sgpe_status st = sgpe_validate_params(p);
+  if (st != SGPE_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SGPE_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SGPE_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SGPE_EDEVICE;
+  if (psi_dev && (reinterpret_cast<uintptr_t>(psi_dev) & 15u) != 0) return SGPE_EINVAL;
+
+  sgpe_ctx* c = new (std::nothrow) sgpe_ctx();
+  if (!c) return SGPE_ENOMEM;
+  c->p = *p;
+  c->device = dev;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  // the kernels' static LDS (reduction scratch) is < 256 bytes
+  c->max_lds = prop.sharedMemPerBlock > 256 ? size_t(prop.sharedMemPerBlock) - 256 : 0;
+  c->rows = sgpe::row_rows_per_block(p->nx, p->ny, c->max_lds);
+  c->cols = sgpe::col_default_cols(p->nx, p->ny, c->max_lds);
+  c->full2x2 = (p->omega_r0 != 0.0);
+  if (sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds) {
+    delete c;
+    return SGPE_ENOMEM;
+  }
+
+  const size_t npts = size_t(p->nx) * size_t(p->ny);
+  auto fail = [&](sgpe_status s) {
+    sgpe_destroy(c);
+    return s;
+  };
+  if (psi_dev) {
+    c->psi = static_cast<float4*>(psi_dev);
+  } else {
+    void* ptr = nullptr;
+    if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return fail(st);
+    c->psi = static_cast<float4*>(ptr);
+    c->own_psi = true;
+  }
+  if ((st = upload(c, &c->tw_x, twiddles(p->nx))) != SGPE_OK) return fail(st);
+  if ((st = upload(c, &c->tw_y, twiddles(p->ny))) != SGPE_OK) return fail(st);
+  for (int imag = 0; imag < 2; ++imag) {
+    for (int half = 0; half < 2; ++half) {
+      std::vector<float4> kx;
+      std::vector<float2> ky;
+      k_tables(*p, imag != 0, half ? 0.5 * p->dt : p->dt, kx, ky);
+      const int idx = 2 * imag + half;
+      if ((st = upload(c, &c->kx_tab[idx], kx)) != SGPE_OK) return fail(st);
+      if ((st = upload(c, &c->ky_tab[idx], ky)) != SGPE_OK) return fail(st);
+    }
+  }
+  if (c->full2x2) {
+    std::vector<float> hb(p->nx);
+    const double dx = 2.0 * p->xmax / p->nx;
+    for (int j = 0; j < p->nx; ++j) {
+      const double x = -p->xmax + dx * j;
+      hb[j] = float(0.5 * p->dt * p->omega_r0 * std::tanh(x / p->omega_rw));
+    }
+    if ((st = upload(c, &c->hbx, hb)) != SGPE_OK) return fail(st);
+  }
+  void* ptr = nullptr;
+  if ((st = dev_alloc(c, &ptr, kMaxPartials * sizeof(double))) != SGPE_OK) return fail(st);
+  c->partials = static_cast<double*>(ptr);
+  if ((st = dev_alloc(c, &ptr, (2 * size_t(kMaxN) + kMaxPartials) * sizeof(double))) != SGPE_OK) return fail(st);
+  c->epart = static_cast<double*>(ptr);
+  if ((st = dev_alloc(c, &ptr, sgpe::norm_blocks() * sizeof(double))) != SGPE_OK) return fail(st);
+  c->npart = static_cast<double*>(ptr);
+  *out = c;
+  return SGPE_OK;
+}
+
+void sgpe_destroy(sgpe_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (void* ptr : c->allocations) (void)hipFree(ptr);
+  (void)hipGetLastError();
+  delete c;
+}
+
+sgpe_status sgpe_set_col_tile(sgpe_ctx* c, int32_t columns) {
+  if (!c) return SGPE_EINVAL;
+  if (columns == 0) {
+    c->cols = sgpe::col_default_cols(c->p.nx, c->p.ny, c->max_lds);
+    return SGPE_OK;
+  }
+  if (!sgpe::col_cols_supported(c->p.nx, c->p.ny, columns, c->max_lds)) return SGPE_EINVAL;
+  c->cols = columns;
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!h) return SGPE_EINVAL;
+  const size_t nx = size_t(c->p.nx), ny = size_t(c->p.ny), npts = nx * ny;
+  for (size_t i = 0; i < 4 * npts; ++i)
+    if (!std::isfinite(h[i])) return SGPE_ENONFINITE;
+  std::vector<float4> buf(npts);
+  const double* up = h;
+  const double* dn = h + 2 * npts;
+  for (size_t i = 0; i < npts; ++i)
+    buf[i] = make_float4(float(up[2 * i]), float(up[2 * i + 1]), float(dn[2 * i]), float(dn[2 * i + 1]));
+  if (hipMemcpyAsync(c->psi, buf.data(), npts * sizeof(float4), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  c->has_state = true;
+  c->latched = SGPE_OK;
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_get_psi(sgpe_ctx* c, double* h) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!h) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const size_t npts = size_t(c->p.nx) * size_t(c->p.ny);
+  std::vector<float4> buf(npts);
+  if (hipMemcpyAsync(buf.data(), c->psi, npts * sizeof(float4), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  bool ok = true;
+  double* up = h;
+  double* dn = h + 2 * npts;
+  for (size_t i = 0; i < npts; ++i) {
+    const float4 w = buf[i];
+    up[2 * i] = w.x;
+    up[2 * i + 1] = w.y;
+    dn[2 * i] = w.z;
+    dn[2 * i + 1] = w.w;
+    ok = ok && std::isfinite(w.x) && std::isfinite(w.y) && std::isfinite(w.z) && std::isfinite(w.w);
+  }
+  if (!ok) c->latched = SGPE_ENONFINITE;
+  return c->latched;
+}
+
+static sgpe_status step_common(sgpe_ctx* c, int64_t n, bool imag) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (n < 0) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  return run_steps(c, n, imag, nullptr);
+}
+
+sgpe_status sgpe_step_real(sgpe_ctx* c, int64_t n) { return step_common(c, n, false); }
+sgpe_status sgpe_step_imag(sgpe_ctx* c, int64_t n) { return step_common(c, n, true); }
+
+sgpe_status sgpe_synchronize(sgpe_ctx* c) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  return sync_and_latch(c);
+}
+
+sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!out) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const long long npts = (long long)c->p.nx * c->p.ny;
+  const int nb = sgpe::norm_blocks();
+  hipError_t e = sgpe::launch_norm(c->psi, npts, c->npart, nb, c->stream);
+  if (e != hipSuccess) return status_of(e);
+  std::vector<double> part(nb);
+  if (hipMemcpyAsync(part.data(), c->npart, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  double s = 0.0;
+  for (double v : part) s += v;
+  const double dx = 2.0 * c->p.xmax / c->p.nx, dy = 2.0 * c->p.ymax / c->p.ny;
+  *out = dx * dy * s;
+  if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
+  return c->latched;
+}
+
+sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!out) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const sgpe_params& p = c->p;
+  const size_t npts = size_t(p.nx) * size_t(p.ny);
+  if (!c->scratch) {
+    void* ptr = nullptr;
+    if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return st;
+    c->scratch = static_cast<float4*>(ptr);
+  }
+  const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
+  EnergyArgs a{};
+  a.psi = c->psi;
+  a.scratch = c->scratch;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.rows_per_block = c->rows;
+  a.cols = sgpe::col_default_cols(p.nx, p.ny, c->max_lds);
+  a.twx = c->tw_x;
+  a.twy = c->tw_y;
+  a.xmin = -p.xmax;
+  a.dx = dx;
+  a.ymin = -p.ymax;
+  a.dy = dy;
+  a.wx2h = 0.5 * p.wx * p.wx;
+  a.wy2h = 0.5 * p.wy * p.wy;
+  a.delta = p.delta;
+  a.g_uu = p.g_uu;
+  a.g_dd = p.g_dd;
+  a.g_ud = p.g_ud;
+  a.k_l = p.k_l;
+  a.omega = p.omega;
+  a.omega_r0 = p.omega_r0;
+  a.omega_rw = p.omega_rw;
+  a.dkx = M_PI / p.xmax;
+  a.dky = M_PI / p.ymax;
+  const int nrb = p.ny / c->rows;
+  const int ncb = p.nx / a.cols;
+  a.row_partials = c->epart;
+  a.col_partials = c->epart + 2 * nrb;
+  hipError_t e = sgpe::launch_energy(a, c->stream);
+  if (e != hipSuccess) return status_of(e);
+  std::vector<double> part(2 * size_t(nrb) + ncb);
+  if (hipMemcpyAsync(part.data(), c->epart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  double er = 0.0, nr = 0.0, ek = 0.0;
+  for (int b = 0; b < nrb; ++b) {
+    er += part[2 * b];
+    nr += part[2 * b + 1];
+  }
+  for (int b = 0; b < ncb; ++b) ek += part[2 * nrb + b];
+  const double w = dx * dy;
+  const double total = w / double(npts) * ek + w * er;
+  *out = total / (w * nr);
+  if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
+  return c->latched;
+}
+
+sgpe_status sgpe_profile_steps(sgpe_ctx* c, int32_t imag, int64_t n, double* row_ms, double* col_ms) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (n <= 0) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  std::vector<hipEvent_t> ev(3 * size_t(n));
+  for (auto& x : ev) {
+    if (hipEventCreate(&x) != hipSuccess) {
+      (void)hipGetLastError();
+      return SGPE_EDEVICE;
+    }
+  }
+  st = run_steps(c, n, imag != 0, &ev);
+  if (st == SGPE_OK) st = sync_and_latch(c);
+  double tr = 0.0, tc = 0.0;
+  if (st == SGPE_OK) {
+    for (int64_t i = 0; i < n; ++i) {
+      float a = 0.f, b = 0.f;
+      (void)hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+      (void)hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+      tr += a;
+      tc += b;
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (st != SGPE_OK) return st;
+  if (row_ms) *row_ms = tr / double(n);
+  if (col_ms) *col_ms = tc / double(n);
+  return SGPE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal interface between the host library (api.cpp) and the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sgpe {
+
+// Row (x) pass modes.
+enum RowMode : int {
+  ROW_FWD = 0,   // forward x-FFT only (enter the mixed (k_x, y) representation)
+  ROW_INV = 1,   // inverse x-FFT and scale (leave it: real space)
+  ROW_STEP = 2,  // inverse x-FFT, scale, real-space exponential R(h), forward x-FFT
+};
+
+// Column (y) pass norm accumulation.
+enum ColNorm : int {
+  NORM_NONE = 0,
+  NORM_DOT = 1,  // Re <psik, U psik>: the norm after the first half of U (U hermitian, U = V^2)
+  NORM_SQ = 2,   // |U psik|^2
+};
+
+struct RowArgs {
+  float4* psi;           // [ny][nx] state, in place
+  int nx, ny;
+  int rows_per_block;
+  const float4* tw;      // forward roots of length nx, {re_hi, im_hi, re_lo, im_lo}
+  // scale applied after the inverse transform: either `scale`, or computed from partials
+  float scale;
+  const double* partials;  // NULL => use `scale`
+  int n_partials;
+  double norm0, parseval_w;  // norm = parseval_w * sum(partials)
+  double inv_npts;           // 1/(nx*ny)
+  // real-space exponential (all pre-multiplied by the sub-step h)
+  float x0, dx, y0, dy;      // x_j = x0 + j dx, y_i = y0 + i dy
+  float hvx, hvy;            // h * wx^2 / 2, h * wy^2 / 2
+  float hdelta2;             // h * delta / 2
+  float hg_uu, hg_dd, hg_ud;
+  const float* hbx;          // h * Omega(x_j) / 2, length nx (full 2x2 variant only)
+};
+
+struct ColArgs {
+  float4* psi;
+  int nx, ny;
+  int cols;                  // columns per workgroup
+  const float4* tw;          // forward roots of length ny
+  const float4* kx_tab;      // per k_x: {d11, d12} {d21, d22} as complex (M'(k_x) - 1)
+  const float2* ky_tab;      // per k_y: P(k_y) - 1
+  double* partials;          // one double per workgroup (norm modes)
+};
+
+struct EnergyArgs {
+  const float4* psi;
+  float4* scratch;
+  int nx, ny;
+  int rows_per_block, cols;
+  const float4* twx;
+  const float4* twy;
+  double xmin, dx, ymin, dy;
+  double wx2h, wy2h;         // wx^2/2, wy^2/2
+  double delta, g_uu, g_dd, g_ud;
+  double k_l, omega, omega_r0, omega_rw;
+  double dkx, dky;
+  double* row_partials;      // 2 per row block: {real-space energy, norm}
+  double* col_partials;      // 1 per column block: k-space quadratic form
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full2x2, hipStream_t s);
+hipError_t launch_col(const ColArgs& a, int norm_mode, hipStream_t s);
+hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
+hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+
+// Workgroup geometry helpers (shared with the host so that partial counts match).
+int row_threads_per_row(int nx);
+// max_lds: the device's LDS bytes per workgroup (minus the kernels' static LDS).
+int row_rows_per_block(int nx, int ny, size_t max_lds);
+int col_default_cols(int nx, int ny, size_t max_lds);
+bool col_cols_supported(int nx, int ny, int cols, size_t max_lds);
+size_t row_lds_bytes(int nx, int rows);
+size_t col_lds_bytes(int ny, int cols);
+int norm_blocks();
+
+}  // namespace sgpe

@@ -1,0 +1,104 @@
+"""Python face of the C ABI: one Solver per context.  Every step runs in libsgpe's HIP kernels;
+this module only marshals arguments and owns the optional torch buffer/stream handles."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import SgpeParams, check, lib
+
+
+class Solver:
+    """Split-step solver context on the current HIP device.
+
+    ``params``: any object (or dict) with the fields of ``workloads.Params`` / ``sgpe_params``.
+    ``stream``: a raw hipStream_t handle (int) or None for the null stream; e.g.
+    ``torch.cuda.current_stream().cuda_stream``.
+    ``psi_dev``: optional device pointer (int) of >= 16*nx*ny bytes that the context borrows,
+    e.g. ``t.data_ptr()`` of a torch float32 tensor of shape (ny, nx, 4).
+    """
+
+    def __init__(self, params, stream=None, psi_dev=None):
+        self._lib = lib()
+        self.params = params
+        self._cp = SgpeParams.from_obj(params)
+        self.nx, self.ny = int(self._cp.nx), int(self._cp.ny)
+        self._ctx = ctypes.c_void_p()
+        check(self._lib.sgpe_create(ctypes.byref(self._cp), ctypes.c_void_p(stream or 0),
+                                    ctypes.c_void_p(psi_dev or 0), ctypes.byref(self._ctx)),
+              "sgpe_create")
+
+    # -- lifetime --------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.sgpe_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state -----------------------------------------------------------------------------
+    def set_psi(self, psi):
+        a = np.ascontiguousarray(np.asarray(psi), dtype=np.complex128)
+        if a.shape != (2, self.ny, self.nx):
+            raise ValueError(f"psi must have shape (2, {self.ny}, {self.nx}), got {a.shape}")
+        check(self._lib.sgpe_set_psi(self._ctx, a.ctypes.data_as(ctypes.c_void_p)), "sgpe_set_psi")
+        return self
+
+    def get_psi(self):
+        out = np.empty((2, self.ny, self.nx), dtype=np.complex128)
+        check(self._lib.sgpe_get_psi(self._ctx, out.ctypes.data_as(ctypes.c_void_p)), "sgpe_get_psi")
+        return out
+
+    # -- stepping --------------------------------------------------------------------------
+    def step_real(self, n):
+        check(self._lib.sgpe_step_real(self._ctx, int(n)), "sgpe_step_real")
+        return self
+
+    def step_imag(self, n):
+        check(self._lib.sgpe_step_imag(self._ctx, int(n)), "sgpe_step_imag")
+        return self
+
+    def synchronize(self):
+        check(self._lib.sgpe_synchronize(self._ctx), "sgpe_synchronize")
+
+    # -- observables -----------------------------------------------------------------------
+    def energy(self) -> float:
+        v = ctypes.c_double()
+        check(self._lib.sgpe_energy(self._ctx, ctypes.byref(v)), "sgpe_energy")
+        return v.value
+
+    def norm(self) -> float:
+        v = ctypes.c_double()
+        check(self._lib.sgpe_norm(self._ctx, ctypes.byref(v)), "sgpe_norm")
+        return v.value
+
+    # -- measurement / tuning --------------------------------------------------------------
+    def profile_steps(self, n, imag=False):
+        """Mean per-launch milliseconds of (row pass, column pass) over n steady-state steps."""
+        r, c = ctypes.c_double(), ctypes.c_double()
+        check(self._lib.sgpe_profile_steps(self._ctx, 1 if imag else 0, int(n), ctypes.byref(r),
+                                           ctypes.byref(c)), "sgpe_profile_steps")
+        return r.value, c.value
+
+    def set_col_tile(self, columns):
+        check(self._lib.sgpe_set_col_tile(self._ctx, int(columns)), "sgpe_set_col_tile")
+
+
+def device_count() -> int:
+    return int(lib().sgpe_device_count())
+
+
+def validate_params(params) -> int:
+    p = SgpeParams.from_obj(params)
+    return int(lib().sgpe_validate_params(ctypes.byref(p)))

@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI: the library loads, exports every function include/sgpe.h
+declares, validates parameters without a device, and reports the absence of a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from workloads import PRESETS, Params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgpe.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgpe_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2010_15069_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["sgpe_create", "sgpe_destroy", "sgpe_set_psi", "sgpe_get_psi", "sgpe_step_real",
+              "sgpe_step_imag", "sgpe_energy", "sgpe_norm", "sgpe_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2010_15069_amd import _lib
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_struct_layout_matches_header():
+    # 2 int32 + 14 doubles, naturally aligned
+    from paper_2010_15069_amd import SgpeParams
+    assert ctypes.sizeof(SgpeParams) == 8 + 14 * 8
+    assert SgpeParams.xmax.offset == 8
+    body = re.search(r"typedef struct \{(.*?)\} sgpe_params;", open(HEADER).read(), flags=re.S).group(1)
+    header_fields = re.findall(r"^\s*(?:int32_t|double)\s+([^;]+);", body, flags=re.M)
+    names = [n.strip() for f in header_fields for n in f.split(",")]
+    assert names == [f[0] for f in SgpeParams._fields_]
+    assert names == list(Params().as_dict().keys())
+
+
+@pytest.mark.parametrize("name", sorted(PRESETS))
+def test_presets_validate(name):
+    from paper_2010_15069_amd import validate_params
+    assert validate_params(PRESETS[name]) == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=48), dict(ny=8), dict(nx=8192), dict(ny=0), dict(nx=-64),
+    dict(xmax=0.0), dict(ymax=-1.0), dict(dt=0.0), dict(dt=-1e-3), dict(norm0=0.0),
+    dict(wx=-1.0), dict(omega_r0=1.0, omega_rw=0.0), dict(g_uu=float("nan")),
+    dict(dt=float("inf")), dict(k_l=float("nan")),
+])
+def test_invalid_params_rejected(bad):
+    from paper_2010_15069_amd import validate_params
+    assert validate_params(Params().replace(**bad)) == 1  # SGPE_EINVAL
+
+
+def test_strerror_never_null(lib):
+    for s in range(-1, 8):
+        assert isinstance(lib.sgpe_strerror(s), bytes)
+
+
+def test_null_arguments(lib):
+    assert lib.sgpe_validate_params(None) == 1
+    from paper_2010_15069_amd import SgpeParams
+    p = SgpeParams.from_obj(Params())
+    assert lib.sgpe_create(ctypes.byref(p), None, None, None) == 1
+    # NULL context: every entry point returns SGPE_EINVAL, destroy is a no-op
+    lib.sgpe_destroy(None)
+    assert lib.sgpe_step_real(None, 1) == 1
+    assert lib.sgpe_step_imag(None, 1) == 1
+    assert lib.sgpe_set_psi(None, None) == 1
+    assert lib.sgpe_get_psi(None, None) == 1
+    d = ctypes.c_double()
+    assert lib.sgpe_energy(None, ctypes.byref(d)) == 1
+    assert lib.sgpe_norm(None, ctypes.byref(d)) == 1
+    assert lib.sgpe_synchronize(None) == 1
+
+
+def test_invalid_params_rejected_before_device_work(lib):
+    from paper_2010_15069_amd import SgpeParams
+    p = SgpeParams.from_obj(Params(nx=100))
+    out = ctypes.c_void_p(1234)
+    assert lib.sgpe_create(ctypes.byref(p), None, None, ctypes.byref(out)) == 1
+    assert out.value is None
+
+
+def test_no_device_reports_edevice(lib):
+    if lib.sgpe_device_count() > 0:
+        pytest.skip("a GPU is visible")
+    from paper_2010_15069_amd import SgpeParams
+    p = SgpeParams.from_obj(PRESETS["tiny"])
+    out = ctypes.c_void_p()
+    assert lib.sgpe_create(ctypes.byref(p), None, None, ctypes.byref(out)) == 3  # SGPE_EDEVICE
+    assert out.value is None
+
+
+def test_one_hip_runtime_in_process(lib):
+    import torch  # noqa: F401  -- torch ships its own HIP runtime; libsgpe must reuse it
+    maps = open("/proc/self/maps").read()
+    hip = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(hip) == 1, hip
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_2010_15069_amd import _lib
+    monkeypatch.setattr(_lib, "_LIB", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libsgpe.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Bars (the method's contract for a complex64 state):
+  * psi relative L2 error <= 1e-5 after 1000 complex64 real-time steps (512^2 workload);
+  * energies within 1e-6 relative;
+  * real-time norm drift <= 1e-6 over 1000 steps.
+Cases span several tiles and both ragged aspect ratios, the smallest and largest supported axis
+lengths, the full-size workloads (checked after a few steps, where the oracle is still quick),
+zero-step calls, call splitting, determinism and the column-tile launch variants.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import OracleGPE
+from workloads import Params, gaussian_state, initial_state, preset, round_to_c64, thomas_fermi_state
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    from paper_2010_15069_amd import Solver, device_count
+    if device_count() <= 0:
+        pytest.skip("no HIP device")
+    return Solver
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_both(Solver, p, psi0, ops):
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_psi(psi0)
+    s = Solver(p)
+    s.set_psi(psi0)
+    for kind, n in ops:
+        if kind == "real":
+            o.step_real(n)
+            s.step_real(n)
+        else:
+            o.step_imag(n)
+            s.step_imag(n)
+    return o, s
+
+
+def check_pair(o, s, psi_tol, e_tol=1e-6, check_norm=True):
+    g = s.get_psi()
+    err = rel_l2(g, o.psi)
+    assert err <= psi_tol, f"psi rel L2 {err:.3e} > {psi_tol:.1e}"
+    eo, eg = o.energy(), s.energy()
+    assert abs(eg - eo) <= e_tol * abs(eo), f"energy {eg!r} vs {eo!r}"
+    if check_norm:
+        no, ng = o.norm(), s.norm()
+        assert abs(ng - no) <= 1e-6 * no, f"norm {ng!r} vs {no!r}"
+    return err
+
+
+# --- the benchmark workloads -------------------------------------------------------------------
+
+def test_tiny_imag_then_real(Solver):
+    p = preset("tiny")
+    psi0 = initial_state(p, "gauss", seed=0)
+    o, s = run_both(Solver, p, psi0, [("imag", 200)])
+    check_pair(o, s, 1e-5)
+    o.step_real(200)
+    s.step_real(200)
+    check_pair(o, s, 1e-5)
+
+
+def test_realtime_512_1000_steps(Solver):
+    p = preset("realtime_512")
+    psi0 = initial_state(p, "tf", seed=0)
+    o, s = run_both(Solver, p, psi0, [("real", 1000)])
+    err = check_pair(o, s, 1e-5)
+    n0 = p.norm0
+    assert abs(s.norm() - n0) <= 1e-6 * n0
+    print(f"512^2 real time, 1000 steps: psi rel L2 = {err:.3e}")
+
+
+@pytest.mark.parametrize("kind", ["imag", "real"])
+def test_spatial_raman_full_2x2(Solver, kind):
+    # the large-ground-state physics (Omega(x) = 2 tanh(x/4), g = 50, trap aspect 1.5) at 128^2
+    p = preset("ground_2048", nx=128, ny=128)
+    psi0 = initial_state(p, "tf", seed=2)
+    o, s = run_both(Solver, p, psi0, [(kind, 300)])
+    check_pair(o, s, 1e-5)
+
+
+def test_metric_1024_full_size(Solver):
+    p = preset("metric_1024")
+    psi0 = initial_state(p, "tf", seed=0)
+    o, s = run_both(Solver, p, psi0, [("real", 10)])
+    check_pair(o, s, 1e-6)
+    o.step_imag(5)
+    s.step_imag(5)
+    check_pair(o, s, 1e-6)
+
+
+def test_ground_2048_full_size(Solver):
+    p = preset("ground_2048")
+    psi0 = initial_state(p, "tf", seed=0)
+    o, s = run_both(Solver, p, psi0, [("imag", 3)])
+    check_pair(o, s, 1e-6)
+
+
+# --- shapes, edge cases ------------------------------------------------------------------------
+
+SHAPES = [(16, 16), (32, 256), (256, 32), (64, 1024), (1024, 64), (2048, 16), (16, 2048),
+          (4096, 16), (16, 4096), (128, 512)]
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_ragged_shapes(Solver, nx, ny):
+    p = Params(nx=nx, ny=ny, xmax=8.0, ymax=6.0, g_uu=3.0, g_dd=4.0, g_ud=2.0, k_l=1.3, omega=0.7,
+               delta=0.2, wx=1.0, wy=1.4, omega_r0=0.5, omega_rw=2.0, dt=1e-3)
+    rng = np.random.default_rng(nx * 7 + ny)
+    psi0 = gaussian_state(p, sigma=1.5, seed=int(rng.integers(1000)), noise=1e-2)
+    o, s = run_both(Solver, p, psi0, [("real", 20), ("imag", 20)])
+    check_pair(o, s, 1e-5)
+
+
+def test_zero_steps_is_a_no_op(Solver):
+    p = preset("tiny")
+    psi0 = initial_state(p, "gauss", seed=4)
+    s = Solver(p)
+    s.set_psi(psi0)
+    s.step_real(0)
+    s.step_imag(0)
+    assert np.array_equal(s.get_psi(), psi0)
+
+
+def test_single_steps_and_call_splitting(Solver):
+    p = preset("realtime_512", nx=128, ny=128)
+    psi0 = initial_state(p, "tf", seed=5)
+    a = Solver(p).set_psi(psi0)
+    b = Solver(p).set_psi(psi0)
+    a.step_real(7)
+    for n in (1, 2, 4):
+        b.step_real(n)
+    assert rel_l2(b.get_psi(), a.get_psi()) < 1e-6
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_psi(psi0)
+    o.step_real(1)
+    c = Solver(p).set_psi(psi0).step_real(1)
+    assert rel_l2(c.get_psi(), o.psi) < 1e-6
+    a.step_imag(5)
+    for n in (2, 3):
+        b.step_imag(n)
+    assert rel_l2(b.get_psi(), a.get_psi()) < 1e-6
+
+
+def test_bitwise_determinism(Solver):
+    p = preset("ground_2048", nx=256, ny=256)
+    psi0 = initial_state(p, "tf", seed=6)
+    outs = []
+    for _ in range(2):
+        s = Solver(p).set_psi(psi0)
+        s.step_imag(30)
+        s.step_real(30)
+        outs.append((s.get_psi(), s.energy(), s.norm()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 1024), (1024, 512), (64, 2048)])
+def test_column_tile_variants(Solver, nx, ny):
+    p = preset("realtime_512", nx=nx, ny=ny)
+    psi0 = initial_state(p, "tf", seed=7)
+    ref_real, ref_imag = None, None
+    for cols in (1, 2, 4, 8, 16):
+        s = Solver(p)
+        try:
+            s.set_col_tile(cols)
+        except Exception:
+            continue
+        s.set_psi(psi0).step_real(10)
+        r = s.get_psi()
+        s.step_imag(10)
+        i = s.get_psi()
+        if ref_real is None:
+            ref_real, ref_imag = r, i
+        else:
+            # column tiling only regroups the fp64 norm partials (imaginary time)
+            assert np.array_equal(r, ref_real), cols
+            assert rel_l2(i, ref_imag) < 1e-6, cols
+
+
+def test_energy_and_norm_of_arbitrary_states(Solver):
+    for (nx, ny, seed) in [(64, 64, 1), (256, 128, 2), (512, 1024, 3)]:
+        p = Params(nx=nx, ny=ny, xmax=7.0, ymax=9.0, g_uu=5.0, g_dd=2.0, g_ud=3.0, k_l=1.1,
+                   omega=0.8, delta=-0.3, wx=1.2, wy=0.9, omega_r0=1.5, omega_rw=3.0)
+        rng = np.random.default_rng(seed)
+        psi = gaussian_state(p, sigma=2.0, noise=0.0) * (1.0 + 0.2 * (rng.standard_normal((2, ny, nx))
+                                                                      + 1j * rng.standard_normal((2, ny, nx))))
+        psi = round_to_c64(psi)
+        o = OracleGPE(p, workers=WORKERS)
+        o.set_psi(psi)
+        s = Solver(p).set_psi(psi)
+        assert abs(s.norm() - o.norm()) <= 1e-9 * o.norm()
+        assert abs(s.energy() - o.energy()) <= 1e-6 * abs(o.energy())
+
+
+def test_nonfinite_input_rejected(Solver):
+    from paper_2010_15069_amd import SgpeError
+    p = preset("tiny")
+    s = Solver(p)
+    bad = initial_state(p, "gauss")
+    bad[1, 3, 5] = np.nan
+    with pytest.raises(SgpeError) as e:
+        s.set_psi(bad)
+    assert e.value.status == 4
+    with pytest.raises(SgpeError) as e:
+        s.step_real(1)  # no state yet
+    assert e.value.status == 5
+
+
+# --- ground states: energy within 1e-6 of the oracle's ---------------------------------------
+
+def _relax(obj, p, step, tol, every=10, max_steps=20000):
+    e_prev = None
+    n = 0
+    while n < max_steps:
+        step(every)
+        n += every
+        e = obj.energy()
+        if e_prev is not None and abs(e - e_prev) < tol * abs(e):
+            return e, n
+        e_prev = e
+    return e_prev, n
+
+
+def test_ground_state_energy_tiny(Solver):
+    p = preset("tiny")
+    psi0 = initial_state(p, "gauss", seed=0)
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_psi(psi0)
+    eo, _ = _relax(o, p, o.step_imag, 1e-12, every=100)
+    s = Solver(p).set_psi(psi0)
+    eg, _ = _relax(s, p, s.step_imag, 1e-10, every=100)
+    assert abs(eg - eo) <= 1e-6 * abs(eo)
+
+
+def test_ground_state_energy_spatial_raman(Solver):
+    p = preset("ground_2048", nx=128, ny=128)
+    psi0 = initial_state(p, "tf", seed=0)
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_psi(psi0)
+    eo, _ = _relax(o, p, o.step_imag, 1e-11, every=50)
+    s = Solver(p).set_psi(psi0)
+    eg, _ = _relax(s, p, s.step_imag, 1e-9, every=50)
+    assert abs(eg - eo) <= 1e-6 * abs(eo), (eg, eo)
