@@ -50,11 +50,12 @@ __device__ __forceinline__ float4 apply_r(float4 w, float hv, float hbx, const R
     const float phu = fmaf(a.hg_uu, nu, fmaf(a.hg_ud, nd, hv + a.hdelta2));
     const float phd = fmaf(a.hg_dd, nd, fmaf(a.hg_ud, nu, hv - a.hdelta2));
     if constexpr (!IMAG) {
-      // psi * exp(-i phi) = psi + psi (cm1 - i s)
+      // psi * exp(-i phi) = psi + psi (cm1 - i s); the small correction is formed first and
+      // added once (one rounding of the large value per step).
       const SinCosM1 su = sincos_m1(phu);
       const SinCosM1 sd = sincos_m1(phd);
-      return make_float4(fmaf(w.x, su.cm1, fmaf(w.y, su.s, w.x)), fmaf(w.y, su.cm1, fmaf(-w.x, su.s, w.y)),
-                         fmaf(w.z, sd.cm1, fmaf(w.w, sd.s, w.z)), fmaf(w.w, sd.cm1, fmaf(-w.z, sd.s, w.w)));
+      return make_float4(w.x + fmaf(w.x, su.cm1, w.y * su.s), w.y + fmaf(w.y, su.cm1, -w.x * su.s),
+                         w.z + fmaf(w.z, sd.cm1, w.w * sd.s), w.w + fmaf(w.w, sd.cm1, -w.z * sd.s));
     } else {
       const float eu = expf(-phu);
       const float ed = expf(-phd);
@@ -74,12 +75,15 @@ __device__ __forceinline__ float4 apply_r(float4 w, float hv, float hbx, const R
       // X = pz psi_u + px psi_d, Y = px psi_u - pz psi_d; (M - 1) psi = cm1 psi - i (X, Y)
       const float xr = fmaf(pz, w.x, px * w.z), xi = fmaf(pz, w.y, px * w.w);
       const float yr = fmaf(px, w.x, -pz * w.z), yi = fmaf(px, w.y, -pz * w.w);
-      const float ur = fmaf(sb.cm1, w.x, w.x + xi), ui = fmaf(sb.cm1, w.y, w.y - xr);
-      const float dr = fmaf(sb.cm1, w.z, w.z + yi), di = fmaf(sb.cm1, w.w, w.w - yr);
+      const float mur = fmaf(sb.cm1, w.x, xi), mui = fmaf(sb.cm1, w.y, -xr);
+      const float mdr = fmaf(sb.cm1, w.z, yi), mdi = fmaf(sb.cm1, w.w, -yr);
+      // E M psi - psi = c_M + (E - 1)(psi + c_M), E - 1 = cm1_A - i s_A; added to psi once.
       const SinCosM1 se = sincos_m1(ha);
-      // u + u (cm1 - i s)
-      return make_float4(fmaf(ur, se.cm1, fmaf(ui, se.s, ur)), fmaf(ui, se.cm1, fmaf(-ur, se.s, ui)),
-                         fmaf(dr, se.cm1, fmaf(di, se.s, dr)), fmaf(di, se.cm1, fmaf(-dr, se.s, di)));
+      const float cur = fmaf(se.s, w.y, fmaf(se.cm1, w.x, fmaf(se.s, mui, fmaf(se.cm1, mur, mur))));
+      const float cui = fmaf(-se.s, w.x, fmaf(se.cm1, w.y, fmaf(-se.s, mur, fmaf(se.cm1, mui, mui))));
+      const float cdr = fmaf(se.s, w.w, fmaf(se.cm1, w.z, fmaf(se.s, mdi, fmaf(se.cm1, mdr, mdr))));
+      const float cdi = fmaf(-se.s, w.z, fmaf(se.cm1, w.w, fmaf(-se.s, mdr, fmaf(se.cm1, mdi, mdi))));
+      return make_float4(w.x + cur, w.y + cui, w.z + cdr, w.w + cdi);
     } else {
       const float ea = expf(-ha);
       float ch, shc;  // cosh(th), sinh(th)/th

@@ -255,3 +255,21 @@ def test_ground_state_energy_spatial_raman(Solver):
     s = Solver(p).set_psi(psi0)
     eg, _ = _relax(s, p, s.step_imag, 1e-9, every=50)
     assert abs(eg - eo) <= 1e-6 * abs(eo), (eg, eo)
+
+
+@pytest.mark.parametrize("variant", ["tiny", "tiny_free", "realtime_512"])
+def test_real_time_norm_drift(Solver, variant):
+    # Unitary steps: a complex64 state's norm stays within 1e-6 over 1000 steps (no coherent
+    # rounding drift), also for a smooth state whose norm sits in a few low-k modes.
+    if variant == "tiny_free":
+        p = preset("tiny", g_uu=0.0, g_dd=0.0, g_ud=0.0, wx=0.0, wy=0.0)
+    else:
+        p = preset(variant)
+    psi0 = initial_state(p, "gauss" if variant.startswith("tiny") else "tf", seed=0)
+    s = Solver(p).set_psi(psi0)
+    n0 = s.norm()
+    worst = 0.0
+    for _ in range(10):
+        s.step_real(100)
+        worst = max(worst, abs(s.norm() - n0) / n0)
+    assert worst <= 1e-6, worst
