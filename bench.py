@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="metric_1024")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the HBM "
+                         "byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs one instance on one GPU; --gpus must be 1", file=sys.stderr)
@@ -86,6 +89,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_reference:
+        n = args.copy_reference * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes_read": 4 * n, "copy_reference_bytes_written": 4 * n,
+                          "launches": 5}))
+        return
 
     from paper_2010_15069_amd import Solver
     from workloads import initial_state, preset
@@ -99,20 +113,16 @@ def main():
     s.set_psi(psi0)
 
     def timed(step, k, batch):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(k // batch + 1)]
+        sizes = [min(batch, k - i) for i in range(0, k, batch)]
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(sizes) + 1)]
         torch.cuda.synchronize()
         evs[0].record(stream)
-        done = 0
-        i = 1
-        while done < k:
-            b = min(batch, k - done)
+        for i, b in enumerate(sizes):
             step(b)
-            evs[i].record(stream)
-            i += 1
-            done += b
+            evs[i + 1].record(stream)
         torch.cuda.synchronize()
-        per = [evs[j - 1].elapsed_time(evs[j]) / batch for j in range(1, i)]
-        total_ms = evs[0].elapsed_time(evs[i - 1])
+        per = [evs[i].elapsed_time(evs[i + 1]) / b for i, b in enumerate(sizes)]
+        total_ms = evs[0].elapsed_time(evs[-1])
         return total_ms, per
 
     # imaginary time (headline)

@@ -31,7 +31,7 @@ __device__ __forceinline__ int col_tile(int b, int ntiles) {
 }
 
 template <int N, int NORM>
-__global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
+__global__ void __launch_bounds__(256) col_kernel(ColArgs a) {
   extern __shared__ float4 lds_raw[];
   __shared__ double red[16];
   constexpr int T = N / 16;
@@ -48,8 +48,10 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
   float4 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[size_t(t + T * m) * rs];
+  TwRegs<N> tr;
+  load_twiddles<N>(tr, t, a.tw);
 
-  fft_pass<N, -1>(v, lds, t, a.tw);
+  fft_pass<N, -1>(v, lds, t, tr);
 
   const float4 d0 = a.kx_tab[2 * x];      // d11, d12
   const float4 d1 = a.kx_tab[2 * x + 1];  // d21, d22
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     if (tid == 0) a.partials[blockIdx.x] = s;
   }
 
-  fft_pass<N, +1>(v, lds, t, a.tw);
+  fft_pass<N, +1>(v, lds, t, tr);
 
 #pragma unroll
   for (int m = 0; m < 16; ++m) p[size_t(t + T * m) * rs] = v[m];

@@ -183,13 +183,53 @@ struct LdsView {
   __device__ __forceinline__ float4& at(int pos) const { return base[(pos + (pos >> 4)) * stride]; }
 };
 
-// One Stockham stage: radix R, L = product of the radices already applied.
-template <int N, int R, int L, int DIR, bool LAST>
-__device__ __forceinline__ void stockham_stage(float4 (&v)[16], const LdsView& lds, int t,
-                                               const float4* __restrict__ tw) {
+// Stage twiddles a thread needs for a length-N transform: the first stage (L = 1) needs none;
+// a later stage of radix R uses W_N^(s r N/(R L)) for its 16/R butterflies and r = 1..R-1.
+template <int N, int L = 1>
+constexpr int tw_count() {
+  constexpr int REM = N / L;
+  constexpr int R = REM >= 16 ? 16 : REM;
+  constexpr int here = L > 1 ? (16 / R) * (R - 1) : 0;
+  if constexpr (R == REM) return here;
+  else return here + tw_count<N, L * R>();
+}
+
+// Per-thread register copy of those twiddles, loaded once per kernel (they depend only on the
+// thread index) and shared by the forward and inverse transforms (the inverse conjugates).
+template <int N>
+struct TwRegs {
+  static constexpr int COUNT = tw_count<N>() > 0 ? tw_count<N>() : 1;
+  float4 w[COUNT];
+};
+
+template <int N, int L = 1, int BASE = 0>
+__device__ __forceinline__ void load_twiddles(TwRegs<N>& tr, int t, const float4* __restrict__ tw) {
   constexpr int T = N / 16;
+  constexpr int REM = N / L;
+  constexpr int R = REM >= 16 ? 16 : REM;
   constexpr int U = 16 / R;
   constexpr int TW_STRIDE = N / (R * L);
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = (t + T * u) & (L - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) tr.w[BASE + u * (R - 1) + (r - 1)] = tw[s * r * TW_STRIDE];
+    }
+  }
+  if constexpr (R != REM) {
+    constexpr int NEXT = BASE + (L > 1 ? U * (R - 1) : 0);
+    load_twiddles<N, L * R, NEXT>(tr, t, tw);
+  }
+}
+
+// One Stockham stage: radix R, L = product of the radices already applied; its twiddles start at
+// tr.w[BASE].
+template <int N, int R, int L, int DIR, bool LAST, int BASE>
+__device__ __forceinline__ void stockham_stage(float4 (&v)[16], const LdsView& lds, int t,
+                                               const TwRegs<N>& tr) {
+  constexpr int T = N / 16;
+  constexpr int U = 16 / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     float4 a[R];
@@ -199,7 +239,7 @@ __device__ __forceinline__ void stockham_stage(float4 (&v)[16], const LdsView& l
     const int s = b & (L - 1);
     if constexpr (L > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[r] = twmul<DIR>(a[r], tw[s * r * TW_STRIDE]);
+      for (int r = 1; r < R; ++r) a[r] = twmul<DIR>(a[r], tr.w[BASE + u * (R - 1) + (r - 1)]);
     }
     dft<R, DIR>(a);
     if constexpr (LAST) {
@@ -214,21 +254,21 @@ __device__ __forceinline__ void stockham_stage(float4 (&v)[16], const LdsView& l
 }
 
 // Full length-N transform of the 16 registers (positions t + T*m) in place.  All threads of the
-// workgroup call it (it contains workgroup barriers).  tw is the forward root table of length N.
-template <int N, int DIR, int L = 1>
-__device__ __forceinline__ void fft_pass(float4 (&v)[16], const LdsView& lds, int t,
-                                         const float4* __restrict__ tw) {
+// workgroup call it (it contains workgroup barriers).
+template <int N, int DIR, int L = 1, int BASE = 0>
+__device__ __forceinline__ void fft_pass(float4 (&v)[16], const LdsView& lds, int t, const TwRegs<N>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= 16 ? 16 : REM;
   constexpr bool LAST = (R == REM);
   constexpr int T = N / 16;
-  stockham_stage<N, R, L, DIR, LAST>(v, lds, t, tw);
+  stockham_stage<N, R, L, DIR, LAST, BASE>(v, lds, t, tr);
   if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = lds.at(t + T * m);
     __syncthreads();
-    fft_pass<N, DIR, L * R>(v, lds, t, tw);
+    constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
+    fft_pass<N, DIR, L * R, NEXT>(v, lds, t, tr);
   }
 }
 
@@ -241,13 +281,13 @@ struct SinCosM1 {
   float cm1, s, sinc;
 };
 
-__device__ __forceinline__ SinCosM1 sincos_m1(float phi) {
+__device__ __forceinline__ SinCosM1 sincos_m1_reduced(float phi) {
   const float k = rintf(phi * 0.636619772367581343f);
   float r = fmaf(-k, 1.57079637050628662f, phi);   // pi/2 hi
   r = fmaf(-k, -4.37113900018624283e-8f, r);        // pi/2 lo
   const float r2 = r * r;
-  const float ps = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, 2.75573192e-6f, -1.98412698e-4f), 8.33333333e-3f),
-                                 -1.66666667e-1f), 0.0f);   // sin r / r - 1
+  const float ps = r2 * fmaf(r2, fmaf(r2, fmaf(r2, 2.75573192e-6f, -1.98412698e-4f), 8.33333333e-3f),
+                             -1.66666667e-1f);   // sin r / r - 1
   const float sr = fmaf(r, ps, r);
   const float cr_m1 = r2 * fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -2.75573192e-7f, 2.48015873e-5f),
                                                   -1.38888889e-3f), 4.16666667e-2f), -0.5f);
@@ -265,6 +305,25 @@ __device__ __forceinline__ SinCosM1 sincos_m1(float phi) {
     out.sinc = out.s / phi;
   }
   return out;
+}
+
+// |phi| <= pi/4 needs no reduction; the polynomials alone are accurate there.
+__device__ __forceinline__ SinCosM1 sincos_m1_small(float phi) {
+  const float r2 = phi * phi;
+  const float ps = r2 * fmaf(r2, fmaf(r2, fmaf(r2, 2.75573192e-6f, -1.98412698e-4f), 8.33333333e-3f),
+                             -1.66666667e-1f);
+  SinCosM1 out;
+  out.s = fmaf(phi, ps, phi);
+  out.cm1 = r2 * fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -2.75573192e-7f, 2.48015873e-5f),
+                                             -1.38888889e-3f), 4.16666667e-2f), -0.5f);
+  out.sinc = 1.0f + ps;
+  return out;
+}
+
+__device__ __forceinline__ SinCosM1 sincos_m1(float phi) {
+  // The branch is uniform in the common case (every phase of the wave below pi/4).
+  if (fabsf(phi) <= 0.785398163f) return sincos_m1_small(phi);
+  return sincos_m1_reduced(phi);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -26,7 +26,7 @@ int row_rows_per_block(int nx, int ny, size_t max_lds) {
 bool col_cols_supported(int nx, int ny, int cols, size_t max_lds) {
   if (cols < 1 || (cols & (cols - 1)) != 0 || cols > nx) return false;
   const int t = ny / 16;
-  if (cols * t > 512) return false;
+  if (cols * t > 256) return false;
   return col_lds_bytes(ny, cols) <= max_lds;
 }
 
@@ -63,6 +63,8 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   float4 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[t + T * m];
+  TwRegs<N> tr;
+  load_twiddles<N>(tr, t, a.twx);
   const double y = a.ymin + a.dy * row;
   double er = 0.0, nr = 0.0;
 #pragma unroll
@@ -83,14 +85,14 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
     a.row_partials[2 * blockIdx.x] = se;
     a.row_partials[2 * blockIdx.x + 1] = sn;
   }
-  fft_pass<N, -1>(v, lds, t, a.twx);
+  fft_pass<N, -1>(v, lds, t, tr);
   float4* __restrict__ q = a.scratch + size_t(row) * N;
 #pragma unroll
   for (int m = 0; m < 16; ++m) q[t + T * m] = v[m];
 }
 
 template <int N>
-__global__ void __launch_bounds__(512) energy_col_kernel(EnergyArgs a) {
+__global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
   extern __shared__ float4 lds_raw[];
   __shared__ double red[16];
   constexpr int T = N / 16;
@@ -105,7 +107,9 @@ __global__ void __launch_bounds__(512) energy_col_kernel(EnergyArgs a) {
   float4 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[size_t(t + T * m) * rs];
-  fft_pass<N, -1>(v, lds, t, a.twy);
+  TwRegs<N> tr;
+  load_twiddles<N>(tr, t, a.twy);
+  fft_pass<N, -1>(v, lds, t, tr);
   const double kx = (x < a.nx / 2 ? x : x - a.nx) * a.dkx;
   const double bz = a.k_l * kx;
   double acc = 0.0;

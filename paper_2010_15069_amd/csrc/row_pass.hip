@@ -125,12 +125,14 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs a) {
   float4 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[t + T * m];
+  TwRegs<N> tr;
+  load_twiddles<N>(tr, t, a.tw);
 
   if constexpr (MODE == ROW_FWD) {
-    fft_pass<N, -1>(v, lds, t, a.tw);
+    fft_pass<N, -1>(v, lds, t, tr);
   } else {
     const float s = row_scale(a);
-    fft_pass<N, +1>(v, lds, t, a.tw);
+    fft_pass<N, +1>(v, lds, t, tr);
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = make_float4(v[m].x * s, v[m].y * s, v[m].z * s, v[m].w * s);
     if constexpr (MODE == ROW_STEP) {
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs a) {
         const float hbx = FULL ? a.hbx[j] : 0.0f;
         v[m] = apply_r<IMAG, FULL>(v[m], hv, hbx, a);
       }
-      fft_pass<N, -1>(v, lds, t, a.tw);
+      fft_pass<N, -1>(v, lds, t, tr);
     }
   }
 #pragma unroll
