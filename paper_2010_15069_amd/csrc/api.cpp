@@ -126,8 +126,9 @@ void k_tables(const sgpe_params& p, bool imag, double h, std::vector<float4>& kx
       m12r = -pr * sh * bx;        m12i = 0.0;
       m22r = pr * (ch + sh * bz);  m22i = 0.0;
     }
+    // per component: {d_own, d_other} of its row of M' - 1 (up: d11, d12; down: d22, d21)
     kx_out[2 * size_t(j)] = make_float4(float(m11r - 1.0), float(m11i), float(m12r), float(m12i));
-    kx_out[2 * size_t(j) + 1] = make_float4(float(m12r), float(m12i), float(m22r - 1.0), float(m22i));
+    kx_out[2 * size_t(j) + 1] = make_float4(float(m22r - 1.0), float(m22i), float(m12r), float(m12i));
   }
   for (int i = 0; i < p.ny; ++i) {
     const double ky = kval(i, p.ny, dy);
@@ -496,8 +497,8 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   a.scratch = c->scratch;
   a.nx = p.nx;
   a.ny = p.ny;
-  a.rows_per_block = c->rows;
-  a.cols = sgpe::col_default_cols(p.nx, p.ny, c->max_lds);
+  a.rows_per_block = sgpe::energy_rows_per_block(p.nx, p.ny, c->max_lds);
+  a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
   a.twx = c->tw_x;
   a.twy = c->tw_y;
   a.xmin = -p.xmax;
@@ -516,7 +517,7 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   a.omega_rw = p.omega_rw;
   a.dkx = M_PI / p.xmax;
   a.dky = M_PI / p.ymax;
-  const int nrb = p.ny / c->rows;
+  const int nrb = p.ny / a.rows_per_block;
   const int ncb = p.nx / a.cols;
   a.row_partials = c->epart;
   a.col_partials = c->epart + 2 * nrb;

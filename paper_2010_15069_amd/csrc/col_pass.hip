@@ -1,28 +1,22 @@
 // HIP kernels of the split-step solver for gfx950: the column pass.
 //
-// One Strang step K(dt/2) R(dt) K(dt/2) (Sec. 3.2) is computed by two fused sweeps over the
-// state, which lives in HBM as [ny][nx] float4 {re_up, im_up, re_dn, im_dn}:
+// Per column: forward y-FFT, the k-space 2x2 propagator U_K(h) (kinetic + spin-momentum term of
+// Eq. (H1) and the uniform Raman coupling of Eq. (H4), exponentiated per Eq. (TEOp)), inverse
+// y-FFT; in imaginary time it also writes one fp64 norm partial per workgroup.  The state is read
+// and written in the mixed (k_x, y) representation left by the row pass (see row_pass.hip).
 //
-//   row pass    -- per row: inverse x-FFT, scale, real-space 2x2 exponential R (trap, detuning,
-//                  mean field, spatial Raman coupling; Eqs. (H2)-(H4)), forward x-FFT;
-//   column pass -- per column: forward y-FFT, k-space 2x2 propagator (kinetic, spin-momentum and
-//                  uniform Raman coupling; Eqs. (H1), (H4)), inverse y-FFT.
+// Thread layout: lanes 2j and 2j+1 own the up and down component of the same positions of a
+// column; consecutive lane pairs own consecutive columns, so one row of a C-column tile is
+// 16 C contiguous bytes.  U_K couples the components; the partner comes over a DPP lane swap.
 //
-// Between sweeps the state is in the mixed representation (k_x, y).  Adjacent K(dt/2) halves of
-// consecutive steps are merged into one K(dt) in the column pass, so a run of n steps costs
-// 2n + 2 sweeps.  In imaginary time the column pass also produces the norm that the next row pass
-// rescales by (Parseval), so renormalisation costs no extra sweep.
-//
-// Every operator close to the identity is applied as psi + (U - 1) psi with U - 1 held to fp32
-// relative accuracy, so that unit-modulus propagators do not pick up a coherent |U| != 1 error
-// from rounding their tables.
+// U_K = P(k_y) M'(k_x) is applied as w + [c1 + q (w + c1)] with c1 = (M' - 1) w and q = P - 1,
+// the bracket formed first and added to w once: the dominant modes of a smooth state are rounded
+// once per step instead of twice per factor (which gives a coherent norm drift).
 #include "fft_device.hpp"
 #include "sgpe_internal.hpp"
 
 namespace sgpe {
-// -------------------------------------------------------------------------------------------
-// Column pass
-// -------------------------------------------------------------------------------------------
+
 __device__ __forceinline__ int col_tile(int b, int ntiles) {
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles so
   // that tiles sharing 128-byte lines meet in the same L2.
@@ -31,55 +25,50 @@ __device__ __forceinline__ int col_tile(int b, int ntiles) {
 }
 
 template <int N, int NORM>
-__global__ void __launch_bounds__(256) col_kernel(ColArgs a) {
-  extern __shared__ float4 lds_raw[];
-  __shared__ double red[16];
+__global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
+  extern __shared__ float2 lds_raw[];
+  __shared__ double red[64];
   constexpr int T = N / 16;
   const int C = a.cols;
   const int tid = threadIdx.x;
-  const int c = tid & (C - 1);
-  const int t = tid / C;
+  const int comp = tid & 1;
+  const int pair = tid >> 1;
+  const int cc = pair & (C - 1);
+  const int t = pair / C;
   const int tile = col_tile(blockIdx.x, a.nx / C);
-  const int x = tile * C + c;
-  const LdsView lds{lds_raw + c, C};
-  float4* __restrict__ p = a.psi + x;
-  const size_t rs = size_t(a.nx);
+  const int x = tile * C + cc;
+  const LdsView<float2> lds{lds_raw + 2 * cc + comp, 2 * C};
+  // element (row y) of this lane's component is p[2 * y * nx]
+  float2* __restrict__ p = reinterpret_cast<float2*>(a.psi + x) + comp;
+  const size_t rs = 2 * size_t(a.nx);
 
-  float4 v[16];
+  float2 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[size_t(t + T * m) * rs];
   TwRegs<N> tr;
   load_twiddles<N>(tr, t, a.tw);
+  // this component's row of M' - 1 at k_x: {d_own, d_other}
+  const float4 d = a.kx_tab[2 * x + comp];
 
   fft_pass<N, -1>(v, lds, t, tr);
 
-  const float4 d0 = a.kx_tab[2 * x];      // d11, d12
-  const float4 d1 = a.kx_tab[2 * x + 1];  // d21, d22
   double acc = 0.0;
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
-    const float4 w = v[m];
+    const float2 w = v[m];
+    const float2 o = pair_swap(w);
     const float2 q = a.ky_tab[t + T * m];
-    // U = P M' with M' = 1 + D (per k_x) and P = 1 + q (per k_y):
-    //   U w = w + [c1 + q (w + c1)],  c1 = D w.
-    // The bracket is small; it is accumulated on its own and added to w once, so the dominant
-    // modes of a smooth state are rounded once per step (rounding w + small twice per factor
-    // gives a coherent norm drift of ~1e-8 per step).
-    const float c1ur = fmaf(-d0.w, w.w, fmaf(d0.z, w.z, fmaf(-d0.y, w.y, d0.x * w.x)));
-    const float c1ui = fmaf(d0.w, w.z, fmaf(d0.z, w.w, fmaf(d0.y, w.x, d0.x * w.y)));
-    const float c1dr = fmaf(-d1.w, w.w, fmaf(d1.z, w.z, fmaf(-d1.y, w.y, d1.x * w.x)));
-    const float c1di = fmaf(d1.w, w.z, fmaf(d1.z, w.w, fmaf(d1.y, w.x, d1.x * w.y)));
-    const float cur = fmaf(-q.y, w.y, fmaf(q.x, w.x, fmaf(-q.y, c1ui, fmaf(q.x, c1ur, c1ur))));
-    const float cui = fmaf(q.y, w.x, fmaf(q.x, w.y, fmaf(q.y, c1ur, fmaf(q.x, c1ui, c1ui))));
-    const float cdr = fmaf(-q.y, w.w, fmaf(q.x, w.z, fmaf(-q.y, c1di, fmaf(q.x, c1dr, c1dr))));
-    const float cdi = fmaf(q.y, w.z, fmaf(q.x, w.w, fmaf(q.y, c1dr, fmaf(q.x, c1di, c1di))));
-    const float4 o = make_float4(w.x + cur, w.y + cui, w.z + cdr, w.w + cdi);
+    const float c1r = fmaf(-d.w, o.y, fmaf(d.z, o.x, fmaf(-d.y, w.y, d.x * w.x)));
+    const float c1i = fmaf(d.w, o.x, fmaf(d.z, o.y, fmaf(d.y, w.x, d.x * w.y)));
+    const float cr = fmaf(-q.y, w.y, fmaf(q.x, w.x, fmaf(-q.y, c1i, fmaf(q.x, c1r, c1r))));
+    const float ci = fmaf(q.y, w.x, fmaf(q.x, w.y, fmaf(q.y, c1r, fmaf(q.x, c1i, c1i))));
+    const float2 out = make_float2(w.x + cr, w.y + ci);
     if constexpr (NORM == NORM_DOT) {
-      acc += static_cast<double>(fmaf(w.x, o.x, fmaf(w.y, o.y, fmaf(w.z, o.z, w.w * o.w))));
+      acc += static_cast<double>(fmaf(w.x, out.x, w.y * out.y));
     } else if constexpr (NORM == NORM_SQ) {
-      acc += static_cast<double>(fmaf(o.x, o.x, fmaf(o.y, o.y, fmaf(o.z, o.z, o.w * o.w))));
+      acc += static_cast<double>(fmaf(out.x, out.x, out.y * out.y));
     }
-    v[m] = o;
+    v[m] = out;
   }
   if constexpr (NORM != NORM_NONE) {
     const double s = block_sum(acc, red);
@@ -92,14 +81,14 @@ __global__ void __launch_bounds__(256) col_kernel(ColArgs a) {
   for (int m = 0; m < 16; ++m) p[size_t(t + T * m) * rs] = v[m];
 }
 
+// -------------------------------------------------------------------------------------------
 // Launcher
+// -------------------------------------------------------------------------------------------
 template <int N, int NORM>
 static hipError_t col_launch_t(const ColArgs& a, hipStream_t s) {
-  const int t = N / 16;
-  const dim3 block(a.cols * t);
+  const dim3 block(2 * a.cols * (N / 16));
   const dim3 grid(a.nx / a.cols);
-  const size_t lds = col_lds_bytes(N, a.cols);
-  hipLaunchKernelGGL((col_kernel<N, NORM>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((col_kernel<N, NORM>), grid, block, col_lds_bytes(N, a.cols), s, a);
   return hipGetLastError();
 }
 

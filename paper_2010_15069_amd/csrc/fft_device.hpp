@@ -1,9 +1,11 @@
-// Device building blocks of the split-step solver: register-resident Stockham FFT passes over
-// the two spinor components at once, compensated (hi + lo) twiddle products, and the (U - 1)
-// sine/cosine helper used by the unit-modulus real-space propagators.
+// Device building blocks of the split-step solver: register-resident Stockham FFT passes,
+// compensated (hi + lo) twiddle products, the (U - 1) sine/cosine helper used by the
+// unit-modulus real-space propagators, lane-pair exchange and fp64 reductions.
 //
-// A grid point is carried as one float4 {re_up, im_up, re_dn, im_dn}; both components share the
-// FFT's index arithmetic and twiddles.
+// The FFT code is generic over the per-position value type V:
+//   float2 -- one complex number (the step kernels: each thread owns one spinor component and
+//             the neighbouring lane owns the other component of the same positions);
+//   float4 -- both components {re_up, im_up, re_dn, im_dn} of a position (energy kernels).
 //
 // FFT organisation (transform length N = 16^a * r, r in {1, 2, 4, 8}): T = N/16 threads own one
 // transform, thread t holding the 16 positions t + T*m (m = 0..15).  Each Stockham stage of radix
@@ -11,7 +13,7 @@
 // but the last go through LDS, and the last stage's outputs land back in the thread's own
 // registers in natural order.  So the first stage reads and the last stage writes the positions
 // t + T*m, which are contiguous across threads: global loads and stores are coalesced and no
-// digit reversal pass exists.
+// digit-reversal pass exists.
 //
 // Accuracy: fp32 twiddles rounded once are off the unit circle by ~3e-8, and the same error is
 // re-applied every step, so it accumulates coherently over thousands of steps.  Every
@@ -25,131 +27,131 @@
 namespace sgpe {
 
 // ---------------------------------------------------------------------------------------------
-// float4 = two complex numbers
+// Complex arithmetic on float2 (one complex) and float4 (two complexes sharing the operation).
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+__device__ __forceinline__ float2 vadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 vsub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 vneg(float2 a) { return make_float2(-a.x, -a.y); }
+__device__ __forceinline__ float2 vscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float4 vadd(float4 a, float4 b) {
   return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
 }
-__device__ __forceinline__ float4 sub4(float4 a, float4 b) {
+__device__ __forceinline__ float4 vsub(float4 a, float4 b) {
   return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
 }
+__device__ __forceinline__ float4 vneg(float4 a) { return make_float4(-a.x, -a.y, -a.z, -a.w); }
+__device__ __forceinline__ float4 vscale(float4 a, float s) {
+  return make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
+}
+
 // Multiply by exp(DIR * i*pi/2) = DIR * i  (DIR = -1: forward transform sign).
 template <int DIR>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  if constexpr (DIR < 0) return make_float2(a.y, -a.x);
+  else return make_float2(-a.y, a.x);
+}
+template <int DIR>
 __device__ __forceinline__ float4 rot90(float4 a) {
-  if constexpr (DIR < 0) return make_float4(a.y, -a.x, a.w, -a.z);   // * (-i)
-  else return make_float4(-a.y, a.x, -a.w, a.z);                      // * (+i)
+  if constexpr (DIR < 0) return make_float4(a.y, -a.x, a.w, -a.z);
+  else return make_float4(-a.y, a.x, -a.w, a.z);
 }
 
-// z * (c + i*DIR*s) with c = ch + cl and s = sh + sl given as hi/lo pairs.
+// z * (c + i*DIR*s) with c = ch + cl and s = sh + sl given as hi/lo pairs; the lo products form
+// the innermost term of each fused multiply-add chain.
 template <int DIR>
-__device__ __forceinline__ float2 cmul_comp(float re, float im, float ch, float cl, float sh, float sl) {
-  const float ds_h = DIR < 0 ? -sh : sh;
-  const float ds_l = DIR < 0 ? -sl : sl;
-  // re = re*c - im*(DIR s), im = re*(DIR s) + im*c; the lo parts go into the innermost term.
-  const float lo_r = fmaf(re, cl, -im * ds_l);
-  const float lo_i = fmaf(re, ds_l, im * cl);
-  const float out_r = fmaf(re, ch, fmaf(-im, ds_h, lo_r));
-  const float out_i = fmaf(re, ds_h, fmaf(im, ch, lo_i));
-  return make_float2(out_r, out_i);
+__device__ __forceinline__ float2 cmul_comp(float2 a, float ch, float cl, float sh, float sl) {
+  const float dsh = DIR < 0 ? -sh : sh;
+  const float dsl = DIR < 0 ? -sl : sl;
+  const float lo_r = fmaf(a.x, cl, -a.y * dsl);
+  const float lo_i = fmaf(a.x, dsl, a.y * cl);
+  return make_float2(fmaf(a.x, ch, fmaf(-a.y, dsh, lo_r)), fmaf(a.x, dsh, fmaf(a.y, ch, lo_i)));
 }
-
 template <int DIR>
-__device__ __forceinline__ float4 cmul4_comp(float4 a, float ch, float cl, float sh, float sl) {
-  const float2 u = cmul_comp<DIR>(a.x, a.y, ch, cl, sh, sl);
-  const float2 d = cmul_comp<DIR>(a.z, a.w, ch, cl, sh, sl);
+__device__ __forceinline__ float4 cmul_comp(float4 a, float ch, float cl, float sh, float sl) {
+  const float2 u = cmul_comp<DIR>(make_float2(a.x, a.y), ch, cl, sh, sl);
+  const float2 d = cmul_comp<DIR>(make_float2(a.z, a.w), ch, cl, sh, sl);
   return make_float4(u.x, u.y, d.x, d.y);
 }
 
 // Multiply by a table twiddle w = exp(-2 pi i j / N) stored as {re_hi, im_hi, re_lo, im_lo};
 // the inverse transform (DIR = +1) uses conj(w).
-template <int DIR>
-__device__ __forceinline__ float4 twmul(float4 a, float4 w) {
-  // table holds c - i s  (forward root); cmul_comp<DIR> builds c + i*DIR*s, so pass s = -im.
-  return cmul4_comp<DIR>(a, w.x, w.z, -w.y, -w.w);
+template <int DIR, class V>
+__device__ __forceinline__ V twmul(V a, float4 w) {
+  return cmul_comp<DIR>(a, w.x, w.z, -w.y, -w.w);
 }
 
 // Compensated split constants (value = hi + lo to fp64 accuracy).
-// 1/sqrt(2)
-#define SGPE_R2_HI 0.70710676908493042f
+#define SGPE_R2_HI 0.70710676908493042f   // 1/sqrt(2)
 #define SGPE_R2_LO 1.21016175e-08f
-// cos(pi/8), sin(pi/8)
-#define SGPE_C8_HI 0.92387950420379639f
+#define SGPE_C8_HI 0.92387950420379639f   // cos(pi/8)
 #define SGPE_C8_LO 2.83074897e-08f
-#define SGPE_S8_HI 0.38268342614173889f
+#define SGPE_S8_HI 0.38268342614173889f   // sin(pi/8)
 #define SGPE_S8_LO 6.22335072e-09f
 
-// exp(DIR*i*pi/4) * z: (1 + DIR i)/sqrt(2) * z
+__device__ __forceinline__ float r2mul(float s) { return fmaf(s, SGPE_R2_HI, s * SGPE_R2_LO); }
+
+// exp(DIR*i*pi/4) * z = (1 + DIR i)/sqrt(2) * z
+template <int DIR>
+__device__ __forceinline__ float2 rot45(float2 a) {
+  if constexpr (DIR < 0) return make_float2(r2mul(a.x + a.y), r2mul(a.y - a.x));
+  else return make_float2(r2mul(a.x - a.y), r2mul(a.x + a.y));
+}
 template <int DIR>
 __device__ __forceinline__ float4 rot45(float4 a) {
-  float4 s;
-  if constexpr (DIR < 0) {  // (1 - i)(x + iy) = (x + y) + i(y - x)
-    s = make_float4(a.x + a.y, a.y - a.x, a.z + a.w, a.w - a.z);
-  } else {                  // (1 + i)(x + iy) = (x - y) + i(x + y)
-    s = make_float4(a.x - a.y, a.x + a.y, a.z - a.w, a.z + a.w);
-  }
-  return make_float4(fmaf(s.x, SGPE_R2_HI, s.x * SGPE_R2_LO), fmaf(s.y, SGPE_R2_HI, s.y * SGPE_R2_LO),
-                     fmaf(s.z, SGPE_R2_HI, s.z * SGPE_R2_LO), fmaf(s.w, SGPE_R2_HI, s.w * SGPE_R2_LO));
+  const float2 u = rot45<DIR>(make_float2(a.x, a.y));
+  const float2 d = rot45<DIR>(make_float2(a.z, a.w));
+  return make_float4(u.x, u.y, d.x, d.y);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Small DFTs in registers, natural order in and out: y_k = sum_r x_r exp(DIR 2 pi i r k / R).
 // ---------------------------------------------------------------------------------------------
-template <int DIR>
-__device__ __forceinline__ void dft2(float4& a0, float4& a1) {
-  const float4 t = a0;
-  a0 = add4(t, a1);
-  a1 = sub4(t, a1);
+template <int DIR, class V>
+__device__ __forceinline__ void dft4(V& a0, V& a1, V& a2, V& a3) {
+  const V t0 = vadd(a0, a2), t1 = vsub(a0, a2);
+  const V t2 = vadd(a1, a3), t3 = rot90<DIR>(vsub(a1, a3));
+  a0 = vadd(t0, t2);
+  a2 = vsub(t0, t2);
+  a1 = vadd(t1, t3);
+  a3 = vsub(t1, t3);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft4(float4& a0, float4& a1, float4& a2, float4& a3) {
-  const float4 t0 = add4(a0, a2), t1 = sub4(a0, a2);
-  const float4 t2 = add4(a1, a3), t3 = rot90<DIR>(sub4(a1, a3));
-  a0 = add4(t0, t2);
-  a2 = sub4(t0, t2);
-  a1 = add4(t1, t3);
-  a3 = sub4(t1, t3);
-}
-
-template <int DIR>
-__device__ __forceinline__ void dft8(float4 (&a)[8]) {
-  float4 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
-  float4 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+template <int DIR, class V>
+__device__ __forceinline__ void dft8(V (&a)[8]) {
+  V e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  V o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
   dft4<DIR>(e0, e1, e2, e3);
   dft4<DIR>(o0, o1, o2, o3);
   o1 = rot45<DIR>(o1);
   o2 = rot90<DIR>(o2);
   o3 = rot90<DIR>(rot45<DIR>(o3));
-  a[0] = add4(e0, o0); a[4] = sub4(e0, o0);
-  a[1] = add4(e1, o1); a[5] = sub4(e1, o1);
-  a[2] = add4(e2, o2); a[6] = sub4(e2, o2);
-  a[3] = add4(e3, o3); a[7] = sub4(e3, o3);
+  a[0] = vadd(e0, o0); a[4] = vsub(e0, o0);
+  a[1] = vadd(e1, o1); a[5] = vsub(e1, o1);
+  a[2] = vadd(e2, o2); a[6] = vsub(e2, o2);
+  a[3] = vadd(e3, o3); a[7] = vsub(e3, o3);
 }
 
-// 16-point DFT as 4x4: x index r = r1 + 4 r2, output k = k2 + 4 k1.
-template <int DIR>
-__device__ __forceinline__ void dft16(float4 (&a)[16]) {
+// 16-point DFT as 4x4: input index r = r1 + 4 r2, output k = k2 + 4 k1.
+template <int DIR, class V>
+__device__ __forceinline__ void dft16(V (&a)[16]) {
 #pragma unroll
   for (int r1 = 0; r1 < 4; ++r1) dft4<DIR>(a[r1], a[r1 + 4], a[r1 + 8], a[r1 + 12]);
-  // slot r1 + 4 k2 holds A[r1][k2]; multiply by W16^(r1 k2).
-  // W16^1 = c8 + i DIR s8; W16^2 = rot45; W16^3 = s8 + i DIR c8; W16^4 = rot90;
-  // W16^6 = rot90*rot45; W16^9 = -W16^1.
-  a[5] = cmul4_comp<DIR>(a[5], SGPE_C8_HI, SGPE_C8_LO, SGPE_S8_HI, SGPE_S8_LO);    // (1,1): 1
-  a[9] = rot45<DIR>(a[9]);                                                          // (1,2): 2
-  a[13] = cmul4_comp<DIR>(a[13], SGPE_S8_HI, SGPE_S8_LO, SGPE_C8_HI, SGPE_C8_LO);  // (1,3): 3
-  a[6] = rot45<DIR>(a[6]);                                                          // (2,1): 2
-  a[10] = rot90<DIR>(a[10]);                                                        // (2,2): 4
-  a[14] = rot90<DIR>(rot45<DIR>(a[14]));                                            // (2,3): 6
-  a[7] = cmul4_comp<DIR>(a[7], SGPE_S8_HI, SGPE_S8_LO, SGPE_C8_HI, SGPE_C8_LO);    // (3,1): 3
-  a[11] = rot90<DIR>(rot45<DIR>(a[11]));                                            // (3,2): 6
-  {                                                                                 // (3,3): 9
-    const float4 t = cmul4_comp<DIR>(a[15], SGPE_C8_HI, SGPE_C8_LO, SGPE_S8_HI, SGPE_S8_LO);
-    a[15] = make_float4(-t.x, -t.y, -t.z, -t.w);
-  }
+  // slot r1 + 4 k2 holds A[r1][k2]; multiply by W16^(r1 k2):
+  // W16^1 = c8 + i DIR s8, W16^2 = rot45, W16^3 = s8 + i DIR c8, W16^4 = rot90,
+  // W16^6 = rot90 rot45, W16^9 = -W16^1.
+  a[5] = cmul_comp<DIR>(a[5], SGPE_C8_HI, SGPE_C8_LO, SGPE_S8_HI, SGPE_S8_LO);    // (1,1): 1
+  a[9] = rot45<DIR>(a[9]);                                                       // (1,2): 2
+  a[13] = cmul_comp<DIR>(a[13], SGPE_S8_HI, SGPE_S8_LO, SGPE_C8_HI, SGPE_C8_LO);  // (1,3): 3
+  a[6] = rot45<DIR>(a[6]);                                                       // (2,1): 2
+  a[10] = rot90<DIR>(a[10]);                                                     // (2,2): 4
+  a[14] = rot90<DIR>(rot45<DIR>(a[14]));                                         // (2,3): 6
+  a[7] = cmul_comp<DIR>(a[7], SGPE_S8_HI, SGPE_S8_LO, SGPE_C8_HI, SGPE_C8_LO);    // (3,1): 3
+  a[11] = rot90<DIR>(rot45<DIR>(a[11]));                                         // (3,2): 6
+  a[15] = vneg(cmul_comp<DIR>(a[15], SGPE_C8_HI, SGPE_C8_LO, SGPE_S8_HI, SGPE_S8_LO));  // (3,3): 9
 #pragma unroll
   for (int k2 = 0; k2 < 4; ++k2) dft4<DIR>(a[4 * k2], a[4 * k2 + 1], a[4 * k2 + 2], a[4 * k2 + 3]);
-  // slot k1 + 4 k2 now holds y[k2 + 4 k1]: transpose the 4x4 register tile.
-  float4 t[16];
+  // slot k1 + 4 k2 now holds y[k2 + 4 k1]: transpose the 4x4 register tile (renaming only).
+  V t[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) t[i] = a[i];
 #pragma unroll
@@ -158,10 +160,12 @@ __device__ __forceinline__ void dft16(float4 (&a)[16]) {
     for (int k2 = 0; k2 < 4; ++k2) a[k2 + 4 * k1] = t[k1 + 4 * k2];
 }
 
-template <int R, int DIR>
-__device__ __forceinline__ void dft(float4 (&a)[R]) {
+template <int R, int DIR, class V>
+__device__ __forceinline__ void dft(V (&a)[R]) {
   if constexpr (R == 2) {
-    dft2<DIR>(a[0], a[1]);
+    const V t = a[0];
+    a[0] = vadd(t, a[1]);
+    a[1] = vsub(t, a[1]);
   } else if constexpr (R == 4) {
     dft4<DIR>(a[0], a[1], a[2], a[3]);
   } else if constexpr (R == 8) {
@@ -173,14 +177,15 @@ __device__ __forceinline__ void dft(float4 (&a)[R]) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// LDS addressing: a transform's N points occupy N + N/16 float4 slots (one pad slot per 16) and
-// C transforms are interleaved slot by slot (column pass: lanes of consecutive columns hit
-// consecutive float4s).
+// LDS addressing: a transform's N positions occupy N + N/16 slots (one pad slot per 16
+// positions) and `stride` transforms are interleaved slot by slot, so that lanes which own
+// neighbouring transforms touch neighbouring slots.
 // ---------------------------------------------------------------------------------------------
+template <class V>
 struct LdsView {
-  float4* base;  // slot 0 of transform c
-  int stride;    // C
-  __device__ __forceinline__ float4& at(int pos) const { return base[(pos + (pos >> 4)) * stride]; }
+  V* base;     // slot 0 of this thread's transform
+  int stride;  // number of interleaved transforms
+  __device__ __forceinline__ V& at(int pos) const { return base[(pos + (pos >> 4)) * stride]; }
 };
 
 // Stage twiddles a thread needs for a length-N transform: the first stage (L = 1) needs none;
@@ -225,14 +230,13 @@ __device__ __forceinline__ void load_twiddles(TwRegs<N>& tr, int t, const float4
 
 // One Stockham stage: radix R, L = product of the radices already applied; its twiddles start at
 // tr.w[BASE].
-template <int N, int R, int L, int DIR, bool LAST, int BASE>
-__device__ __forceinline__ void stockham_stage(float4 (&v)[16], const LdsView& lds, int t,
-                                               const TwRegs<N>& tr) {
+template <int N, int R, int L, int DIR, bool LAST, int BASE, class V>
+__device__ __forceinline__ void stockham_stage(V (&v)[16], const LdsView<V>& lds, int t, const TwRegs<N>& tr) {
   constexpr int T = N / 16;
   constexpr int U = 16 / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    float4 a[R];
+    V a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + U * r];
     const int b = t + T * u;
@@ -254,9 +258,9 @@ __device__ __forceinline__ void stockham_stage(float4 (&v)[16], const LdsView& l
 }
 
 // Full length-N transform of the 16 registers (positions t + T*m) in place.  All threads of the
-// workgroup call it (it contains workgroup barriers).
-template <int N, int DIR, int L = 1, int BASE = 0>
-__device__ __forceinline__ void fft_pass(float4 (&v)[16], const LdsView& lds, int t, const TwRegs<N>& tr) {
+// workgroup call it (it contains workgroup barriers); on return every LDS read is complete.
+template <int N, int DIR, int L = 1, int BASE = 0, class V>
+__device__ __forceinline__ void fft_pass(V (&v)[16], const LdsView<V>& lds, int t, const TwRegs<N>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= 16 ? 16 : REM;
   constexpr bool LAST = (R == REM);
@@ -273,9 +277,18 @@ __device__ __forceinline__ void fft_pass(float4 (&v)[16], const LdsView& lds, in
 }
 
 // ---------------------------------------------------------------------------------------------
-// (cos(phi) - 1, sin(phi)) with relative accuracy on both parts for small |phi|.
-// Cody-Waite reduction by pi/2 (the first product is exact inside the FMA for |k| < 2^10),
-// Taylor polynomials on |r| <= pi/4.  Also returns sin(phi)/phi (1 at phi = 0).
+// Lane pairs: lanes 2j and 2j+1 hold the two spinor components of the same positions.  The
+// partner's value comes over the DPP quad permutation [1,0,3,2] (no LDS traffic, no barrier).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float2 pair_swap(float2 x) { return make_float2(pair_swap(x.x), pair_swap(x.y)); }
+
+// ---------------------------------------------------------------------------------------------
+// (cos(phi) - 1, sin(phi)) with relative accuracy on both parts for small |phi|, and
+// sin(phi)/phi.  Cody-Waite reduction by pi/2 (the first product is exact inside the FMA for
+// |k| < 2^10), Taylor polynomials on |r| <= pi/4.
 // ---------------------------------------------------------------------------------------------
 struct SinCosM1 {
   float cm1, s, sinc;
@@ -335,17 +348,24 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum over the workgroup; every thread must call it; red must hold >= blockDim.x/64 doubles.
+// Sum over the workgroup in a fixed order; every thread must call it; red must hold 64 doubles.
 // Result valid in every thread.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
+  const int n = blockDim.x;
   double s = 0.0;
-  for (int w = 0; w < nw; ++w) s += red[w];
+  if ((n & 63) == 0) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    for (int w = 0; w < (n >> 6); ++w) s += red[w];
+  } else {  // a workgroup smaller than one wave (small grids)
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int i = 0; i < n; ++i) s += red[i];
+  }
   __syncthreads();
   return s;
 }

@@ -8,15 +8,15 @@ namespace sgpe {
 // -------------------------------------------------------------------------------------------
 // Geometry
 // -------------------------------------------------------------------------------------------
-int row_threads_per_row(int nx) { return nx / 16; }
+// Step kernels: lane pairs (two components) x T = n/16 lanes per line; a slot of the LDS
+// exchange holds both components (16 bytes).
+size_t row_lds_bytes(int nx, int rows) { return size_t(rows) * size_t(nx + nx / 16) * 16; }
 
-size_t row_lds_bytes(int nx, int rows) { return size_t(rows) * size_t(nx + nx / 16) * sizeof(float4); }
-
-size_t col_lds_bytes(int ny, int cols) { return size_t(cols) * size_t(ny + ny / 16) * sizeof(float4); }
+size_t col_lds_bytes(int ny, int cols) { return size_t(cols) * size_t(ny + ny / 16) * 16; }
 
 int row_rows_per_block(int nx, int ny, size_t max_lds) {
   const int t = nx / 16;
-  int rows = 256 / t;
+  int rows = 128 / t;  // 256 threads
   if (rows < 1) rows = 1;
   if (rows > ny) rows = ny;
   while (rows > 1 && row_lds_bytes(nx, rows) > max_lds) rows >>= 1;
@@ -26,19 +26,38 @@ int row_rows_per_block(int nx, int ny, size_t max_lds) {
 bool col_cols_supported(int nx, int ny, int cols, size_t max_lds) {
   if (cols < 1 || (cols & (cols - 1)) != 0 || cols > nx) return false;
   const int t = ny / 16;
-  if (cols * t > 256) return false;
+  if (2 * cols * t > 512) return false;
   return col_lds_bytes(ny, cols) <= max_lds;
 }
 
 int col_default_cols(int nx, int ny, size_t max_lds) {
   const int t = ny / 16;
-  int c = 256 / t;
+  int c = 128 / t;  // 256 threads
   if (c < 1) c = 1;
   // prefer at least 4 columns (64-byte row segments) while threads and LDS allow it
   int want = 4;
   while (want > c && !col_cols_supported(nx, ny, want, max_lds)) want >>= 1;
   if (want > c) c = want;
   while (c > 1 && !col_cols_supported(nx, ny, c, max_lds)) c >>= 1;
+  return c;
+}
+
+// Energy kernels: one lane holds both components of its 16 positions.
+int energy_rows_per_block(int nx, int ny, size_t max_lds) {
+  const int t = nx / 16;
+  int rows = 256 / t;
+  if (rows < 1) rows = 1;
+  if (rows > ny) rows = ny;
+  while (rows > 1 && size_t(rows) * size_t(nx + nx / 16) * 16 > max_lds) rows >>= 1;
+  return rows;
+}
+
+int energy_cols_per_block(int nx, int ny, size_t max_lds) {
+  const int t = ny / 16;
+  int c = 256 / t;
+  if (c < 1) c = 1;
+  if (c > nx) c = nx;
+  while (c > 1 && size_t(c) * size_t(ny + ny / 16) * 16 > max_lds) c >>= 1;
   return c;
 }
 
@@ -51,14 +70,14 @@ int norm_blocks() { return 256; }
 template <int N>
 __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   extern __shared__ float4 lds_raw[];
-  __shared__ double red[16];
+  __shared__ double red[64];
   constexpr int T = N / 16;
   constexpr int SLOTS = N + N / 16;
   const int tid = threadIdx.x;
   const int rloc = tid / T;
   const int t = tid - rloc * T;
   const int row = blockIdx.x * a.rows_per_block + rloc;
-  const LdsView lds{lds_raw + rloc * SLOTS, 1};
+  const LdsView<float4> lds{lds_raw + rloc * SLOTS, 1};
   const float4* __restrict__ p = a.psi + size_t(row) * N;
   float4 v[16];
 #pragma unroll
@@ -94,14 +113,14 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
 template <int N>
 __global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
   extern __shared__ float4 lds_raw[];
-  __shared__ double red[16];
+  __shared__ double red[64];
   constexpr int T = N / 16;
   const int C = a.cols;
   const int tid = threadIdx.x;
   const int c = tid & (C - 1);
   const int t = tid / C;
   const int x = blockIdx.x * C + c;
-  const LdsView lds{lds_raw + c, C};
+  const LdsView<float4> lds{lds_raw + c, C};
   const float4* __restrict__ p = a.scratch + x;
   const size_t rs = size_t(a.nx);
   float4 v[16];
@@ -131,7 +150,7 @@ __global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
 // -------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) norm_kernel(const float4* __restrict__ psi, long long n,
                                                    double* __restrict__ partials) {
-  __shared__ double red[16];
+  __shared__ double red[64];
   double acc = 0.0;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
     const float4 w = psi[i];
@@ -146,7 +165,7 @@ template <int N>
 static hipError_t energy_row_launch(const EnergyArgs& a, hipStream_t s) {
   const dim3 block(a.rows_per_block * (N / 16));
   const dim3 grid(a.ny / a.rows_per_block);
-  hipLaunchKernelGGL((energy_row_kernel<N>), grid, block, row_lds_bytes(N, a.rows_per_block), s, a);
+  hipLaunchKernelGGL((energy_row_kernel<N>), grid, block, size_t(a.rows_per_block) * (N + N / 16) * 16, s, a);
   return hipGetLastError();
 }
 
@@ -154,7 +173,7 @@ template <int N>
 static hipError_t energy_col_launch(const EnergyArgs& a, hipStream_t s) {
   const dim3 block(a.cols * (N / 16));
   const dim3 grid(a.nx / a.cols);
-  hipLaunchKernelGGL((energy_col_kernel<N>), grid, block, col_lds_bytes(N, a.cols), s, a);
+  hipLaunchKernelGGL((energy_col_kernel<N>), grid, block, size_t(a.cols) * (N + N / 16) * 16, s, a);
   return hipGetLastError();
 }
 

@@ -13,13 +13,19 @@
 // 2n + 2 sweeps.  In imaginary time the column pass also produces the norm that the next row pass
 // rescales by (Parseval), so renormalisation costs no extra sweep.
 //
+// Thread layout: lanes 2j and 2j+1 own the up and down component of the same 16 positions of a
+// row; a global load of a lane pair is one contiguous 16-byte point, so a wave reads 512
+// contiguous bytes per instruction.  The transforms of the two components are independent; the
+// 2x2 real-space exponential gets the partner component over a DPP lane swap.
+//
 // Every operator close to the identity is applied as psi + (U - 1) psi with U - 1 held to fp32
-// relative accuracy, so that unit-modulus propagators do not pick up a coherent |U| != 1 error
-// from rounding their tables.
+// relative accuracy, and the small correction is formed before it is added to psi (one rounding
+// of the large value), so that unit-modulus propagators do not drift coherently.
 #include "fft_device.hpp"
 #include "sgpe_internal.hpp"
 
 namespace sgpe {
+
 // -------------------------------------------------------------------------------------------
 // Sum of the previous column pass's partials -> scale for the row pass.  Every wave computes
 // the same sum in the same order, so every workgroup applies bit-identical scales.
@@ -39,51 +45,53 @@ __device__ __forceinline__ float row_scale(const RowArgs& a) {
 }
 
 // -------------------------------------------------------------------------------------------
-// Real-space exponential R(h) at one point (Eqs. (H2)-(H4), densities of the input).
-// hv = h V(x, y); hbx = h Omega(x) / 2.
+// Real-space exponential R(h) (Eqs. (H2)-(H4), densities of the input), applied to this lane's
+// component w; o is the partner lane's component at the same point.  up = (this lane owns the
+// up component).  hv = h V(x, y); hbx = h Omega(x) / 2.
 // -------------------------------------------------------------------------------------------
+struct RCoef {
+  float hd_own;      // +- h delta / 2 for this component
+  float hg_own;      // h g_{ss} of this component
+  float hg_ud;       // h g_{up dn}
+  float sgn;         // +1 up, -1 down
+  float hg_uu, hg_dd, hdelta2;
+};
+
 template <bool IMAG, bool FULL>
-__device__ __forceinline__ float4 apply_r(float4 w, float hv, float hbx, const RowArgs& a) {
-  const float nu = fmaf(w.x, w.x, w.y * w.y);
-  const float nd = fmaf(w.z, w.z, w.w * w.w);
+__device__ __forceinline__ float2 apply_r(float2 w, float2 o, float hv, float hbx, const RCoef& c) {
+  const float n_own = fmaf(w.x, w.x, w.y * w.y);
+  const float n_oth = fmaf(o.x, o.x, o.y * o.y);
   if constexpr (!FULL) {
-    const float phu = fmaf(a.hg_uu, nu, fmaf(a.hg_ud, nd, hv + a.hdelta2));
-    const float phd = fmaf(a.hg_dd, nd, fmaf(a.hg_ud, nu, hv - a.hdelta2));
+    const float ph = fmaf(c.hg_own, n_own, fmaf(c.hg_ud, n_oth, hv + c.hd_own));
     if constexpr (!IMAG) {
-      // psi * exp(-i phi) = psi + psi (cm1 - i s); the small correction is formed first and
-      // added once (one rounding of the large value per step).
-      const SinCosM1 su = sincos_m1(phu);
-      const SinCosM1 sd = sincos_m1(phd);
-      return make_float4(w.x + fmaf(w.x, su.cm1, w.y * su.s), w.y + fmaf(w.y, su.cm1, -w.x * su.s),
-                         w.z + fmaf(w.z, sd.cm1, w.w * sd.s), w.w + fmaf(w.w, sd.cm1, -w.z * sd.s));
+      // w * exp(-i ph) = w + w (cm1 - i s); the small correction is formed first.
+      const SinCosM1 sc = sincos_m1(ph);
+      return make_float2(w.x + fmaf(w.x, sc.cm1, w.y * sc.s), w.y + fmaf(w.y, sc.cm1, -w.x * sc.s));
     } else {
-      const float eu = expf(-phu);
-      const float ed = expf(-phd);
-      return make_float4(w.x * eu, w.y * eu, w.z * ed, w.w * ed);
+      return vscale(w, expf(-ph));
     }
   } else {
-    // H_R = A 1 + Bx sigma_x + Bz sigma_z (all times h)
-    const float gu = fmaf(a.hg_uu, nu, a.hg_ud * nd);
-    const float gd = fmaf(a.hg_dd, nd, a.hg_ud * nu);
+    // H_R = A 1 + Bx sigma_x + Bz sigma_z (all times h); the up/down densities are
+    // (n_own, n_oth) or (n_oth, n_own).
+    const float nu = c.sgn > 0.0f ? n_own : n_oth;
+    const float nd = c.sgn > 0.0f ? n_oth : n_own;
+    const float gu = fmaf(c.hg_uu, nu, c.hg_ud * nd);
+    const float gd = fmaf(c.hg_dd, nd, c.hg_ud * nu);
     const float ha = fmaf(0.5f, gu + gd, hv);
-    const float hbz = fmaf(0.5f, gu - gd, a.hdelta2);
+    const float hbz = fmaf(0.5f, gu - gd, c.hdelta2);
     const float th = sqrtf(fmaf(hbx, hbx, hbz * hbz));
     if constexpr (!IMAG) {
-      // M = cos(th) 1 - i sin(th)/th (hB . sigma);  psi' = E M psi, E = exp(-i hA)
+      // M = cos(th) 1 - i sin(th)/th (hB . sigma): this component's row of (M - 1) psi is
+      // cm1 w - i X with X = +-pz w + px o.
       const SinCosM1 sb = sincos_m1(th);
-      const float px = sb.sinc * hbx, pz = sb.sinc * hbz;
-      // X = pz psi_u + px psi_d, Y = px psi_u - pz psi_d; (M - 1) psi = cm1 psi - i (X, Y)
-      const float xr = fmaf(pz, w.x, px * w.z), xi = fmaf(pz, w.y, px * w.w);
-      const float yr = fmaf(px, w.x, -pz * w.z), yi = fmaf(px, w.y, -pz * w.w);
-      const float mur = fmaf(sb.cm1, w.x, xi), mui = fmaf(sb.cm1, w.y, -xr);
-      const float mdr = fmaf(sb.cm1, w.z, yi), mdi = fmaf(sb.cm1, w.w, -yr);
-      // E M psi - psi = c_M + (E - 1)(psi + c_M), E - 1 = cm1_A - i s_A; added to psi once.
+      const float px = sb.sinc * hbx, pz = c.sgn * sb.sinc * hbz;
+      const float xr = fmaf(pz, w.x, px * o.x), xi = fmaf(pz, w.y, px * o.y);
+      const float mr = fmaf(sb.cm1, w.x, xi), mi = fmaf(sb.cm1, w.y, -xr);
+      // E M psi - psi = c_M + (E - 1)(w + c_M), E - 1 = cm1_A - i s_A; added to w once.
       const SinCosM1 se = sincos_m1(ha);
-      const float cur = fmaf(se.s, w.y, fmaf(se.cm1, w.x, fmaf(se.s, mui, fmaf(se.cm1, mur, mur))));
-      const float cui = fmaf(-se.s, w.x, fmaf(se.cm1, w.y, fmaf(-se.s, mur, fmaf(se.cm1, mui, mui))));
-      const float cdr = fmaf(se.s, w.w, fmaf(se.cm1, w.z, fmaf(se.s, mdi, fmaf(se.cm1, mdr, mdr))));
-      const float cdi = fmaf(-se.s, w.z, fmaf(se.cm1, w.w, fmaf(-se.s, mdr, fmaf(se.cm1, mdi, mdi))));
-      return make_float4(w.x + cur, w.y + cui, w.z + cdr, w.w + cdi);
+      const float cr = fmaf(se.s, w.y, fmaf(se.cm1, w.x, fmaf(se.s, mi, fmaf(se.cm1, mr, mr))));
+      const float ci = fmaf(-se.s, w.x, fmaf(se.cm1, w.y, fmaf(-se.s, mr, fmaf(se.cm1, mi, mi))));
+      return make_float2(w.x + cr, w.y + ci);
     } else {
       const float ea = expf(-ha);
       float ch, shc;  // cosh(th), sinh(th)/th
@@ -98,11 +106,9 @@ __device__ __forceinline__ float4 apply_r(float4 w, float hv, float hbx, const R
         ch = 0.5f * (ep + em);
         shc = 0.5f * (ep - em) / th;
       }
-      const float m11 = ea * fmaf(-shc, hbz, ch);
-      const float m22 = ea * fmaf(shc, hbz, ch);
-      const float m12 = -ea * shc * hbx;
-      return make_float4(fmaf(m11, w.x, m12 * w.z), fmaf(m11, w.y, m12 * w.w),
-                         fmaf(m12, w.x, m22 * w.z), fmaf(m12, w.y, m22 * w.w));
+      const float m_own = ea * fmaf(-c.sgn * shc, hbz, ch);
+      const float m_x = -ea * shc * hbx;
+      return make_float2(fmaf(m_own, w.x, m_x * o.x), fmaf(m_own, w.y, m_x * o.y));
     }
   }
 }
@@ -111,20 +117,23 @@ __device__ __forceinline__ float4 apply_r(float4 w, float hv, float hbx, const R
 // Row pass
 // -------------------------------------------------------------------------------------------
 template <int N, int MODE, bool IMAG, bool FULL>
-__global__ void __launch_bounds__(256) row_kernel(RowArgs a) {
-  extern __shared__ float4 lds_raw[];
+__global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
+  extern __shared__ float2 lds_raw[];
   constexpr int T = N / 16;
   constexpr int SLOTS = N + N / 16;
   const int tid = threadIdx.x;
-  const int rloc = tid / T;
-  const int t = tid - rloc * T;
+  const int comp = tid & 1;
+  const int pair = tid >> 1;
+  const int rloc = pair / T;
+  const int t = pair - rloc * T;
   const int row = blockIdx.x * a.rows_per_block + rloc;
-  const LdsView lds{lds_raw + rloc * SLOTS, 1};
-  float4* __restrict__ p = a.psi + size_t(row) * N;
+  const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 2};
+  // element `pos` of this lane's component is p[2 * pos]
+  float2* __restrict__ p = reinterpret_cast<float2*>(a.psi + size_t(row) * N) + comp;
 
-  float4 v[16];
+  float2 v[16];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = p[t + T * m];
+  for (int m = 0; m < 16; ++m) v[m] = p[2 * (t + T * m)];
   TwRegs<N> tr;
   load_twiddles<N>(tr, t, a.tw);
 
@@ -134,8 +143,17 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs a) {
     const float s = row_scale(a);
     fft_pass<N, +1>(v, lds, t, tr);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = make_float4(v[m].x * s, v[m].y * s, v[m].z * s, v[m].w * s);
+    for (int m = 0; m < 16; ++m) v[m] = vscale(v[m], s);
     if constexpr (MODE == ROW_STEP) {
+      const bool up = (comp == 0);
+      RCoef c;
+      c.sgn = up ? 1.0f : -1.0f;
+      c.hd_own = up ? a.hdelta2 : -a.hdelta2;
+      c.hg_own = up ? a.hg_uu : a.hg_dd;
+      c.hg_ud = a.hg_ud;
+      c.hg_uu = a.hg_uu;
+      c.hg_dd = a.hg_dd;
+      c.hdelta2 = a.hdelta2;
       const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
       const float hvy = a.hvy * y * y;
 #pragma unroll
@@ -144,23 +162,24 @@ __global__ void __launch_bounds__(256) row_kernel(RowArgs a) {
         const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
         const float hv = fmaf(a.hvx * x, x, hvy);
         const float hbx = FULL ? a.hbx[j] : 0.0f;
-        v[m] = apply_r<IMAG, FULL>(v[m], hv, hbx, a);
+        const float2 o = pair_swap(v[m]);
+        v[m] = apply_r<IMAG, FULL>(v[m], o, hv, hbx, c);
       }
       fft_pass<N, -1>(v, lds, t, tr);
     }
   }
 #pragma unroll
-  for (int m = 0; m < 16; ++m) p[t + T * m] = v[m];
+  for (int m = 0; m < 16; ++m) p[2 * (t + T * m)] = v[m];
 }
 
+// -------------------------------------------------------------------------------------------
 // Launcher
+// -------------------------------------------------------------------------------------------
 template <int N, int MODE, bool IMAG, bool FULL>
 static hipError_t row_launch_t(const RowArgs& a, hipStream_t s) {
-  const int t = N / 16;
-  const dim3 block(a.rows_per_block * t);
+  const dim3 block(2 * a.rows_per_block * (N / 16));
   const dim3 grid(a.ny / a.rows_per_block);
-  const size_t lds = row_lds_bytes(N, a.rows_per_block);
-  hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL>), grid, block, row_lds_bytes(N, a.rows_per_block), s, a);
   return hipGetLastError();
 }
 

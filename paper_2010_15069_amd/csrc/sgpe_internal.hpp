@@ -72,11 +72,12 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 
 // Workgroup geometry helpers (shared with the host so that partial counts match).
-int row_threads_per_row(int nx);
 // max_lds: the device's LDS bytes per workgroup (minus the kernels' static LDS).
 int row_rows_per_block(int nx, int ny, size_t max_lds);
 int col_default_cols(int nx, int ny, size_t max_lds);
 bool col_cols_supported(int nx, int ny, int cols, size_t max_lds);
+int energy_rows_per_block(int nx, int ny, size_t max_lds);
+int energy_cols_per_block(int nx, int ny, size_t max_lds);
 size_t row_lds_bytes(int nx, int rows);
 size_t col_lds_bytes(int ny, int cols);
 int norm_blocks();
