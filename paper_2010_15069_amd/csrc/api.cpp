@@ -33,8 +33,10 @@ struct sgpe_ctx {
   float4* psi = nullptr;
   bool own_psi = false;
   float4* scratch = nullptr;
-  float4* tw_x = nullptr;
+  float4* tw_x = nullptr;   // compensated roots (energy kernels)
   float4* tw_y = nullptr;
+  float4* twp_x = nullptr;  // fp32-rounded roots with modulus corrections (step kernels)
+  float4* twp_y = nullptr;
   // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
   float4* kx_tab[4] = {nullptr, nullptr, nullptr, nullptr};
   float2* ky_tab[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -85,6 +87,20 @@ std::vector<float4> twiddles(int n) {
     const double c = std::cos(a), s = std::sin(a);
     const float ch = float(c), sh = float(s);
     t[j] = make_float4(ch, sh, float(c - double(ch)), float(s - double(sh)));
+  }
+  return t;
+}
+
+// Roots exp(-2 pi i j / n) rounded once to fp32 as {cos, sin, eta, 0}, where
+// 1 + eta = 1 / (cos^2 + sin^2) of the rounded pair (evaluated in fp64): the step kernels'
+// forward transform multiplies by the rounded root and their exact inverse by conj(root)(1 + eta).
+std::vector<float4> twiddles_plain(int n) {
+  std::vector<float4> t(n);
+  for (int j = 0; j < n; ++j) {
+    const double a = 2.0 * M_PI * double(j) / double(n);
+    const float c = float(std::cos(a)), s = float(std::sin(a));
+    const double m2 = double(c) * double(c) + double(s) * double(s);
+    t[j] = make_float4(c, s, float(1.0 / m2 - 1.0), 0.0f);
   }
   return t;
 }
@@ -155,7 +171,7 @@ RowArgs row_args(const sgpe_ctx* c) {
   a.nx = p.nx;
   a.ny = p.ny;
   a.rows_per_block = c->rows;
-  a.tw = c->tw_x;
+  a.tw = c->twp_x;
   a.scale = 1.0f;
   a.partials = nullptr;
   a.n_partials = 0;
@@ -185,7 +201,7 @@ ColArgs col_args(const sgpe_ctx* c, bool imag, bool half) {
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.cols = c->cols;
-  a.tw = c->tw_y;
+  a.tw = c->twp_y;
   const int idx = 2 * (imag ? 1 : 0) + (half ? 1 : 0);
   a.kx_tab = c->kx_tab[idx];
   a.ky_tab = c->ky_tab[idx];
@@ -340,6 +356,8 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
   }
   if ((st = upload(c, &c->tw_x, twiddles(p->nx))) != SGPE_OK) return fail(st);
   if ((st = upload(c, &c->tw_y, twiddles(p->ny))) != SGPE_OK) return fail(st);
+  if ((st = upload(c, &c->twp_x, twiddles_plain(p->nx))) != SGPE_OK) return fail(st);
+  if ((st = upload(c, &c->twp_y, twiddles_plain(p->ny))) != SGPE_OK) return fail(st);
   for (int imag = 0; imag < 2; ++imag) {
     for (int half = 0; half < 2; ++half) {
       std::vector<float4> kx;

@@ -45,12 +45,12 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
   float2 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[size_t(t + T * m) * rs];
-  TwRegs<N> tr;
+  TwPlain<N> tr;
   load_twiddles<N>(tr, t, a.tw);
   // this component's row of M' - 1 at k_x: {d_own, d_other}
   const float4 d = a.kx_tab[2 * x + comp];
 
-  fft_pass<N, -1>(v, lds, t, tr);
+  fwd_pass<N>(v, lds, t, tr);
 
   double acc = 0.0;
 #pragma unroll
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
     if (tid == 0) a.partials[blockIdx.x] = s;
   }
 
-  fft_pass<N, +1>(v, lds, t, tr);
+  inv_pass<N>(v, lds, t, tr);
 
 #pragma unroll
   for (int m = 0; m < 16; ++m) p[size_t(t + T * m) * rs] = v[m];

@@ -277,6 +277,307 @@ __device__ __forceinline__ void fft_pass(V (&v)[16], const LdsView<V>& lds, int 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Step-kernel transforms: a forward transform with roots rounded once to fp32, and its exact
+// inverse.
+//
+// A forward transform with fp32-rounded roots w~ is a slightly perturbed DFT.  Followed by the
+// textbook inverse (conjugate roots), the round trip is not the identity: |w~| != 1 scales every
+// butterfly path and that same map is re-applied every step (a coherent drift).  Here the inverse
+// instead undoes the forward stage by stage in reverse order: each small DFT by its conjugate
+// structure and each rounded root by conj(w~) (1 + eta) with 1 + eta = 1/|w~|^2 held in fp32.
+// The pair is then an exact inverse in exact arithmetic, the round trip carries only random
+// rounding, and the rounded roots enter the split step only through commutators with the step's
+// operators, O(dt eps) per step.  The forward costs 4 instructions per complex product instead
+// of 8 for a compensated one, the inverse 6.
+// ---------------------------------------------------------------------------------------------
+#define SGPE_P_R2 0.70710676908493042f       // fp32(1/sqrt(2))
+#define SGPE_P_R2_ETA 3.42285418e-08f        // 1/(2 r2^2) - 1 for the fp32 r2
+#define SGPE_P_C8 0.92387950420379639f       // fp32(cos(pi/8))
+#define SGPE_P_S8 0.38268342614173889f       // fp32(sin(pi/8))
+#define SGPE_P_8_ETA 5.70685721e-08f         // 1/(c8^2 + s8^2) - 1 for the fp32 pair
+
+__device__ __forceinline__ float2 pf_rot90(float2 a) { return make_float2(a.y, -a.x); }   // * (-i)
+__device__ __forceinline__ float2 pi_rot90(float2 a) { return make_float2(-a.y, a.x); }   // * (+i)
+// * r2 (1 - i) and its exact inverse * r2 (1 + i) (1 + eta)
+__device__ __forceinline__ float2 pf_rot45(float2 a) {
+  return make_float2(SGPE_P_R2 * (a.x + a.y), SGPE_P_R2 * (a.y - a.x));
+}
+__device__ __forceinline__ float2 pi_rot45(float2 a) {
+  const float ur = SGPE_P_R2 * (a.x - a.y), ui = SGPE_P_R2 * (a.x + a.y);
+  return make_float2(fmaf(ur, SGPE_P_R2_ETA, ur), fmaf(ui, SGPE_P_R2_ETA, ui));
+}
+// * (c - i s) and its exact inverse * (c + i s) (1 + eta)
+__device__ __forceinline__ float2 pf_cmul(float2 a, float c, float s) {
+  return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -a.x * s));
+}
+__device__ __forceinline__ float2 pi_cmul(float2 a, float c, float s, float eta) {
+  const float ur = fmaf(a.x, c, -a.y * s), ui = fmaf(a.y, c, a.x * s);
+  return make_float2(fmaf(ur, eta, ur), fmaf(ui, eta, ui));
+}
+
+// forward small DFTs (sign -1)
+__device__ __forceinline__ void pf_dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = vadd(a0, a2), t1 = vsub(a0, a2);
+  const float2 t2 = vadd(a1, a3), t3 = pf_rot90(vsub(a1, a3));
+  a0 = vadd(t0, t2);
+  a2 = vsub(t0, t2);
+  a1 = vadd(t1, t3);
+  a3 = vsub(t1, t3);
+}
+// its exact inverse times 4 (conjugate structure; the constants are exact)
+__device__ __forceinline__ void pi_dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = vadd(a0, a2), t1 = vsub(a0, a2);
+  const float2 t2 = vadd(a1, a3), t3 = pi_rot90(vsub(a1, a3));
+  a0 = vadd(t0, t2);
+  a2 = vsub(t0, t2);
+  a1 = vadd(t1, t3);
+  a3 = vsub(t1, t3);
+}
+
+__device__ __forceinline__ void pf_dft8(float2 (&a)[8]) {
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  pf_dft4(e0, e1, e2, e3);
+  pf_dft4(o0, o1, o2, o3);
+  o1 = pf_rot45(o1);
+  o2 = pf_rot90(o2);
+  o3 = pf_rot90(pf_rot45(o3));
+  a[0] = vadd(e0, o0); a[4] = vsub(e0, o0);
+  a[1] = vadd(e1, o1); a[5] = vsub(e1, o1);
+  a[2] = vadd(e2, o2); a[6] = vsub(e2, o2);
+  a[3] = vadd(e3, o3); a[7] = vsub(e3, o3);
+}
+// exact inverse of pf_dft8, times 8
+__device__ __forceinline__ void pi_dft8(float2 (&a)[8]) {
+  float2 e0 = vadd(a[0], a[4]), o0 = vsub(a[0], a[4]);
+  float2 e1 = vadd(a[1], a[5]), o1 = vsub(a[1], a[5]);
+  float2 e2 = vadd(a[2], a[6]), o2 = vsub(a[2], a[6]);
+  float2 e3 = vadd(a[3], a[7]), o3 = vsub(a[3], a[7]);
+  o1 = pi_rot45(o1);
+  o2 = pi_rot90(o2);
+  o3 = pi_rot45(pi_rot90(o3));
+  pi_dft4(e0, e1, e2, e3);
+  pi_dft4(o0, o1, o2, o3);
+  a[0] = e0; a[2] = e1; a[4] = e2; a[6] = e3;
+  a[1] = o0; a[3] = o1; a[5] = o2; a[7] = o3;
+}
+
+// forward 16-point DFT (4x4; input r = r1 + 4 r2, output k = k2 + 4 k1)
+__device__ __forceinline__ void pf_dft16(float2 (&a)[16]) {
+#pragma unroll
+  for (int r1 = 0; r1 < 4; ++r1) pf_dft4(a[r1], a[r1 + 4], a[r1 + 8], a[r1 + 12]);
+  a[5] = pf_cmul(a[5], SGPE_P_C8, SGPE_P_S8);             // W16^1
+  a[9] = pf_rot45(a[9]);                                 // W16^2
+  a[13] = pf_cmul(a[13], SGPE_P_S8, SGPE_P_C8);           // W16^3
+  a[6] = pf_rot45(a[6]);                                 // W16^2
+  a[10] = pf_rot90(a[10]);                               // W16^4
+  a[14] = pf_rot90(pf_rot45(a[14]));                     // W16^6
+  a[7] = pf_cmul(a[7], SGPE_P_S8, SGPE_P_C8);             // W16^3
+  a[11] = pf_rot90(pf_rot45(a[11]));                     // W16^6
+  a[15] = vneg(pf_cmul(a[15], SGPE_P_C8, SGPE_P_S8));     // W16^9 = -W16^1
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) pf_dft4(a[4 * k2], a[4 * k2 + 1], a[4 * k2 + 2], a[4 * k2 + 3]);
+  float2 t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = a[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) a[k2 + 4 * k1] = t[k1 + 4 * k2];
+}
+// exact inverse of pf_dft16, times 16: the same steps undone in reverse order
+__device__ __forceinline__ void pi_dft16(float2 (&a)[16]) {
+  float2 t[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = a[k2 + 4 * k1];
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) pi_dft4(t[4 * k2], t[4 * k2 + 1], t[4 * k2 + 2], t[4 * k2 + 3]);
+  t[5] = pi_cmul(t[5], SGPE_P_C8, SGPE_P_S8, SGPE_P_8_ETA);
+  t[9] = pi_rot45(t[9]);
+  t[13] = pi_cmul(t[13], SGPE_P_S8, SGPE_P_C8, SGPE_P_8_ETA);
+  t[6] = pi_rot45(t[6]);
+  t[10] = pi_rot90(t[10]);
+  t[14] = pi_rot45(pi_rot90(t[14]));
+  t[7] = pi_cmul(t[7], SGPE_P_S8, SGPE_P_C8, SGPE_P_8_ETA);
+  t[11] = pi_rot45(pi_rot90(t[11]));
+  t[15] = vneg(pi_cmul(t[15], SGPE_P_C8, SGPE_P_S8, SGPE_P_8_ETA));
+#pragma unroll
+  for (int r1 = 0; r1 < 4; ++r1) pi_dft4(t[r1], t[r1 + 4], t[r1 + 8], t[r1 + 12]);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = t[i];
+}
+
+template <int R>
+__device__ __forceinline__ void pf_dft(float2 (&a)[R]) {
+  if constexpr (R == 2) {
+    const float2 t = a[0];
+    a[0] = vadd(t, a[1]);
+    a[1] = vsub(t, a[1]);
+  } else if constexpr (R == 4) {
+    pf_dft4(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    pf_dft8(a);
+  } else {
+    static_assert(R == 16, "radix");
+    pf_dft16(a);
+  }
+}
+template <int R>
+__device__ __forceinline__ void pi_dft(float2 (&a)[R]) {
+  if constexpr (R == 2) {
+    const float2 t = a[0];
+    a[0] = vadd(t, a[1]);
+    a[1] = vsub(t, a[1]);
+  } else if constexpr (R == 4) {
+    pi_dft4(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    pi_dft8(a);
+  } else {
+    static_assert(R == 16, "radix");
+    pi_dft16(a);
+  }
+}
+
+// Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and the modulus
+// correction eta; table entries are float4 {cos, sin, eta, 0} of exp(-2 pi i j / N).
+template <int N>
+struct TwPlain {
+  static constexpr int COUNT = tw_count<N>() > 0 ? tw_count<N>() : 1;
+  float2 cs[COUNT];
+  float eta[COUNT];
+};
+
+template <int N, int L = 1, int BASE = 0>
+__device__ __forceinline__ void load_twiddles(TwPlain<N>& tr, int t, const float4* __restrict__ tw) {
+  constexpr int T = N / 16;
+  constexpr int REM = N / L;
+  constexpr int R = REM >= 16 ? 16 : REM;
+  constexpr int U = 16 / R;
+  constexpr int TW_STRIDE = N / (R * L);
+  if constexpr (L > 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = (t + T * u) & (L - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float4 w = tw[s * r * TW_STRIDE];
+        tr.cs[BASE + u * (R - 1) + (r - 1)] = make_float2(w.x, w.y);
+        tr.eta[BASE + u * (R - 1) + (r - 1)] = w.z;
+      }
+    }
+  }
+  if constexpr (R != REM) {
+    constexpr int NEXT = BASE + (L > 1 ? U * (R - 1) : 0);
+    load_twiddles<N, L * R, NEXT>(tr, t, tw);
+  }
+}
+
+// forward stage (plain roots)
+template <int N, int R, int L, bool LAST, int BASE>
+__device__ __forceinline__ void pf_stage(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
+  constexpr int T = N / 16;
+  constexpr int U = 16 / R;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    float2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[u + U * r];
+    const int b = t + T * u;
+    const int s = b & (L - 1);
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tr.cs[BASE + u * (R - 1) + (r - 1)];
+        a[r] = pf_cmul(a[r], w.x, w.y);
+      }
+    }
+    pf_dft<R>(a);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[u + U * k] = a[k];
+    } else {
+      const int q = b / L;
+#pragma unroll
+      for (int k = 0; k < R; ++k) lds.at(q * R * L + s + L * k) = a[k];
+    }
+  }
+}
+
+// Forward length-N transform (positions t + T*m in and out), plain roots.
+template <int N, int L = 1, int BASE = 0>
+__device__ __forceinline__ void fwd_pass(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
+  constexpr int REM = N / L;
+  constexpr int R = REM >= 16 ? 16 : REM;
+  constexpr bool LAST = (R == REM);
+  constexpr int T = N / 16;
+  pf_stage<N, R, L, LAST, BASE>(v, lds, t, tr);
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = lds.at(t + T * m);
+    __syncthreads();
+    constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
+    fwd_pass<N, L * R, NEXT>(v, lds, t, tr);
+  }
+}
+
+// Inverse stage: the forward stage's outputs (from LDS, or the registers for the last stage)
+// through the exact inverse butterfly and inverse roots, into registers {u + U r}.
+template <int N, int R, int L, bool LAST, int BASE>
+__device__ __forceinline__ void pi_stage(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
+  constexpr int T = N / 16;
+  constexpr int U = 16 / R;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    float2 a[R];
+    const int b = t + T * u;
+    const int s = b & (L - 1);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) a[k] = v[u + U * k];
+    } else {
+      const int q = b / L;
+#pragma unroll
+      for (int k = 0; k < R; ++k) a[k] = lds.at(q * R * L + s + L * k);
+    }
+    pi_dft<R>(a);
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tr.cs[BASE + u * (R - 1) + (r - 1)];
+        a[r] = pi_cmul(a[r], w.x, w.y, tr.eta[BASE + u * (R - 1) + (r - 1)]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[u + U * r] = a[r];
+  }
+}
+
+// Exact inverse of fwd_pass, times N: the stages undone in reverse order.  All threads of the
+// workgroup call it; on return every LDS read is complete.
+template <int N, int L = 1, int BASE = 0>
+__device__ __forceinline__ void inv_pass(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
+  constexpr int REM = N / L;
+  constexpr int R = REM >= 16 ? 16 : REM;
+  constexpr bool LAST = (R == REM);
+  constexpr int T = N / 16;
+  if constexpr (LAST) {
+    pi_stage<N, R, L, true, BASE>(v, lds, t, tr);
+  } else {
+    constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
+    inv_pass<N, L * R, NEXT>(v, lds, t, tr);
+    // undo "read positions t + T m from LDS", then this stage
+#pragma unroll
+    for (int m = 0; m < 16; ++m) lds.at(t + T * m) = v[m];
+    __syncthreads();
+    pi_stage<N, R, L, false, BASE>(v, lds, t, tr);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Lane pairs: lanes 2j and 2j+1 hold the two spinor components of the same positions.  The
 // partner's value comes over the DPP quad permutation [1,0,3,2] (no LDS traffic, no barrier).
 // ---------------------------------------------------------------------------------------------

@@ -134,14 +134,14 @@ __global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
   float2 v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = p[2 * (t + T * m)];
-  TwRegs<N> tr;
+  TwPlain<N> tr;
   load_twiddles<N>(tr, t, a.tw);
 
   if constexpr (MODE == ROW_FWD) {
-    fft_pass<N, -1>(v, lds, t, tr);
+    fwd_pass<N>(v, lds, t, tr);
   } else {
     const float s = row_scale(a);
-    fft_pass<N, +1>(v, lds, t, tr);
+    inv_pass<N>(v, lds, t, tr);
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = vscale(v[m], s);
     if constexpr (MODE == ROW_STEP) {
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
         const float2 o = pair_swap(v[m]);
         v[m] = apply_r<IMAG, FULL>(v[m], o, hv, hbx, c);
       }
-      fft_pass<N, -1>(v, lds, t, tr);
+      fwd_pass<N>(v, lds, t, tr);
     }
   }
 #pragma unroll

@@ -24,7 +24,7 @@ struct RowArgs {
   float4* psi;           // [ny][nx] state, in place
   int nx, ny;
   int rows_per_block;
-  const float4* tw;      // forward roots of length nx, {re_hi, im_hi, re_lo, im_lo}
+  const float4* tw;      // roots exp(-2 pi i j / nx) as {cos, sin, eta, 0} (fp32-rounded, see fwd_pass)
   // scale applied after the inverse transform: either `scale`, or computed from partials
   float scale;
   const double* partials;  // NULL => use `scale`
@@ -43,7 +43,7 @@ struct ColArgs {
   float4* psi;
   int nx, ny;
   int cols;                  // columns per workgroup
-  const float4* tw;          // forward roots of length ny
+  const float4* tw;          // roots exp(-2 pi i j / ny) as {cos, sin, eta, 0}
   const float4* kx_tab;      // per k_x: {d11, d12} {d21, d22} as complex (M'(k_x) - 1)
   const float2* ky_tab;      // per k_y: P(k_y) - 1
   double* partials;          // one double per workgroup (norm modes)
@@ -54,8 +54,8 @@ struct EnergyArgs {
   float4* scratch;
   int nx, ny;
   int rows_per_block, cols;
-  const float4* twx;
-  const float4* twy;
+  const float4* twx;         // compensated roots {re_hi, im_hi, re_lo, im_lo}, length nx
+  const float4* twy;         // the same, length ny
   double xmin, dx, ymin, dy;
   double wx2h, wy2h;         // wx^2/2, wy^2/2
   double delta, g_uu, g_dd, g_ud;
