@@ -284,35 +284,39 @@ __device__ __forceinline__ void fft_pass(V (&v)[16], const LdsView<V>& lds, int 
 // textbook inverse (conjugate roots), the round trip is not the identity: |w~| != 1 scales every
 // butterfly path and that same map is re-applied every step (a coherent drift).  Here the inverse
 // instead undoes the forward stage by stage in reverse order: each small DFT by its conjugate
-// structure and each rounded root by conj(w~) (1 + eta) with 1 + eta = 1/|w~|^2 held in fp32.
-// The pair is then an exact inverse in exact arithmetic, the round trip carries only random
-// rounding, and the rounded roots enter the split step only through commutators with the step's
-// operators, O(dt eps) per step.  The forward costs 4 instructions per complex product instead
-// of 8 for a compensated one, the inverse 6.
+// structure and each rounded root by v = conj(w~) / |w~|^2.  v is held as conj(w~) plus a low part
+// conj(w~) eta (eta = 1/|w~|^2 - 1, about 1e-8) that enters the fma chain of the product before
+// the large terms, so every result is rounded once from the exact product.  (Scaling a rounded
+// product by 1 + eta afterwards does not work: eta is below half an ulp and the rounding drops
+// it, the same way every step.)  The pair is then an exact inverse in exact arithmetic, the round
+// trip carries only unbiased rounding, and the rounded roots enter the split step only through
+// commutators with the step's operators, O(dt eps) per step.  The forward costs 4 instructions
+// per complex product instead of 8 for a compensated one; the inverse costs 8.
 // ---------------------------------------------------------------------------------------------
 #define SGPE_P_R2 0.70710676908493042f       // fp32(1/sqrt(2))
-#define SGPE_P_R2_ETA 3.42285418e-08f        // 1/(2 r2^2) - 1 for the fp32 r2
+#define SGPE_P_R2_LO 2.42032350e-08f         // r2 (1/(2 r2^2) - 1) for the fp32 r2
 #define SGPE_P_C8 0.92387950420379639f       // fp32(cos(pi/8))
 #define SGPE_P_S8 0.38268342614173889f       // fp32(sin(pi/8))
-#define SGPE_P_8_ETA 5.70685721e-08f         // 1/(c8^2 + s8^2) - 1 for the fp32 pair
+#define SGPE_P_C8_LO 5.27244843e-08f         // c8 eta8, eta8 = 1/(c8^2 + s8^2) - 1 for the pair
+#define SGPE_P_S8_LO 2.18391971e-08f         // s8 eta8
 
 __device__ __forceinline__ float2 pf_rot90(float2 a) { return make_float2(a.y, -a.x); }   // * (-i)
 __device__ __forceinline__ float2 pi_rot90(float2 a) { return make_float2(-a.y, a.x); }   // * (+i)
-// * r2 (1 - i) and its exact inverse * r2 (1 + i) (1 + eta)
+// * r2 (1 - i) and its exact inverse * (1 + i) / (2 r2)
 __device__ __forceinline__ float2 pf_rot45(float2 a) {
   return make_float2(SGPE_P_R2 * (a.x + a.y), SGPE_P_R2 * (a.y - a.x));
 }
 __device__ __forceinline__ float2 pi_rot45(float2 a) {
-  const float ur = SGPE_P_R2 * (a.x - a.y), ui = SGPE_P_R2 * (a.x + a.y);
-  return make_float2(fmaf(ur, SGPE_P_R2_ETA, ur), fmaf(ui, SGPE_P_R2_ETA, ui));
+  const float d = a.x - a.y, e = a.x + a.y;
+  return make_float2(fmaf(d, SGPE_P_R2, d * SGPE_P_R2_LO), fmaf(e, SGPE_P_R2, e * SGPE_P_R2_LO));
 }
-// * (c - i s) and its exact inverse * (c + i s) (1 + eta)
+// * (c - i s) and its exact inverse * ((c + lx) + i (s + ly)), (lx, ly) = (c, s) eta
 __device__ __forceinline__ float2 pf_cmul(float2 a, float c, float s) {
   return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -a.x * s));
 }
-__device__ __forceinline__ float2 pi_cmul(float2 a, float c, float s, float eta) {
-  const float ur = fmaf(a.x, c, -a.y * s), ui = fmaf(a.y, c, a.x * s);
-  return make_float2(fmaf(ur, eta, ur), fmaf(ui, eta, ui));
+__device__ __forceinline__ float2 pi_cmul(float2 a, float c, float s, float lx, float ly) {
+  return make_float2(fmaf(a.x, c, fmaf(-a.y, s, fmaf(a.x, lx, -a.y * ly))),
+                     fmaf(a.y, c, fmaf(a.x, s, fmaf(a.y, lx, a.x * ly))));
 }
 
 // forward small DFTs (sign -1)
@@ -394,15 +398,15 @@ __device__ __forceinline__ void pi_dft16(float2 (&a)[16]) {
     for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = a[k2 + 4 * k1];
 #pragma unroll
   for (int k2 = 0; k2 < 4; ++k2) pi_dft4(t[4 * k2], t[4 * k2 + 1], t[4 * k2 + 2], t[4 * k2 + 3]);
-  t[5] = pi_cmul(t[5], SGPE_P_C8, SGPE_P_S8, SGPE_P_8_ETA);
+  t[5] = pi_cmul(t[5], SGPE_P_C8, SGPE_P_S8, SGPE_P_C8_LO, SGPE_P_S8_LO);
   t[9] = pi_rot45(t[9]);
-  t[13] = pi_cmul(t[13], SGPE_P_S8, SGPE_P_C8, SGPE_P_8_ETA);
+  t[13] = pi_cmul(t[13], SGPE_P_S8, SGPE_P_C8, SGPE_P_S8_LO, SGPE_P_C8_LO);
   t[6] = pi_rot45(t[6]);
   t[10] = pi_rot90(t[10]);
   t[14] = pi_rot45(pi_rot90(t[14]));
-  t[7] = pi_cmul(t[7], SGPE_P_S8, SGPE_P_C8, SGPE_P_8_ETA);
+  t[7] = pi_cmul(t[7], SGPE_P_S8, SGPE_P_C8, SGPE_P_S8_LO, SGPE_P_C8_LO);
   t[11] = pi_rot45(pi_rot90(t[11]));
-  t[15] = vneg(pi_cmul(t[15], SGPE_P_C8, SGPE_P_S8, SGPE_P_8_ETA));
+  t[15] = vneg(pi_cmul(t[15], SGPE_P_C8, SGPE_P_S8, SGPE_P_C8_LO, SGPE_P_S8_LO));
 #pragma unroll
   for (int r1 = 0; r1 < 4; ++r1) pi_dft4(t[r1], t[r1 + 4], t[r1 + 8], t[r1 + 12]);
 #pragma unroll
@@ -440,13 +444,14 @@ __device__ __forceinline__ void pi_dft(float2 (&a)[R]) {
   }
 }
 
-// Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and the modulus
-// correction eta; table entries are float4 {cos, sin, eta, 0} of exp(-2 pi i j / N).
+// Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and the low part
+// (cos, sin) eta of its exact inverse; table entries are float4 {cos, sin, cos eta, sin eta} of
+// exp(-2 pi i j / N).
 template <int N>
 struct TwPlain {
   static constexpr int COUNT = tw_count<N>() > 0 ? tw_count<N>() : 1;
   float2 cs[COUNT];
-  float eta[COUNT];
+  float2 lo[COUNT];
 };
 
 template <int N, int L = 1, int BASE = 0>
@@ -464,7 +469,7 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N>& tr, int t, const float
       for (int r = 1; r < R; ++r) {
         const float4 w = tw[s * r * TW_STRIDE];
         tr.cs[BASE + u * (R - 1) + (r - 1)] = make_float2(w.x, w.y);
-        tr.eta[BASE + u * (R - 1) + (r - 1)] = w.z;
+        tr.lo[BASE + u * (R - 1) + (r - 1)] = make_float2(w.z, w.w);
       }
     }
   }
@@ -547,7 +552,8 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[16], const LdsView<float2>&
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const float2 w = tr.cs[BASE + u * (R - 1) + (r - 1)];
-        a[r] = pi_cmul(a[r], w.x, w.y, tr.eta[BASE + u * (R - 1) + (r - 1)]);
+        const float2 l = tr.lo[BASE + u * (R - 1) + (r - 1)];
+        a[r] = pi_cmul(a[r], w.x, w.y, l.x, l.y);
       }
     }
 #pragma unroll

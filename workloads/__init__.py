@@ -74,6 +74,9 @@ PRESETS = {
     # The same physics at 1024^2: the split-step throughput workload.
     "metric_1024": Params(nx=1024, ny=1024, g_uu=10.0, g_dd=10.0, g_ud=10.0, k_l=2.0,
                           omega=1.0, delta=0.2, dt=5e-4),
+    # Ground-state time-to-solution: the 1024^2 physics at 256^2, imaginary-time step 1e-3.
+    "ground_256": Params(nx=256, ny=256, g_uu=10.0, g_dd=10.0, g_ud=10.0, k_l=2.0,
+                         omega=1.0, delta=0.2, dt=1e-3),
     # Large ground state: 2048^2 imaginary time, Omega(x) = 2 tanh(x/4) in real space, g = 50,
     # trap aspect ratio 1.5 (wx = 1, wy = 1.5); k_L = 2 and delta = 0 (not fixed by the
     # configuration); dt = 1e-3.
