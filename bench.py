@@ -5,12 +5,14 @@
 Workload: 1024 x 1024 grid, two components, complex64 state resident in HBM; g_uu = g_dd = g_ud
 = 10, k_L = 2, uniform Raman Omega = 1, detuning 0.2, harmonic trap, Thomas-Fermi start (seed 0).
 A step is one imaginary-time Strang step K(dt/2) R(dt) K(dt/2) with renormalisation (every stage of
-the hot path); real-time steps are reported beside it.  K steps are timed in batches of 100
-(one step_imag(100) call each) with HIP events; value = K / total time.
+the hot path), dt = 1e-3; real-time steps (dt = 5e-4) are reported beside it.  K steps are timed
+in batches of 100 (one step_imag(100) call each) with HIP events; value = K / total time.
 
-Prints one JSON line.  Also reports the dominant kernel's HBM roofline fraction (algorithmic
-bytes over its mean launch time, measured with HIP events around every launch) and the FP64
-oracle's throughput on a bounded sample of the same workload on the host cores.
+Prints one JSON line.  Also reports: the dominant kernel's HBM roofline fraction (algorithmic bytes
+over its mean launch time, from back-to-back launches between HIP events on the solver's stream);
+the same physics at 512^2 and 2048^2; the ground-state time-to-solution (wall time until the
+energy is within 1e-6 of the FP64 oracle's converged value, 256^2); and the FP64 oracle's
+throughput on a bounded sample of the 1024^2 workload on the host cores.
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_POINT_PASS = 32      # one pass reads and writes both complex64 components
 BYTES_PER_POINT_STEP = 64      # two passes per step
+IMAG_DT = 1e-3                 # imaginary-time step of the throughput workload
 
 
 def median_mad(xs):
@@ -70,6 +73,60 @@ def cpu_baseline(p, psi0, seconds):
                       f"({el:.1f} s, scipy.fft workers={cores})"}
 
 
+def other_grids(torch, stream, timed, p, steps=500, warmup=50):
+    """The same physics at 512^2 and 2048^2: imaginary-time split-steps/s (dt = 1e-3) and the
+    HBM roofline fraction on B_alg."""
+    from paper_2010_15069_amd import Solver
+    from workloads import initial_state
+    res = {}
+    for n in (512, 2048):
+        q = p.replace(nx=n, ny=n, dt=IMAG_DT)
+        s = Solver(q, stream=stream.cuda_stream)
+        s.set_psi(initial_state(q, "tf", seed=0))
+        s.step_imag(warmup)
+        total_ms, per = timed(s.step_imag, steps, 100)
+        v = steps / (total_ms * 1e-3)
+        res[f"{n}x{n}"] = {"split_steps_per_s": v, "step_ms_median": median_mad(per)[0],
+                           "hbm_roofline_frac": BYTES_PER_POINT_STEP * n * n * v / (HBM_PEAK_GBS * 1e9)}
+        s.close()
+    return res
+
+
+def ground_state_time(torch, stream, check_every=50, max_steps=200000):
+    """Wall time from set_psi (Thomas-Fermi start) until the energy is within 1e-6 (relative) of
+    the FP64 oracle's converged imaginary-time energy for the same workload and time step
+    (tests/golden/ground_energy.json); the energy is checked every `check_every` steps and the
+    checks are inside the timed region."""
+    from paper_2010_15069_amd import Solver
+    from workloads import initial_state, preset
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "ground_energy.json")))
+    name = ref["workload"]
+    p = preset(name)
+    psi0 = initial_state(p, "tf", seed=0)
+    e_ref = float(ref["energy"])
+    s = Solver(p, stream=stream.cuda_stream)
+    s.set_psi(psi0)                      # warm-up of the code paths, then the timed run
+    s.step_imag(check_every)
+    s.energy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_psi(psi0)
+    steps, e = 0, None
+    while steps < max_steps:
+        s.step_imag(check_every)
+        steps += check_every
+        e = s.energy()
+        if abs(e - e_ref) <= 1e-6 * abs(e_ref):
+            break
+    el = time.perf_counter() - t0
+    s.close()
+    return {"workload": f"{name}: {p.nx}x{p.ny} x 2 components, g=10 (all), k_L=2, Omega=1, "
+                        f"delta=0.2, harmonic trap, imaginary-time dt={p.dt}, Thomas-Fermi start",
+            "time_to_1e-6_s": el, "steps": steps, "energy": e, "energy_ref": e_ref,
+            "rel_error": abs(e - e_ref) / abs(e_ref), "check_every": check_every,
+            "reached": abs(e - e_ref) <= 1e-6 * abs(e_ref)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +135,8 @@ def main():
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ground", action="store_true", help="skip the ground-state time-to-solution")
+    ap.add_argument("--no-other-grids", action="store_true", help="skip the 512^2 and 2048^2 lines")
     ap.add_argument("--workload", default="metric_1024")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the HBM "
@@ -104,13 +163,15 @@ def main():
     from paper_2010_15069_amd import Solver
     from workloads import initial_state, preset
 
-    p = preset(args.workload)
-    psi0 = initial_state(p, "tf", seed=0)
+    p = preset(args.workload)                 # real time: dt = 5e-4
+    p_imag = p.replace(dt=IMAG_DT)            # imaginary time: dt = 1e-3
+    psi0 = initial_state(p, "tf", seed=0)     # the start does not depend on dt
     npts = p.nx * p.ny
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    s = Solver(p, stream=stream.cuda_stream)
+    s = Solver(p_imag, stream=stream.cuda_stream)
     s.set_psi(psi0)
+    s_real = Solver(p, stream=stream.cuda_stream)
 
     def timed(step, k, batch):
         sizes = [min(batch, k - i) for i in range(0, k, batch)]
@@ -133,14 +194,23 @@ def main():
     e_final = s.energy()
 
     # real time, same workload
-    s.set_psi(psi0)
-    s.step_real(args.warmup)
-    total_r, per_r = timed(s.step_real, args.steps, args.batch)
+    s_real.set_psi(psi0)
+    s_real.step_real(args.warmup)
+    total_r, per_r = timed(s_real.step_real, args.steps, args.batch)
     med_r, mad_r = median_mad(per_r)
+    s_real.close()
 
-    # per-kernel launch times (HIP events around every launch) -> roofline of the dominant kernel
+    # Dominant kernel's launch duration in the real (alternating) schedule: the timed region gives
+    # the step time; HIP events around every launch of 200 further steps split it between the two
+    # passes (the events add the same small overhead to both).  Same-pass back-to-back launches
+    # are reported beside it: there each XCD re-reads its own output from L2.
+    step_ms = total_ms / args.steps
     s.set_psi(psi0)
-    row_ms, col_ms = s.profile_steps(200, imag=True)
+    s.step_imag(20)
+    ev_row, ev_col = s.profile_steps(200, imag=True)
+    row_ms = step_ms * ev_row / (ev_row + ev_col)
+    col_ms = step_ms * ev_col / (ev_row + ev_col)
+    b2b_row, b2b_col = s.profile_kernels(200, imag=True)
     dom_name, dom_ms = ("col_pass", col_ms) if col_ms >= row_ms else ("row_pass", row_ms)
     alg_bytes = BYTES_PER_POINT_PASS * npts
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
@@ -163,21 +233,30 @@ def main():
             "workload": f"{args.workload}: {p.nx}x{p.ny} grid x 2 components, complex64 state, "
                         f"imaginary-time Strang split steps with renormalisation, g=10 (all), k_L=2, "
                         f"Omega=1 (k-space), delta=0.2, harmonic trap, Thomas-Fermi start",
-            "grid": [p.ny, p.nx], "components": 2, "dt": p.dt, "batch": args.batch,
+            "grid": [p.ny, p.nx], "components": 2, "dt": p_imag.dt, "dt_real": p.dt,
+            "batch": args.batch,
         },
         "step_ms_median": med, "step_ms_mad": mad,
         "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts * value / (HBM_PEAK_GBS * 1e9),
         "real_time": {"value": args.steps / (total_r * 1e-3), "unit": "split-steps/s",
                       "step_ms_median": med_r, "step_ms_mad": mad_r},
-        "kernels_ms": {"row_pass": row_ms, "col_pass": col_ms},
+        "kernels_ms": {"row_pass": row_ms, "col_pass": col_ms,
+                       "method": "imaginary-time step time split by per-launch HIP event means"},
+        "kernels_back_to_back_ms": {"row_pass": b2b_row, "col_pass": b2b_col},
         "energy_after_timed_steps": e_final,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_detail": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "launch_ms": dom_ms},
     }
+    s.close()
+    if not args.no_other_grids:
+        out["other_grids"] = other_grids(torch, stream, timed, p)
+    if not args.no_ground:
+        out["ground_state"] = ground_state_time(torch, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds)
-    s.close()
     print(json.dumps(out), flush=True)
 
 

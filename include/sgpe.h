@@ -121,6 +121,15 @@ sgpe_status sgpe_synchronize(sgpe_ctx* ctx);
 sgpe_status sgpe_profile_steps(sgpe_ctx* ctx, int32_t imag, int64_t n,
                                double* row_ms, double* col_ms);
 
+/* Measurement helper: mean duration in milliseconds of one steady-state row-pass launch and
+ * one column-pass launch (real time: imag = 0; imaginary time: imag = 1), each from n launches
+ * issued back to back between one HIP event pair -- the per-kernel figure a kernel-trace
+ * profiler reports.  The launches work on a copy of the state in the mixed representation; the
+ * state is restored afterwards, so a caller sees no change.  Allocates the state-sized scratch
+ * buffer on first use.  Synchronises.  Either output pointer may be NULL. */
+sgpe_status sgpe_profile_kernels(sgpe_ctx* ctx, int32_t imag, int64_t n,
+                                 double* row_ms, double* col_ms);
+
 /* Static description of a status code.  Never NULL. */
 const char* sgpe_strerror(sgpe_status s);
 

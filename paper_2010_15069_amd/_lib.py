@@ -47,7 +47,7 @@ _LIB = None
 EXPORTS = [
     "sgpe_validate_params", "sgpe_device_count", "sgpe_create", "sgpe_destroy", "sgpe_set_psi",
     "sgpe_get_psi", "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
-    "sgpe_synchronize", "sgpe_profile_steps", "sgpe_strerror", "sgpe_set_col_tile",
+    "sgpe_synchronize", "sgpe_profile_steps", "sgpe_profile_kernels", "sgpe_strerror", "sgpe_set_col_tile",
 ]
 
 
@@ -100,6 +100,9 @@ def _lib():
     lib.sgpe_profile_steps.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double),
                                        P(ctypes.c_double)]
     lib.sgpe_profile_steps.restype = st
+    lib.sgpe_profile_kernels.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double),
+                                         P(ctypes.c_double)]
+    lib.sgpe_profile_kernels.restype = st
     lib.sgpe_strerror.argtypes = [ctypes.c_int]
     lib.sgpe_strerror.restype = ctypes.c_char_p
     lib.sgpe_set_col_tile.argtypes = [vp, ctypes.c_int32]

@@ -593,4 +593,57 @@ sgpe_status sgpe_profile_steps(sgpe_ctx* c, int32_t imag, int64_t n, double* row
   return SGPE_OK;
 }
 
+sgpe_status sgpe_profile_kernels(sgpe_ctx* c, int32_t imag, int64_t n, double* row_ms, double* col_ms) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (n <= 0) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const sgpe_params& p = c->p;
+  const size_t bytes = size_t(p.nx) * size_t(p.ny) * sizeof(float4);
+  if (!c->scratch) {
+    void* ptr = nullptr;
+    if ((st = dev_alloc(c, &ptr, bytes)) != SGPE_OK) return st;
+    c->scratch = static_cast<float4*>(ptr);
+  }
+  hipEvent_t ev[4];
+  int made = 0;
+  for (; made < 4; ++made) {
+    if (hipEventCreate(&ev[made]) != hipSuccess) break;
+  }
+  hipStream_t s = c->stream;
+  hipError_t e = made == 4 ? hipSuccess : hipErrorOutOfMemory;
+  // keep the state; enter the mixed representation with valid norm partials
+  if (e == hipSuccess) e = hipMemcpyAsync(c->scratch, c->psi, bytes, hipMemcpyDeviceToDevice, s);
+  RowArgs ra = row_args(c);
+  if (e == hipSuccess) e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, s);
+  const int steady_norm = imag ? sgpe::NORM_DOT : sgpe::NORM_NONE;
+  if (e == hipSuccess) e = sgpe::launch_col(col_args(c, imag != 0, true), sgpe::NORM_DOT, s);
+  RowArgs r = ra;
+  r.scale = float(1.0 / (double(p.nx) * double(p.ny)));
+  if (imag) {
+    r.partials = c->partials;
+    r.n_partials = p.nx / c->cols;
+  }
+  const ColArgs ca = col_args(c, imag != 0, false);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+  for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = sgpe::launch_row(r, sgpe::ROW_STEP, imag != 0, c->full2x2, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+  for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = sgpe::launch_col(ca, steady_norm, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->psi, c->scratch, bytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  float a = 0.f, b = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2], ev[3]);
+  for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return status_of(e);
+  }
+  if (row_ms) *row_ms = double(a) / double(n);
+  if (col_ms) *col_ms = double(b) / double(n);
+  return c->latched;
+}
+
 }  // extern "C"

@@ -37,14 +37,17 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
   const int t = pair / C;
   const int tile = col_tile(blockIdx.x, a.nx / C);
   const int x = tile * C + cc;
-  const LdsView<float2> lds{lds_raw + 2 * cc + comp, 2 * C};
-  // element (row y) of this lane's component is p[2 * y * nx]
-  float2* __restrict__ p = reinterpret_cast<float2*>(a.psi + x) + comp;
-  const size_t rs = 2 * size_t(a.nx);
+  const LdsView<float2> lds{lds_raw + 2 * cc + comp, 1 + __builtin_ctz(C)};
+  // element (row y) of this lane's component is at byte offset 16 (y nx + x) + 8 comp; 32-bit
+  // offsets from a wave-uniform base, the row stride a wave-uniform value
+  const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
+  const uint32_t rstride = 16u * static_cast<uint32_t>(a.nx);
+  const uint32_t off0 = static_cast<uint32_t>(t) * rstride + 16u * static_cast<uint32_t>(x) + 8u * comp;
+  const uint32_t mstride = static_cast<uint32_t>(T) * rstride;
 
   float2 v[16];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = p[size_t(t + T * m) * rs];
+  for (int m = 0; m < 16; ++m) v[m] = *reinterpret_cast<const float2*>(base + off0 + mstride * m);
   TwPlain<N> tr;
   load_twiddles<N>(tr, t, a.tw);
   // this component's row of M' - 1 at k_x: {d_own, d_other}
@@ -57,7 +60,7 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
   for (int m = 0; m < 16; ++m) {
     const float2 w = v[m];
     const float2 o = pair_swap(w);
-    const float2 q = a.ky_tab[t + T * m];
+    const float2 q = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.ky_tab) + 8u * static_cast<uint32_t>(t + T * m));
     const float c1r = fmaf(-d.w, o.y, fmaf(d.z, o.x, fmaf(-d.y, w.y, d.x * w.x)));
     const float c1i = fmaf(d.w, o.x, fmaf(d.z, o.y, fmaf(d.y, w.x, d.x * w.y)));
     const float cr = fmaf(-q.y, w.y, fmaf(q.x, w.x, fmaf(-q.y, c1i, fmaf(q.x, c1r, c1r))));
@@ -77,8 +80,9 @@ __global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
 
   inv_pass<N>(v, lds, t, tr);
 
+  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
 #pragma unroll
-  for (int m = 0; m < 16; ++m) p[size_t(t + T * m) * rs] = v[m];
+  for (int m = 0; m < 16; ++m) *reinterpret_cast<float2*>(out + off0 + mstride * m) = v[m];
 }
 
 // -------------------------------------------------------------------------------------------

@@ -184,8 +184,8 @@ __device__ __forceinline__ void dft(V (&a)[R]) {
 template <class V>
 struct LdsView {
   V* base;     // slot 0 of this thread's transform
-  int stride;  // number of interleaved transforms
-  __device__ __forceinline__ V& at(int pos) const { return base[(pos + (pos >> 4)) * stride]; }
+  int shift;   // log2 of the number of interleaved transforms (a power of two)
+  __device__ __forceinline__ V& at(int pos) const { return base[(pos + (pos >> 4)) << shift]; }
 };
 
 // Stage twiddles a thread needs for a length-N transform: the first stage (L = 1) needs none;
@@ -464,10 +464,11 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N>& tr, int t, const float
   if constexpr (L > 1) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int s = (t + T * u) & (L - 1);
+      // byte offset of root s r TW_STRIDE, 32-bit from the uniform table base
+      const uint32_t o = static_cast<uint32_t>((t + T * u) & (L - 1)) * (16u * TW_STRIDE);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float4 w = tw[s * r * TW_STRIDE];
+        const float4 w = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(tw) + o * r);
         tr.cs[BASE + u * (R - 1) + (r - 1)] = make_float2(w.x, w.y);
         tr.lo[BASE + u * (R - 1) + (r - 1)] = make_float2(w.z, w.w);
       }
@@ -510,8 +511,22 @@ __device__ __forceinline__ void pf_stage(float2 (&v)[16], const LdsView<float2>&
   }
 }
 
+// Ordering of the LDS exchanges between stages: a workgroup barrier, or -- when every transform
+// lies inside one wave (WSYNC) -- a wave-level fence: one wave's LDS operations complete in
+// issue order, so only the compiler's reordering has to be prevented.
+template <bool WSYNC>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WSYNC) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Forward length-N transform (positions t + T*m in and out), plain roots.
-template <int N, int L = 1, int BASE = 0>
+template <int N, bool WSYNC = false, int L = 1, int BASE = 0>
 __device__ __forceinline__ void fwd_pass(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= 16 ? 16 : REM;
@@ -519,12 +534,12 @@ __device__ __forceinline__ void fwd_pass(float2 (&v)[16], const LdsView<float2>&
   constexpr int T = N / 16;
   pf_stage<N, R, L, LAST, BASE>(v, lds, t, tr);
   if constexpr (!LAST) {
-    __syncthreads();
+    lds_sync<WSYNC>();
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = lds.at(t + T * m);
-    __syncthreads();
+    lds_sync<WSYNC>();
     constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
-    fwd_pass<N, L * R, NEXT>(v, lds, t, tr);
+    fwd_pass<N, WSYNC, L * R, NEXT>(v, lds, t, tr);
   }
 }
 
@@ -563,7 +578,7 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[16], const LdsView<float2>&
 
 // Exact inverse of fwd_pass, times N: the stages undone in reverse order.  All threads of the
 // workgroup call it; on return every LDS read is complete.
-template <int N, int L = 1, int BASE = 0>
+template <int N, bool WSYNC = false, int L = 1, int BASE = 0>
 __device__ __forceinline__ void inv_pass(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= 16 ? 16 : REM;
@@ -573,13 +588,13 @@ __device__ __forceinline__ void inv_pass(float2 (&v)[16], const LdsView<float2>&
     pi_stage<N, R, L, true, BASE>(v, lds, t, tr);
   } else {
     constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
-    inv_pass<N, L * R, NEXT>(v, lds, t, tr);
+    inv_pass<N, WSYNC, L * R, NEXT>(v, lds, t, tr);
     // undo "read positions t + T m from LDS", then this stage
 #pragma unroll
     for (int m = 0; m < 16; ++m) lds.at(t + T * m) = v[m];
-    __syncthreads();
+    lds_sync<WSYNC>();
     pi_stage<N, R, L, false, BASE>(v, lds, t, tr);
-    __syncthreads();
+    lds_sync<WSYNC>();
   }
 }
 
@@ -641,10 +656,22 @@ __device__ __forceinline__ SinCosM1 sincos_m1_small(float phi) {
 }
 
 __device__ __forceinline__ SinCosM1 sincos_m1(float phi) {
-  // The branch is uniform in the common case (every phase of the wave below pi/4).
   if (fabsf(phi) <= 0.785398163f) return sincos_m1_small(phi);
   return sincos_m1_reduced(phi);
 }
+
+// The same with the routine fixed at compile time: SMALL requires |phi| <= pi/4; the reduced
+// routine is exact for every phi.  Kernels pick one per wave (see wave_all), so a wave runs one
+// straight-line routine instead of both paths under an execution mask.
+template <bool SMALL>
+__device__ __forceinline__ SinCosM1 sincos_m1_t(float phi) {
+  if constexpr (SMALL) return sincos_m1_small(phi);
+  else return sincos_m1_reduced(phi);
+}
+constexpr float kSmallPhase = 0.785398163f;   // pi/4
+
+// True in every lane iff p holds in every active lane of the wave (a wave-uniform value).
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
 
 // ---------------------------------------------------------------------------------------------
 // Deterministic reductions in fp64.

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   const int rloc = tid / T;
   const int t = tid - rloc * T;
   const int row = blockIdx.x * a.rows_per_block + rloc;
-  const LdsView<float4> lds{lds_raw + rloc * SLOTS, 1};
+  const LdsView<float4> lds{lds_raw + rloc * SLOTS, 0};
   const float4* __restrict__ p = a.psi + size_t(row) * N;
   float4 v[16];
 #pragma unroll
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
   const int c = tid & (C - 1);
   const int t = tid / C;
   const int x = blockIdx.x * C + c;
-  const LdsView<float4> lds{lds_raw + c, C};
+  const LdsView<float4> lds{lds_raw + c, __builtin_ctz(C)};
   const float4* __restrict__ p = a.scratch + x;
   const size_t rs = size_t(a.nx);
   float4 v[16];

@@ -45,9 +45,9 @@ __device__ __forceinline__ float row_scale(const RowArgs& a) {
 }
 
 // -------------------------------------------------------------------------------------------
-// Real-space exponential R(h) (Eqs. (H2)-(H4), densities of the input), applied to this lane's
-// component w; o is the partner lane's component at the same point.  up = (this lane owns the
-// up component).  hv = h V(x, y); hbx = h Omega(x) / 2.
+// Real-space exponential R(h) (Eqs. (H2)-(H4), densities of the input).  Each lane applies its
+// component's row of the 2x2 exponential to its value w; o is the partner lane's value at the
+// same point.  hv = h V(x, y); hbx = h Omega(x) / 2.
 // -------------------------------------------------------------------------------------------
 struct RCoef {
   float hd_own;      // +- h delta / 2 for this component
@@ -57,65 +57,124 @@ struct RCoef {
   float hg_uu, hg_dd, hdelta2;
 };
 
-template <bool IMAG, bool FULL>
-__device__ __forceinline__ float2 apply_r(float2 w, float2 o, float hv, float hbx, const RCoef& c) {
-  const float n_own = fmaf(w.x, w.x, w.y * w.y);
-  const float n_oth = fmaf(o.x, o.x, o.y * o.y);
-  if constexpr (!FULL) {
-    const float ph = fmaf(c.hg_own, n_own, fmaf(c.hg_ud, n_oth, hv + c.hd_own));
-    if constexpr (!IMAG) {
-      // w * exp(-i ph) = w + w (cm1 - i s); the small correction is formed first.
-      const SinCosM1 sc = sincos_m1(ph);
-      return make_float2(w.x + fmaf(w.x, sc.cm1, w.y * sc.s), w.y + fmaf(w.y, sc.cm1, -w.x * sc.s));
-    } else {
-      return vscale(w, expf(-ph));
-    }
+// Diagonal R (no spatial Raman coupling): w exp(-ph) in imaginary time, w exp(-i ph) in real
+// time, with ph = h (V + g_own n_own + g_ud n_other +- delta/2).  The real-time form is
+// w + w (cm1 - i s), the small correction formed first.
+template <bool IMAG, bool SMALL>
+__device__ __forceinline__ float2 apply_r_diag(float2 w, float ph) {
+  if constexpr (!IMAG) {
+    const SinCosM1 sc = sincos_m1_t<SMALL>(ph);
+    return make_float2(w.x + fmaf(w.x, sc.cm1, w.y * sc.s), w.y + fmaf(w.y, sc.cm1, -w.x * sc.s));
   } else {
-    // H_R = A 1 + Bx sigma_x + Bz sigma_z (all times h); the up/down densities are
-    // (n_own, n_oth) or (n_oth, n_own).
-    const float nu = c.sgn > 0.0f ? n_own : n_oth;
-    const float nd = c.sgn > 0.0f ? n_oth : n_own;
-    const float gu = fmaf(c.hg_uu, nu, c.hg_ud * nd);
-    const float gd = fmaf(c.hg_dd, nd, c.hg_ud * nu);
-    const float ha = fmaf(0.5f, gu + gd, hv);
-    const float hbz = fmaf(0.5f, gu - gd, c.hdelta2);
-    const float th = sqrtf(fmaf(hbx, hbx, hbz * hbz));
-    if constexpr (!IMAG) {
-      // M = cos(th) 1 - i sin(th)/th (hB . sigma): this component's row of (M - 1) psi is
-      // cm1 w - i X with X = +-pz w + px o.
-      const SinCosM1 sb = sincos_m1(th);
-      const float px = sb.sinc * hbx, pz = c.sgn * sb.sinc * hbz;
-      const float xr = fmaf(pz, w.x, px * o.x), xi = fmaf(pz, w.y, px * o.y);
-      const float mr = fmaf(sb.cm1, w.x, xi), mi = fmaf(sb.cm1, w.y, -xr);
-      // E M psi - psi = c_M + (E - 1)(w + c_M), E - 1 = cm1_A - i s_A; added to w once.
-      const SinCosM1 se = sincos_m1(ha);
-      const float cr = fmaf(se.s, w.y, fmaf(se.cm1, w.x, fmaf(se.s, mi, fmaf(se.cm1, mr, mr))));
-      const float ci = fmaf(-se.s, w.x, fmaf(se.cm1, w.y, fmaf(-se.s, mr, fmaf(se.cm1, mi, mi))));
-      return make_float2(w.x + cr, w.y + ci);
+    return vscale(w, expf(-ph));
+  }
+}
+
+// Full 2x2 R: H_R = A 1 + Bx sigma_x + Bz sigma_z (all times h).  The angles (A, |B|) of this
+// point, for the wave's choice of routine.
+struct RFull {
+  float ha, hbz, th;
+};
+__device__ __forceinline__ RFull r_full_angles(float n_own, float n_oth, float hv, const RCoef& c, float hbx) {
+  const float nu = c.sgn > 0.0f ? n_own : n_oth;
+  const float nd = c.sgn > 0.0f ? n_oth : n_own;
+  const float gu = fmaf(c.hg_uu, nu, c.hg_ud * nd);
+  const float gd = fmaf(c.hg_dd, nd, c.hg_ud * nu);
+  RFull f;
+  f.ha = fmaf(0.5f, gu + gd, hv);
+  f.hbz = fmaf(0.5f, gu - gd, c.hdelta2);
+  f.th = sqrtf(fmaf(hbx, hbx, f.hbz * f.hbz));
+  return f;
+}
+// Whether the SMALL routines are valid for this point.
+template <bool IMAG>
+__device__ __forceinline__ bool r_full_small(const RFull& f) {
+  if constexpr (!IMAG) return fabsf(f.ha) <= kSmallPhase && f.th <= kSmallPhase;
+  else return f.th < 0.25f;
+}
+
+template <bool IMAG, bool SMALL>
+__device__ __forceinline__ float2 apply_r_full(float2 w, float2 o, const RFull& f, float hbx, float sgn) {
+  if constexpr (!IMAG) {
+    // M = cos(th) 1 - i sin(th)/th (hB . sigma): this component's row of (M - 1) psi is
+    // cm1 w - i X with X = +-pz w + px o.
+    const SinCosM1 sb = sincos_m1_t<SMALL>(f.th);
+    const float px = sb.sinc * hbx, pz = sgn * sb.sinc * f.hbz;
+    const float xr = fmaf(pz, w.x, px * o.x), xi = fmaf(pz, w.y, px * o.y);
+    const float mr = fmaf(sb.cm1, w.x, xi), mi = fmaf(sb.cm1, w.y, -xr);
+    // E M psi - psi = c_M + (E - 1)(w + c_M), E - 1 = cm1_A - i s_A; added to w once.
+    const SinCosM1 se = sincos_m1_t<SMALL>(f.ha);
+    const float cr = fmaf(se.s, w.y, fmaf(se.cm1, w.x, fmaf(se.s, mi, fmaf(se.cm1, mr, mr))));
+    const float ci = fmaf(-se.s, w.x, fmaf(se.cm1, w.y, fmaf(-se.s, mr, fmaf(se.cm1, mi, mi))));
+    return make_float2(w.x + cr, w.y + ci);
+  } else {
+    const float ea = expf(-f.ha);
+    float ch, shc;  // cosh(th), sinh(th)/th
+    if constexpr (SMALL) {
+      const float t2 = f.th * f.th;
+      ch = fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.48015873e-5f, 1.38888889e-3f), 4.16666667e-2f), 0.5f), 1.0f);
+      shc = fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.75573192e-6f, 1.98412698e-4f), 8.33333333e-3f),
+                           1.66666667e-1f), 1.0f);
     } else {
-      const float ea = expf(-ha);
-      float ch, shc;  // cosh(th), sinh(th)/th
-      if (th < 0.25f) {
-        const float t2 = th * th;
+      if (f.th < 0.25f) {
+        const float t2 = f.th * f.th;
         ch = fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.48015873e-5f, 1.38888889e-3f), 4.16666667e-2f), 0.5f), 1.0f);
         shc = fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.75573192e-6f, 1.98412698e-4f), 8.33333333e-3f),
                              1.66666667e-1f), 1.0f);
       } else {
-        const float ep = expf(th);
+        const float ep = expf(f.th);
         const float em = 1.0f / ep;
         ch = 0.5f * (ep + em);
-        shc = 0.5f * (ep - em) / th;
+        shc = 0.5f * (ep - em) / f.th;
       }
-      const float m_own = ea * fmaf(-c.sgn * shc, hbz, ch);
-      const float m_x = -ea * shc * hbx;
-      return make_float2(fmaf(m_own, w.x, m_x * o.x), fmaf(m_own, w.y, m_x * o.y));
     }
+    const float m_own = ea * fmaf(-sgn * shc, f.hbz, ch);
+    const float m_x = -ea * shc * hbx;
+    return make_float2(fmaf(m_own, w.x, m_x * o.x), fmaf(m_own, w.y, m_x * o.y));
   }
 }
 
 // -------------------------------------------------------------------------------------------
 // Row pass
 // -------------------------------------------------------------------------------------------
+// R on the thread's 16 points.  For each point index the wave takes one routine: the short one
+// when every lane's angles allow it (the common case), else the general one -- a wave-uniform
+// branch, so a wave never runs both.
+template <int N, bool IMAG, bool FULL>
+__device__ __forceinline__ void row_apply_r(float2 (&v)[16], const RowArgs& a, int row, int t, bool up) {
+  constexpr int T = N / 16;
+  RCoef c;
+  c.sgn = up ? 1.0f : -1.0f;
+  c.hd_own = up ? a.hdelta2 : -a.hdelta2;
+  c.hg_own = up ? a.hg_uu : a.hg_dd;
+  c.hg_ud = a.hg_ud;
+  c.hg_uu = a.hg_uu;
+  c.hg_dd = a.hg_dd;
+  c.hdelta2 = a.hdelta2;
+  const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
+  const float hvy = a.hvy * y * y;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int j = t + T * m;
+    const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
+    const float hv = fmaf(a.hvx * x, x, hvy);
+    const float n_own = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+    if constexpr (!FULL) {
+      const float n_oth = pair_swap(n_own);
+      const float ph = fmaf(c.hg_own, n_own, fmaf(c.hg_ud, n_oth, hv + c.hd_own));
+      if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) v[m] = apply_r_diag<IMAG, true>(v[m], ph);
+      else v[m] = apply_r_diag<IMAG, false>(v[m], ph);
+    } else {
+      const float hbx = a.hbx[j];
+      const float2 o = pair_swap(v[m]);
+      const float n_oth = fmaf(o.x, o.x, o.y * o.y);
+      const RFull f = r_full_angles(n_own, n_oth, hv, c, hbx);
+      if (wave_all(r_full_small<IMAG>(f))) v[m] = apply_r_full<IMAG, true>(v[m], o, f, hbx, c.sgn);
+      else v[m] = apply_r_full<IMAG, false>(v[m], o, f, hbx, c.sgn);
+    }
+  }
+}
+
 template <int N, int MODE, bool IMAG, bool FULL>
 __global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
   extern __shared__ float2 lds_raw[];
@@ -127,13 +186,15 @@ __global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
   const int rloc = pair / T;
   const int t = pair - rloc * T;
   const int row = blockIdx.x * a.rows_per_block + rloc;
-  const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 2};
-  // element `pos` of this lane's component is p[2 * pos]
-  float2* __restrict__ p = reinterpret_cast<float2*>(a.psi + size_t(row) * N) + comp;
+  const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
+  // element `pos` of this lane's component is at byte offset 16 pos from the row start; 32-bit
+  // offsets from a wave-uniform base
+  const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
+  const uint32_t off0 = (static_cast<uint32_t>(row) * N + static_cast<uint32_t>(t)) * 16u + 8u * comp;
 
   float2 v[16];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = p[2 * (t + T * m)];
+  for (int m = 0; m < 16; ++m) v[m] = *reinterpret_cast<const float2*>(base + off0 + 16u * T * m);
   TwPlain<N> tr;
   load_twiddles<N>(tr, t, a.tw);
 
@@ -145,31 +206,13 @@ __global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = vscale(v[m], s);
     if constexpr (MODE == ROW_STEP) {
-      const bool up = (comp == 0);
-      RCoef c;
-      c.sgn = up ? 1.0f : -1.0f;
-      c.hd_own = up ? a.hdelta2 : -a.hdelta2;
-      c.hg_own = up ? a.hg_uu : a.hg_dd;
-      c.hg_ud = a.hg_ud;
-      c.hg_uu = a.hg_uu;
-      c.hg_dd = a.hg_dd;
-      c.hdelta2 = a.hdelta2;
-      const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
-      const float hvy = a.hvy * y * y;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int j = t + T * m;
-        const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
-        const float hv = fmaf(a.hvx * x, x, hvy);
-        const float hbx = FULL ? a.hbx[j] : 0.0f;
-        const float2 o = pair_swap(v[m]);
-        v[m] = apply_r<IMAG, FULL>(v[m], o, hv, hbx, c);
-      }
+      row_apply_r<N, IMAG, FULL>(v, a, row, t, comp == 0);
       fwd_pass<N>(v, lds, t, tr);
     }
   }
+  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
 #pragma unroll
-  for (int m = 0; m < 16; ++m) p[2 * (t + T * m)] = v[m];
+  for (int m = 0; m < 16; ++m) *reinterpret_cast<float2*>(out + off0 + 16u * T * m) = v[m];
 }
 
 // -------------------------------------------------------------------------------------------

@@ -91,6 +91,14 @@ class Solver:
                                            ctypes.byref(c)), "sgpe_profile_steps")
         return r.value, c.value
 
+    def profile_kernels(self, n, imag=False):
+        """Mean milliseconds of one (row pass, column pass) launch, each from n back-to-back
+        launches; the state is left unchanged."""
+        r, c = ctypes.c_double(), ctypes.c_double()
+        check(self._lib.sgpe_profile_kernels(self._ctx, 1 if imag else 0, int(n), ctypes.byref(r),
+                                             ctypes.byref(c)), "sgpe_profile_kernels")
+        return r.value, c.value
+
     def set_col_tile(self, columns):
         check(self._lib.sgpe_set_col_tile(self._ctx, int(columns)), "sgpe_set_col_tile")
 

@@ -273,3 +273,22 @@ def test_real_time_norm_drift(Solver, variant):
         s.step_real(100)
         worst = max(worst, abs(s.norm() - n0) / n0)
     assert worst <= 1e-6, worst
+
+
+def test_ground_256_reaches_oracle_converged_energy(Solver):
+    # The time-to-solution workload: from the Thomas-Fermi start, imaginary-time relaxation on
+    # the GPU reaches the FP64 oracle's converged energy (stored by
+    # tests/golden/make_ground_energy.py) to 1e-6 relative, and stays there.  The oracle itself
+    # is within 1e-6 after 31000 steps and within 2e-8 after 40000.
+    import json
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ground_energy.json")))
+    p = preset(ref["workload"])
+    s = Solver(p).set_psi(initial_state(p, "tf", seed=0))
+    s.step_imag(40000)
+    e1 = s.energy()
+    s.step_imag(10000)
+    e2 = s.energy()
+    e_ref = float(ref["energy"])
+    assert abs(e1 - e_ref) <= 1e-6 * abs(e_ref), (e1, e_ref)
+    assert abs(e2 - e_ref) <= 1e-6 * abs(e_ref), (e2, e_ref)
+    assert abs(s.norm() - p.norm0) <= 1e-6 * p.norm0
