@@ -133,9 +133,36 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* ctx, int32_t imag, int64_t n,
 /* Static description of a status code.  Never NULL. */
 const char* sgpe_strerror(sgpe_status s);
 
-/* Tuning knob: columns per workgroup of the column pass (0 = default).  Values are powers of
- * two in [1, 8] subject to the device's LDS limit; an unsupported value returns SGPE_EINVAL. */
+/* Tuning knob: columns per column-pass workgroup, the rest of the schedule kept (prefetching
+ * is dropped if the new width does not allow it).  0 restores the whole default schedule.  An
+ * unsupported value returns SGPE_EINVAL and changes nothing.  See sgpe_schedule. */
 sgpe_status sgpe_set_col_tile(sgpe_ctx* ctx, int32_t columns);
+
+/* Launch schedule of the two passes -- how the work is cut into lanes and workgroups.  It does
+ * not change the arithmetic of any point: real-time results are bit-identical under every valid
+ * schedule; imaginary-time results differ only in the grouping of the fp64 norm partials.
+ *   col_tile    columns per column-pass workgroup (power of two)
+ *   row_iters   row groups per row-pass workgroup, 1 or 2: with 2, the next group's data is loaded
+ *               while the current one is transformed (16 points per lane, <= 256 threads)
+ *   col_iters   the same for column tiles
+ *   row_points  points per lane of the x transforms: 16, or 8 / 4 when nx <= 1024
+ *   col_points  the same for the y transforms and ny
+ * A workgroup has 2 * lines * (n / points) threads, at most 512 (256 when prefetching), and its
+ * LDS must fit the device. */
+typedef struct {
+  int32_t col_tile;
+  int32_t row_iters;
+  int32_t col_iters;
+  int32_t row_points;
+  int32_t col_points;
+} sgpe_schedule;
+
+/* The schedule in use.  SGPE_EINVAL if either pointer is NULL. */
+sgpe_status sgpe_get_schedule(sgpe_ctx* ctx, sgpe_schedule* out);
+
+/* Set the schedule; NULL restores the default (chosen from the grid size and the device's
+ * compute-unit count).  An unsupported schedule returns SGPE_EINVAL and changes nothing. */
+sgpe_status sgpe_set_schedule(sgpe_ctx* ctx, const sgpe_schedule* schedule);
 
 #ifdef __cplusplus
 }

@@ -35,6 +35,13 @@ class SgpeParams(ctypes.Structure):
         return out
 
 
+class Schedule(ctypes.Structure):
+    """sgpe_schedule: launch schedule of the two passes (see include/sgpe.h)."""
+    _fields_ = [("col_tile", ctypes.c_int32), ("row_iters", ctypes.c_int32),
+                ("col_iters", ctypes.c_int32), ("row_points", ctypes.c_int32),
+                ("col_points", ctypes.c_int32)]
+
+
 class SgpeError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = int(status)
@@ -47,7 +54,8 @@ _LIB = None
 EXPORTS = [
     "sgpe_validate_params", "sgpe_device_count", "sgpe_create", "sgpe_destroy", "sgpe_set_psi",
     "sgpe_get_psi", "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
-    "sgpe_synchronize", "sgpe_profile_steps", "sgpe_profile_kernels", "sgpe_strerror", "sgpe_set_col_tile",
+    "sgpe_synchronize", "sgpe_profile_steps", "sgpe_profile_kernels", "sgpe_strerror",
+    "sgpe_set_col_tile", "sgpe_get_schedule", "sgpe_set_schedule",
 ]
 
 
@@ -103,6 +111,10 @@ def _lib():
     lib.sgpe_profile_kernels.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double),
                                          P(ctypes.c_double)]
     lib.sgpe_profile_kernels.restype = st
+    lib.sgpe_get_schedule.argtypes = [vp, P(Schedule)]
+    lib.sgpe_get_schedule.restype = st
+    lib.sgpe_set_schedule.argtypes = [vp, P(Schedule)]
+    lib.sgpe_set_schedule.restype = st
     lib.sgpe_strerror.argtypes = [ctypes.c_int]
     lib.sgpe_strerror.restype = ctypes.c_char_p
     lib.sgpe_set_col_tile.argtypes = [vp, ctypes.c_int32]

@@ -47,6 +47,11 @@ struct sgpe_ctx {
   size_t max_lds = 0;       // dynamic LDS bytes available per workgroup
   int rows = 1;             // rows per row-pass workgroup
   int cols = 1;             // columns per column-pass workgroup
+  int row_iters = 1;        // row groups per row-pass workgroup (the next one prefetched)
+  int col_iters = 1;        // column tiles per column-pass workgroup
+  int row_points = 16;      // points per lane of the x transforms
+  int col_points = 16;      // points per lane of the y transforms
+  int n_cu = 1;             // compute units of the device
   bool full2x2 = false;
   bool has_state = false;
   sgpe_status latched = SGPE_OK;
@@ -159,6 +164,36 @@ void k_tables(const sgpe_params& p, bool imag, double h, std::vector<float4>& kx
   }
 }
 
+// Default schedule (from measured sweeps on MI355X).  Points per lane: 16 where the grid alone
+// fills the device; on small grids fewer points per lane (more lanes, a shorter instruction
+// stream per lane) cut each pass's latency.  Row prefetching (two row groups per workgroup) pays
+// only when the one-group grid is a single round of resident workgroups (two per compute unit):
+// then nothing else would overlap the first loads and last stores.  With more rounds, later
+// workgroups' loads already overlap earlier ones' arithmetic and halving the resident waves
+// loses.  Column prefetching needs the narrower tile and measured slower everywhere; it stays
+// off by default.
+int default_points(int n, size_t npts) {
+  if (n > sgpe::kMaxNSmallP) return 16;
+  if (npts >= (size_t(1) << 19)) return 16;
+  return npts >= (size_t(1) << 17) ? 8 : 4;
+}
+
+void default_schedule(sgpe_ctx* c) {
+  const int nx = c->p.nx, ny = c->p.ny;
+  const size_t npts = size_t(nx) * size_t(ny);
+  c->row_points = default_points(nx, npts);
+  c->col_points = default_points(ny, npts);
+  c->rows = sgpe::row_rows_per_block(nx, ny, c->row_points, c->max_lds);
+  c->cols = sgpe::col_default_cols(nx, ny, c->col_points, c->max_lds);
+  c->row_iters = 1;
+  c->col_iters = 1;
+  const int groups = ny / c->rows;
+  if (c->row_points == 16 && groups == 2 * c->n_cu && sgpe::schedule_supported(nx, c->rows, 2, 16))
+    c->row_iters = 2;
+}
+
+int col_groups(const sgpe_ctx* c) { return c->p.nx / (c->cols * c->col_iters); }
+
 sgpe_status status_of(hipError_t e) {
   if (e == hipSuccess) return SGPE_OK;
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SGPE_ENOMEM;
@@ -219,9 +254,9 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
   hipStream_t s = c->stream;
   hipError_t e;
   RowArgs ra = row_args(c);
-  e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, s);
+  e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_iters, c->row_points, s);
   if (e != hipSuccess) return status_of(e);
-  e = sgpe::launch_col(col_args(c, imag, true), sgpe::NORM_NONE, s);
+  e = sgpe::launch_col(col_args(c, imag, true), sgpe::NORM_NONE, c->col_iters, c->col_points, s);
   if (e != hipSuccess) return status_of(e);
   size_t evi = 0;
   for (int64_t i = 1; i <= n; ++i) {
@@ -229,15 +264,15 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
     r.scale = inv_n;
     if (imag && i > 1) {
       r.partials = c->partials;
-      r.n_partials = c->p.nx / c->cols;
+      r.n_partials = col_groups(c);
     }
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
-    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, s);
+    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, c->row_iters, c->row_points, s);
     if (e != hipSuccess) return status_of(e);
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
     const bool last = (i == n);
     const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
-    e = sgpe::launch_col(col_args(c, imag, last), nm, s);
+    e = sgpe::launch_col(col_args(c, imag, last), nm, c->col_iters, c->col_points, s);
     if (e != hipSuccess) return status_of(e);
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
   }
@@ -245,9 +280,9 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
   r.scale = inv_n;
   if (imag) {
     r.partials = c->partials;
-    r.n_partials = c->p.nx / c->cols;
+    r.n_partials = col_groups(c);
   }
-  e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, s);
+  e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_iters, c->row_points, s);
   return status_of(e);
 }
 
@@ -334,8 +369,8 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
   c->stream = static_cast<hipStream_t>(hip_stream);
   // the kernels' static LDS (reduction scratch) is < 256 bytes
   c->max_lds = prop.sharedMemPerBlock > 256 ? size_t(prop.sharedMemPerBlock) - 256 : 0;
-  c->rows = sgpe::row_rows_per_block(p->nx, p->ny, c->max_lds);
-  c->cols = sgpe::col_default_cols(p->nx, p->ny, c->max_lds);
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  default_schedule(c);
   c->full2x2 = (p->omega_r0 != 0.0);
   if (sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds) {
     delete c;
@@ -401,11 +436,49 @@ void sgpe_destroy(sgpe_ctx* c) {
 sgpe_status sgpe_set_col_tile(sgpe_ctx* c, int32_t columns) {
   if (!c) return SGPE_EINVAL;
   if (columns == 0) {
-    c->cols = sgpe::col_default_cols(c->p.nx, c->p.ny, c->max_lds);
+    default_schedule(c);
     return SGPE_OK;
   }
-  if (!sgpe::col_cols_supported(c->p.nx, c->p.ny, columns, c->max_lds)) return SGPE_EINVAL;
+  const sgpe_params& p = c->p;
+  if (columns < 1) return SGPE_EINVAL;
+  int iters = c->col_iters;
+  if (!sgpe::col_cols_supported(p.nx, p.ny, columns, iters, c->col_points, c->max_lds)) iters = 1;
+  if (!sgpe::col_cols_supported(p.nx, p.ny, columns, iters, c->col_points, c->max_lds)) return SGPE_EINVAL;
   c->cols = columns;
+  c->col_iters = iters;
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_get_schedule(sgpe_ctx* c, sgpe_schedule* out) {
+  if (!c || !out) return SGPE_EINVAL;
+  out->col_tile = c->cols;
+  out->row_iters = c->row_iters;
+  out->col_iters = c->col_iters;
+  out->row_points = c->row_points;
+  out->col_points = c->col_points;
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_set_schedule(sgpe_ctx* c, const sgpe_schedule* s) {
+  if (!c) return SGPE_EINVAL;
+  if (!s) {
+    default_schedule(c);
+    return SGPE_OK;
+  }
+  const sgpe_params& p = c->p;
+  if (s->row_points != 4 && s->row_points != 8 && s->row_points != 16) return SGPE_EINVAL;
+  if (s->col_tile < 1) return SGPE_EINVAL;
+  const int rows = sgpe::row_rows_per_block(p.nx, p.ny, s->row_points, c->max_lds);
+  if (!sgpe::schedule_supported(p.nx, rows, s->row_iters, s->row_points) || p.ny % (rows * s->row_iters) != 0 ||
+      sgpe::row_lds_bytes(p.nx, rows) > c->max_lds)
+    return SGPE_EINVAL;
+  if (!sgpe::col_cols_supported(p.nx, p.ny, s->col_tile, s->col_iters, s->col_points, c->max_lds)) return SGPE_EINVAL;
+  c->rows = rows;
+  c->cols = s->col_tile;
+  c->row_iters = s->row_iters;
+  c->col_iters = s->col_iters;
+  c->row_points = s->row_points;
+  c->col_points = s->col_points;
   return SGPE_OK;
 }
 
@@ -615,21 +688,21 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* c, int32_t imag, int64_t n, double* r
   // keep the state; enter the mixed representation with valid norm partials
   if (e == hipSuccess) e = hipMemcpyAsync(c->scratch, c->psi, bytes, hipMemcpyDeviceToDevice, s);
   RowArgs ra = row_args(c);
-  if (e == hipSuccess) e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, s);
+  if (e == hipSuccess) e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_iters, c->row_points, s);
   const int steady_norm = imag ? sgpe::NORM_DOT : sgpe::NORM_NONE;
-  if (e == hipSuccess) e = sgpe::launch_col(col_args(c, imag != 0, true), sgpe::NORM_DOT, s);
+  if (e == hipSuccess) e = sgpe::launch_col(col_args(c, imag != 0, true), sgpe::NORM_DOT, c->col_iters, c->col_points, s);
   RowArgs r = ra;
   r.scale = float(1.0 / (double(p.nx) * double(p.ny)));
   if (imag) {
     r.partials = c->partials;
-    r.n_partials = p.nx / c->cols;
+    r.n_partials = col_groups(c);
   }
   const ColArgs ca = col_args(c, imag != 0, false);
   if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-  for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = sgpe::launch_row(r, sgpe::ROW_STEP, imag != 0, c->full2x2, s);
+  for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = sgpe::launch_row(r, sgpe::ROW_STEP, imag != 0, c->full2x2, c->row_iters, c->row_points, s);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s);
-  for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = sgpe::launch_col(ca, steady_norm, s);
+  for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = sgpe::launch_col(ca, steady_norm, c->col_iters, c->col_points, s);
   if (e == hipSuccess) e = hipEventRecord(ev[3], s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->psi, c->scratch, bytes, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

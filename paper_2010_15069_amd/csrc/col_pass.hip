@@ -17,106 +17,138 @@
 
 namespace sgpe {
 
-__device__ __forceinline__ int col_tile(int b, int ntiles) {
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles so
-  // that tiles sharing 128-byte lines meet in the same L2.
-  if ((ntiles & 7) == 0) return (b & 7) * (ntiles >> 3) + (b >> 3);
+__device__ __forceinline__ int col_group(int b, int ngroups) {
+  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tile groups
+  // so that tiles sharing 128-byte lines meet in the same L2.
+  if ((ngroups & 7) == 0) return (b & 7) * (ngroups >> 3) + (b >> 3);
   return b;
 }
 
-template <int N, int NORM>
-__global__ void __launch_bounds__(512) col_kernel(ColArgs a) {
+// A workgroup handles ITERS adjacent tiles of C columns, one after the other; the next tile's
+// data is loaded into registers before the current tile is transformed.  P points per lane:
+// T = N / P lanes per transform.
+template <int N, int NORM, int ITERS, int P>
+__global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) {
   extern __shared__ float2 lds_raw[];
   __shared__ double red[64];
-  constexpr int T = N / 16;
+  constexpr int T = N / P;
   const int C = a.cols;
   const int tid = threadIdx.x;
   const int comp = tid & 1;
   const int pair = tid >> 1;
   const int cc = pair & (C - 1);
   const int t = pair / C;
-  const int tile = col_tile(blockIdx.x, a.nx / C);
-  const int x = tile * C + cc;
+  const int tile0 = col_group(blockIdx.x, a.nx / (C * ITERS)) * ITERS;
+  const int x0 = tile0 * C + cc;
   const LdsView<float2> lds{lds_raw + 2 * cc + comp, 1 + __builtin_ctz(C)};
   // element (row y) of this lane's component is at byte offset 16 (y nx + x) + 8 comp; 32-bit
   // offsets from a wave-uniform base, the row stride a wave-uniform value
   const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
+  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
   const uint32_t rstride = 16u * static_cast<uint32_t>(a.nx);
-  const uint32_t off0 = static_cast<uint32_t>(t) * rstride + 16u * static_cast<uint32_t>(x) + 8u * comp;
   const uint32_t mstride = static_cast<uint32_t>(T) * rstride;
+  const uint32_t tile_stride = 16u * static_cast<uint32_t>(C);
+  uint32_t off = static_cast<uint32_t>(t) * rstride + 16u * static_cast<uint32_t>(x0) + 8u * comp;
 
-  float2 v[16];
+  float2 v[P], nxt[P];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = *reinterpret_cast<const float2*>(base + off0 + mstride * m);
-  TwPlain<N> tr;
-  load_twiddles<N>(tr, t, a.tw);
+  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + off + mstride * m);
   // this component's row of M' - 1 at k_x: {d_own, d_other}
-  const float4 d = a.kx_tab[2 * x + comp];
-
-  fwd_pass<N>(v, lds, t, tr);
+  float4 d = a.kx_tab[2 * x0 + comp], dn = d;
+  // stage the k_y operator row in LDS now, so no global load waits in the middle of the pass
+  float2* __restrict__ kyl = lds_raw + 2 * C * (N + N / 16);
+  for (int i = tid; i < N; i += blockDim.x) kyl[i] = a.ky_tab[i];
+  TwPlain<N, P> tr;
+  load_twiddles<N>(tr, t, a.tw);
 
   double acc = 0.0;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const float2 w = v[m];
-    const float2 o = pair_swap(w);
-    const float2 q = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.ky_tab) + 8u * static_cast<uint32_t>(t + T * m));
-    const float c1r = fmaf(-d.w, o.y, fmaf(d.z, o.x, fmaf(-d.y, w.y, d.x * w.x)));
-    const float c1i = fmaf(d.w, o.x, fmaf(d.z, o.y, fmaf(d.y, w.x, d.x * w.y)));
-    const float cr = fmaf(-q.y, w.y, fmaf(q.x, w.x, fmaf(-q.y, c1i, fmaf(q.x, c1r, c1r))));
-    const float ci = fmaf(q.y, w.x, fmaf(q.x, w.y, fmaf(q.y, c1r, fmaf(q.x, c1i, c1i))));
-    const float2 out = make_float2(w.x + cr, w.y + ci);
-    if constexpr (NORM == NORM_DOT) {
-      acc += static_cast<double>(fmaf(w.x, out.x, w.y * out.y));
-    } else if constexpr (NORM == NORM_SQ) {
-      acc += static_cast<double>(fmaf(out.x, out.x, out.y * out.y));
+  for (int it = 0; it < ITERS; ++it) {
+    if (it + 1 < ITERS) {
+#pragma unroll
+      for (int m = 0; m < P; ++m)
+        nxt[m] = *reinterpret_cast<const float2*>(base + off + tile_stride + mstride * m);
+      dn = a.kx_tab[2 * (x0 + (it + 1) * C) + comp];
     }
-    v[m] = out;
+    fwd_pass<N>(v, lds, t, tr);
+    if constexpr (N <= P) __syncthreads();   // a single-stage transform has no barrier of its own
+
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const float2 w = v[m];
+      const float2 o = pair_swap(w);
+      const float2 q = kyl[t + T * m];
+      const float c1r = fmaf(-d.w, o.y, fmaf(d.z, o.x, fmaf(-d.y, w.y, d.x * w.x)));
+      const float c1i = fmaf(d.w, o.x, fmaf(d.z, o.y, fmaf(d.y, w.x, d.x * w.y)));
+      const float cr = fmaf(-q.y, w.y, fmaf(q.x, w.x, fmaf(-q.y, c1i, fmaf(q.x, c1r, c1r))));
+      const float ci = fmaf(q.y, w.x, fmaf(q.x, w.y, fmaf(q.y, c1r, fmaf(q.x, c1i, c1i))));
+      const float2 res = make_float2(w.x + cr, w.y + ci);
+      if constexpr (NORM == NORM_DOT) {
+        acc += static_cast<double>(fmaf(w.x, res.x, w.y * res.y));
+      } else if constexpr (NORM == NORM_SQ) {
+        acc += static_cast<double>(fmaf(res.x, res.x, res.y * res.y));
+      }
+      v[m] = res;
+    }
+
+    inv_pass<N>(v, lds, t, tr);
+
+#pragma unroll
+    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + off + mstride * m) = v[m];
+    if (it + 1 < ITERS) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) v[m] = nxt[m];
+      d = dn;
+      off += tile_stride;
+    }
   }
   if constexpr (NORM != NORM_NONE) {
-    const double s = block_sum(acc, red);
-    if (tid == 0) a.partials[blockIdx.x] = s;
+    const double sum = block_sum(acc, red);
+    if (tid == 0) a.partials[blockIdx.x] = sum;
   }
-
-  inv_pass<N>(v, lds, t, tr);
-
-  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
-#pragma unroll
-  for (int m = 0; m < 16; ++m) *reinterpret_cast<float2*>(out + off0 + mstride * m) = v[m];
 }
 
 // -------------------------------------------------------------------------------------------
 // Launcher
 // -------------------------------------------------------------------------------------------
 template <int N, int NORM>
-static hipError_t col_launch_t(const ColArgs& a, hipStream_t s) {
-  const dim3 block(2 * a.cols * (N / 16));
-  const dim3 grid(a.nx / a.cols);
-  hipLaunchKernelGGL((col_kernel<N, NORM>), grid, block, col_lds_bytes(N, a.cols), s, a);
+static hipError_t col_launch_t(const ColArgs& a, int iters, int points, hipStream_t s) {
+  const dim3 block(2 * a.cols * (N / points));
+  const dim3 grid(a.nx / (a.cols * iters));
+  const size_t lds = col_lds_bytes(N, a.cols);
+  if (points == 16) {
+    if (iters == 2) hipLaunchKernelGGL((col_kernel<N, NORM, 2, 16>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((col_kernel<N, NORM, 1, 16>), grid, block, lds, s, a);
+  } else if constexpr (N <= kMaxNSmallP) {
+    if (points == 8) hipLaunchKernelGGL((col_kernel<N, NORM, 1, 8>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((col_kernel<N, NORM, 1, 4>), grid, block, lds, s, a);
+  }
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t col_launch_n(const ColArgs& a, int norm, hipStream_t s) {
+static hipError_t col_launch_n(const ColArgs& a, int norm, int iters, int points, hipStream_t s) {
   switch (norm) {
-    case NORM_NONE: return col_launch_t<N, NORM_NONE>(a, s);
-    case NORM_DOT: return col_launch_t<N, NORM_DOT>(a, s);
-    case NORM_SQ: return col_launch_t<N, NORM_SQ>(a, s);
+    case NORM_NONE: return col_launch_t<N, NORM_NONE>(a, iters, points, s);
+    case NORM_DOT: return col_launch_t<N, NORM_DOT>(a, iters, points, s);
+    case NORM_SQ: return col_launch_t<N, NORM_SQ>(a, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_col(const ColArgs& a, int norm, hipStream_t s) {
+hipError_t launch_col(const ColArgs& a, int norm, int iters, int points, hipStream_t s) {
+  if (!schedule_supported(a.ny, a.cols, iters, points)) return hipErrorInvalidValue;
+  if (a.nx % (a.cols * iters) != 0) return hipErrorInvalidValue;
   switch (a.ny) {
-    case 16: return col_launch_n<16>(a, norm, s);
-    case 32: return col_launch_n<32>(a, norm, s);
-    case 64: return col_launch_n<64>(a, norm, s);
-    case 128: return col_launch_n<128>(a, norm, s);
-    case 256: return col_launch_n<256>(a, norm, s);
-    case 512: return col_launch_n<512>(a, norm, s);
-    case 1024: return col_launch_n<1024>(a, norm, s);
-    case 2048: return col_launch_n<2048>(a, norm, s);
-    case 4096: return col_launch_n<4096>(a, norm, s);
+    case 16: return col_launch_n<16>(a, norm, iters, points, s);
+    case 32: return col_launch_n<32>(a, norm, iters, points, s);
+    case 64: return col_launch_n<64>(a, norm, iters, points, s);
+    case 128: return col_launch_n<128>(a, norm, iters, points, s);
+    case 256: return col_launch_n<256>(a, norm, iters, points, s);
+    case 512: return col_launch_n<512>(a, norm, iters, points, s);
+    case 1024: return col_launch_n<1024>(a, norm, iters, points, s);
+    case 2048: return col_launch_n<2048>(a, norm, iters, points, s);
+    case 4096: return col_launch_n<4096>(a, norm, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }

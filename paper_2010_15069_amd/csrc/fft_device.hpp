@@ -444,22 +444,36 @@ __device__ __forceinline__ void pi_dft(float2 (&a)[R]) {
   }
 }
 
+// Step-kernel transforms with P points per thread (P = 4, 8 or 16; T = N / P threads per
+// transform, thread t holding positions t + T m).  Stages have radix P, then the remainder.
+
+// Stage roots a thread needs: the first stage (L = 1) needs none; a later stage of radix R uses
+// W_N^(s r N/(R L)) for its P/R butterflies and r = 1..R-1.
+template <int N, int P, int L = 1>
+constexpr int tw_count_p() {
+  constexpr int REM = N / L;
+  constexpr int R = REM >= P ? P : REM;
+  constexpr int here = L > 1 ? (P / R) * (R - 1) : 0;
+  if constexpr (R == REM) return here;
+  else return here + tw_count_p<N, P, L * R>();
+}
+
 // Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and the low part
 // (cos, sin) eta of its exact inverse; table entries are float4 {cos, sin, cos eta, sin eta} of
-// exp(-2 pi i j / N).
-template <int N>
+// exp(-2 pi i j / N).  Loaded once per kernel (they depend only on the thread index).
+template <int N, int P = 16>
 struct TwPlain {
-  static constexpr int COUNT = tw_count<N>() > 0 ? tw_count<N>() : 1;
+  static constexpr int COUNT = tw_count_p<N, P>() > 0 ? tw_count_p<N, P>() : 1;
   float2 cs[COUNT];
   float2 lo[COUNT];
 };
 
-template <int N, int L = 1, int BASE = 0>
-__device__ __forceinline__ void load_twiddles(TwPlain<N>& tr, int t, const float4* __restrict__ tw) {
-  constexpr int T = N / 16;
+template <int N, int P, int L = 1, int BASE = 0>
+__device__ __forceinline__ void load_twiddles(TwPlain<N, P>& tr, int t, const float4* __restrict__ tw) {
+  constexpr int T = N / P;
   constexpr int REM = N / L;
-  constexpr int R = REM >= 16 ? 16 : REM;
-  constexpr int U = 16 / R;
+  constexpr int R = REM >= P ? P : REM;
+  constexpr int U = P / R;
   constexpr int TW_STRIDE = N / (R * L);
   if constexpr (L > 1) {
 #pragma unroll
@@ -476,15 +490,15 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N>& tr, int t, const float
   }
   if constexpr (R != REM) {
     constexpr int NEXT = BASE + (L > 1 ? U * (R - 1) : 0);
-    load_twiddles<N, L * R, NEXT>(tr, t, tw);
+    load_twiddles<N, P, L * R, NEXT>(tr, t, tw);
   }
 }
 
 // forward stage (plain roots)
-template <int N, int R, int L, bool LAST, int BASE>
-__device__ __forceinline__ void pf_stage(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
-  constexpr int T = N / 16;
-  constexpr int U = 16 / R;
+template <int N, int P, int R, int L, bool LAST, int BASE>
+__device__ __forceinline__ void pf_stage(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
+  constexpr int T = N / P;
+  constexpr int U = P / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     float2 a[R];
@@ -526,29 +540,29 @@ __device__ __forceinline__ void lds_sync() {
 }
 
 // Forward length-N transform (positions t + T*m in and out), plain roots.
-template <int N, bool WSYNC = false, int L = 1, int BASE = 0>
-__device__ __forceinline__ void fwd_pass(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
+template <int N, bool WSYNC = false, int L = 1, int BASE = 0, int P>
+__device__ __forceinline__ void fwd_pass(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
   constexpr int REM = N / L;
-  constexpr int R = REM >= 16 ? 16 : REM;
+  constexpr int R = REM >= P ? P : REM;
   constexpr bool LAST = (R == REM);
-  constexpr int T = N / 16;
-  pf_stage<N, R, L, LAST, BASE>(v, lds, t, tr);
+  constexpr int T = N / P;
+  pf_stage<N, P, R, L, LAST, BASE>(v, lds, t, tr);
   if constexpr (!LAST) {
     lds_sync<WSYNC>();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = lds.at(t + T * m);
+    for (int m = 0; m < P; ++m) v[m] = lds.at(t + T * m);
     lds_sync<WSYNC>();
-    constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
+    constexpr int NEXT = BASE + (L > 1 ? (P / R) * (R - 1) : 0);
     fwd_pass<N, WSYNC, L * R, NEXT>(v, lds, t, tr);
   }
 }
 
 // Inverse stage: the forward stage's outputs (from LDS, or the registers for the last stage)
 // through the exact inverse butterfly and inverse roots, into registers {u + U r}.
-template <int N, int R, int L, bool LAST, int BASE>
-__device__ __forceinline__ void pi_stage(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
-  constexpr int T = N / 16;
-  constexpr int U = 16 / R;
+template <int N, int P, int R, int L, bool LAST, int BASE>
+__device__ __forceinline__ void pi_stage(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
+  constexpr int T = N / P;
+  constexpr int U = P / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     float2 a[R];
@@ -578,22 +592,22 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[16], const LdsView<float2>&
 
 // Exact inverse of fwd_pass, times N: the stages undone in reverse order.  All threads of the
 // workgroup call it; on return every LDS read is complete.
-template <int N, bool WSYNC = false, int L = 1, int BASE = 0>
-__device__ __forceinline__ void inv_pass(float2 (&v)[16], const LdsView<float2>& lds, int t, const TwPlain<N>& tr) {
+template <int N, bool WSYNC = false, int L = 1, int BASE = 0, int P>
+__device__ __forceinline__ void inv_pass(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
   constexpr int REM = N / L;
-  constexpr int R = REM >= 16 ? 16 : REM;
+  constexpr int R = REM >= P ? P : REM;
   constexpr bool LAST = (R == REM);
-  constexpr int T = N / 16;
+  constexpr int T = N / P;
   if constexpr (LAST) {
-    pi_stage<N, R, L, true, BASE>(v, lds, t, tr);
+    pi_stage<N, P, R, L, true, BASE>(v, lds, t, tr);
   } else {
-    constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
+    constexpr int NEXT = BASE + (L > 1 ? (P / R) * (R - 1) : 0);
     inv_pass<N, WSYNC, L * R, NEXT>(v, lds, t, tr);
     // undo "read positions t + T m from LDS", then this stage
 #pragma unroll
-    for (int m = 0; m < 16; ++m) lds.at(t + T * m) = v[m];
+    for (int m = 0; m < P; ++m) lds.at(t + T * m) = v[m];
     lds_sync<WSYNC>();
-    pi_stage<N, R, L, false, BASE>(v, lds, t, tr);
+    pi_stage<N, P, R, L, false, BASE>(v, lds, t, tr);
     lds_sync<WSYNC>();
   }
 }

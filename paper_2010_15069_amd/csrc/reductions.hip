@@ -8,37 +8,35 @@ namespace sgpe {
 // -------------------------------------------------------------------------------------------
 // Geometry
 // -------------------------------------------------------------------------------------------
-// Step kernels: lane pairs (two components) x T = n/16 lanes per line; a slot of the LDS
+// Step kernels: lane pairs (two components) x T = n/points lanes per line; a slot of the LDS
 // exchange holds both components (16 bytes).
 size_t row_lds_bytes(int nx, int rows) { return size_t(rows) * size_t(nx + nx / 16) * 16; }
 
-size_t col_lds_bytes(int ny, int cols) { return size_t(cols) * size_t(ny + ny / 16) * 16; }
+// column pass: the transforms' exchange slots, then the k_y operator row (one float2 per k_y)
+size_t col_lds_bytes(int ny, int cols) { return size_t(cols) * size_t(ny + ny / 16) * 16 + size_t(ny) * 8; }
 
-int row_rows_per_block(int nx, int ny, size_t max_lds) {
-  const int t = nx / 16;
-  int rows = 128 / t;  // 256 threads
+int row_rows_per_block(int nx, int ny, int points, size_t max_lds) {
+  int rows = 128 * points / nx;  // 256 threads
   if (rows < 1) rows = 1;
   if (rows > ny) rows = ny;
   while (rows > 1 && row_lds_bytes(nx, rows) > max_lds) rows >>= 1;
   return rows;
 }
 
-bool col_cols_supported(int nx, int ny, int cols, size_t max_lds) {
-  if (cols < 1 || (cols & (cols - 1)) != 0 || cols > nx) return false;
-  const int t = ny / 16;
-  if (2 * cols * t > 512) return false;
+bool col_cols_supported(int nx, int ny, int cols, int iters, int points, size_t max_lds) {
+  if (cols > nx || nx % (cols * iters) != 0) return false;
+  if (!schedule_supported(ny, cols, iters, points)) return false;
   return col_lds_bytes(ny, cols) <= max_lds;
 }
 
-int col_default_cols(int nx, int ny, size_t max_lds) {
-  const int t = ny / 16;
-  int c = 128 / t;  // 256 threads
+int col_default_cols(int nx, int ny, int points, size_t max_lds) {
+  int c = 128 * points / ny;  // 256 threads
   if (c < 1) c = 1;
   // prefer at least 4 columns (64-byte row segments) while threads and LDS allow it
   int want = 4;
-  while (want > c && !col_cols_supported(nx, ny, want, max_lds)) want >>= 1;
+  while (want > c && !col_cols_supported(nx, ny, want, 1, points, max_lds)) want >>= 1;
   if (want > c) c = want;
-  while (c > 1 && !col_cols_supported(nx, ny, c, max_lds)) c >>= 1;
+  while (c > 1 && !col_cols_supported(nx, ny, c, 1, points, max_lds)) c >>= 1;
   return c;
 }
 

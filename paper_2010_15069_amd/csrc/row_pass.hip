@@ -140,9 +140,9 @@ __device__ __forceinline__ float2 apply_r_full(float2 w, float2 o, const RFull& 
 // R on the thread's 16 points.  For each point index the wave takes one routine: the short one
 // when every lane's angles allow it (the common case), else the general one -- a wave-uniform
 // branch, so a wave never runs both.
-template <int N, bool IMAG, bool FULL>
-__device__ __forceinline__ void row_apply_r(float2 (&v)[16], const RowArgs& a, int row, int t, bool up) {
-  constexpr int T = N / 16;
+template <int N, bool IMAG, bool FULL, int P>
+__device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, int row, int t, bool up) {
+  constexpr int T = N / P;
   RCoef c;
   c.sgn = up ? 1.0f : -1.0f;
   c.hd_own = up ? a.hdelta2 : -a.hdelta2;
@@ -154,7 +154,7 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[16], const RowArgs& a, i
   const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
   const float hvy = a.hvy * y * y;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
+  for (int m = 0; m < P; ++m) {
     const int j = t + T * m;
     const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
     const float hv = fmaf(a.hvx * x, x, hvy);
@@ -175,80 +175,110 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[16], const RowArgs& a, i
   }
 }
 
-template <int N, int MODE, bool IMAG, bool FULL>
-__global__ void __launch_bounds__(512) row_kernel(RowArgs a) {
+// A workgroup handles ITERS groups of rows_per_block rows, one after the other; the next group's
+// data is loaded into registers before the current group is transformed, so its memory latency
+// hides behind this group's arithmetic.  P points per lane: T = N / P lanes per transform.
+template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
+__global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) {
   extern __shared__ float2 lds_raw[];
-  constexpr int T = N / 16;
+  constexpr int T = N / P;
   constexpr int SLOTS = N + N / 16;
   const int tid = threadIdx.x;
   const int comp = tid & 1;
   const int pair = tid >> 1;
   const int rloc = pair / T;
   const int t = pair - rloc * T;
-  const int row = blockIdx.x * a.rows_per_block + rloc;
+  const int row0 = blockIdx.x * ITERS * a.rows_per_block + rloc;
   const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
   // element `pos` of this lane's component is at byte offset 16 pos from the row start; 32-bit
   // offsets from a wave-uniform base
   const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
-  const uint32_t off0 = (static_cast<uint32_t>(row) * N + static_cast<uint32_t>(t)) * 16u + 8u * comp;
+  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
+  const uint32_t lane_off = static_cast<uint32_t>(t) * 16u + 8u * comp;
+  const uint32_t group_stride = static_cast<uint32_t>(a.rows_per_block) * (16u * N);
 
-  float2 v[16];
+  float2 v[P], nxt[P];
+  uint32_t off = static_cast<uint32_t>(row0) * (16u * N) + lane_off;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = *reinterpret_cast<const float2*>(base + off0 + 16u * T * m);
-  TwPlain<N> tr;
+  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + off + 16u * T * m);
+  TwPlain<N, P> tr;
   load_twiddles<N>(tr, t, a.tw);
+  float s = 1.0f;
+  if constexpr (MODE != ROW_FWD) s = row_scale(a);
 
-  if constexpr (MODE == ROW_FWD) {
-    fwd_pass<N>(v, lds, t, tr);
-  } else {
-    const float s = row_scale(a);
-    inv_pass<N>(v, lds, t, tr);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = vscale(v[m], s);
-    if constexpr (MODE == ROW_STEP) {
-      row_apply_r<N, IMAG, FULL>(v, a, row, t, comp == 0);
+  for (int it = 0; it < ITERS; ++it) {
+    if (it + 1 < ITERS) {
+#pragma unroll
+      for (int m = 0; m < P; ++m)
+        nxt[m] = *reinterpret_cast<const float2*>(base + off + group_stride + 16u * T * m);
+    }
+    if constexpr (MODE == ROW_FWD) {
       fwd_pass<N>(v, lds, t, tr);
+    } else {
+      inv_pass<N>(v, lds, t, tr);
+#pragma unroll
+      for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
+      if constexpr (MODE == ROW_STEP) {
+        row_apply_r<N, IMAG, FULL>(v, a, row0 + it * a.rows_per_block, t, comp == 0);
+        fwd_pass<N>(v, lds, t, tr);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + off + 16u * T * m) = v[m];
+    if (it + 1 < ITERS) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) v[m] = nxt[m];
+      off += group_stride;
     }
   }
-  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
-#pragma unroll
-  for (int m = 0; m < 16; ++m) *reinterpret_cast<float2*>(out + off0 + 16u * T * m) = v[m];
 }
 
 // -------------------------------------------------------------------------------------------
 // Launcher
 // -------------------------------------------------------------------------------------------
 template <int N, int MODE, bool IMAG, bool FULL>
-static hipError_t row_launch_t(const RowArgs& a, hipStream_t s) {
-  const dim3 block(2 * a.rows_per_block * (N / 16));
-  const dim3 grid(a.ny / a.rows_per_block);
-  hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL>), grid, block, row_lds_bytes(N, a.rows_per_block), s, a);
+static hipError_t row_launch_t(const RowArgs& a, int iters, int points, hipStream_t s) {
+  const dim3 block(2 * a.rows_per_block * (N / points));
+  const dim3 grid(a.ny / (a.rows_per_block * iters));
+  const size_t lds = row_lds_bytes(N, a.rows_per_block);
+  if (points == 16) {
+    if (iters == 2) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 2, 16>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 16>), grid, block, lds, s, a);
+  } else if constexpr (N <= kMaxNSmallP) {
+    if (points == 8) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 8>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 4>), grid, block, lds, s, a);
+  }
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t row_launch_n(const RowArgs& a, int mode, bool imag, bool full, hipStream_t s) {
+static hipError_t row_launch_n(const RowArgs& a, int mode, bool imag, bool full, int iters, int points, hipStream_t s) {
   switch (mode) {
-    case ROW_FWD: return row_launch_t<N, ROW_FWD, false, false>(a, s);
-    case ROW_INV: return row_launch_t<N, ROW_INV, false, false>(a, s);
+    case ROW_FWD: return row_launch_t<N, ROW_FWD, false, false>(a, iters, points, s);
+    case ROW_INV: return row_launch_t<N, ROW_INV, false, false>(a, iters, points, s);
     case ROW_STEP:
-      if (imag) return full ? row_launch_t<N, ROW_STEP, true, true>(a, s) : row_launch_t<N, ROW_STEP, true, false>(a, s);
-      return full ? row_launch_t<N, ROW_STEP, false, true>(a, s) : row_launch_t<N, ROW_STEP, false, false>(a, s);
+      if (imag) return full ? row_launch_t<N, ROW_STEP, true, true>(a, iters, points, s)
+                            : row_launch_t<N, ROW_STEP, true, false>(a, iters, points, s);
+      return full ? row_launch_t<N, ROW_STEP, false, true>(a, iters, points, s)
+                  : row_launch_t<N, ROW_STEP, false, false>(a, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full, hipStream_t s) {
+hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full, int iters, int points, hipStream_t s) {
+  if (!schedule_supported(a.nx, a.rows_per_block, iters, points)) return hipErrorInvalidValue;
+  if (a.ny % (a.rows_per_block * iters) != 0) return hipErrorInvalidValue;
   switch (a.nx) {
-    case 16: return row_launch_n<16>(a, mode, imag, full, s);
-    case 32: return row_launch_n<32>(a, mode, imag, full, s);
-    case 64: return row_launch_n<64>(a, mode, imag, full, s);
-    case 128: return row_launch_n<128>(a, mode, imag, full, s);
-    case 256: return row_launch_n<256>(a, mode, imag, full, s);
-    case 512: return row_launch_n<512>(a, mode, imag, full, s);
-    case 1024: return row_launch_n<1024>(a, mode, imag, full, s);
-    case 2048: return row_launch_n<2048>(a, mode, imag, full, s);
-    case 4096: return row_launch_n<4096>(a, mode, imag, full, s);
+    case 16: return row_launch_n<16>(a, mode, imag, full, iters, points, s);
+    case 32: return row_launch_n<32>(a, mode, imag, full, iters, points, s);
+    case 64: return row_launch_n<64>(a, mode, imag, full, iters, points, s);
+    case 128: return row_launch_n<128>(a, mode, imag, full, iters, points, s);
+    case 256: return row_launch_n<256>(a, mode, imag, full, iters, points, s);
+    case 512: return row_launch_n<512>(a, mode, imag, full, iters, points, s);
+    case 1024: return row_launch_n<1024>(a, mode, imag, full, iters, points, s);
+    case 2048: return row_launch_n<2048>(a, mode, imag, full, iters, points, s);
+    case 4096: return row_launch_n<4096>(a, mode, imag, full, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }

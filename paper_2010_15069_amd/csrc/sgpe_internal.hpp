@@ -66,16 +66,30 @@ struct EnergyArgs {
 };
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full2x2, hipStream_t s);
-hipError_t launch_col(const ColArgs& a, int norm_mode, hipStream_t s);
+// Pass geometry.  points: points per lane of the transforms (16; 8 or 4 for lengths up to
+// kMaxNSmallP, where more lanes shorten each lane's instruction stream); groups: rows (row pass)
+// or columns (column pass) per workgroup; iters: row groups / column tiles per workgroup, 1 or 2
+// (the next one prefetched while this one runs; 16 points per lane, at most 256 threads).
+constexpr int kMaxNSmallP = 1024;
+inline bool schedule_supported(int n, int groups, int iters, int points) {
+  if (points != 16 && !((points == 8 || points == 4) && n <= kMaxNSmallP)) return false;
+  if (n < points || groups < 1 || (groups & (groups - 1)) != 0) return false;
+  if (iters != 1 && iters != 2) return false;
+  if (iters == 2 && points != 16) return false;
+  const int threads = 2 * groups * (n / points);
+  return threads <= (iters == 2 ? 256 : 512);
+}
+
+hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full2x2, int iters, int points, hipStream_t s);
+hipError_t launch_col(const ColArgs& a, int norm_mode, int iters, int points, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 
 // Workgroup geometry helpers (shared with the host so that partial counts match).
 // max_lds: the device's LDS bytes per workgroup (minus the kernels' static LDS).
-int row_rows_per_block(int nx, int ny, size_t max_lds);
-int col_default_cols(int nx, int ny, size_t max_lds);
-bool col_cols_supported(int nx, int ny, int cols, size_t max_lds);
+int row_rows_per_block(int nx, int ny, int points, size_t max_lds);
+int col_default_cols(int nx, int ny, int points, size_t max_lds);
+bool col_cols_supported(int nx, int ny, int cols, int iters, int points, size_t max_lds);
 int energy_rows_per_block(int nx, int ny, size_t max_lds);
 int energy_cols_per_block(int nx, int ny, size_t max_lds);
 size_t row_lds_bytes(int nx, int rows);

@@ -6,7 +6,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import SgpeParams, check, lib
+from ._lib import Schedule, SgpeParams, check, lib
 
 
 class Solver:
@@ -99,8 +99,27 @@ class Solver:
                                              ctypes.byref(c)), "sgpe_profile_kernels")
         return r.value, c.value
 
+    def get_schedule(self) -> dict:
+        sc = Schedule()
+        check(self._lib.sgpe_get_schedule(self._ctx, ctypes.byref(sc)), "sgpe_get_schedule")
+        return {name: int(getattr(sc, name)) for name, _ in Schedule._fields_}
+
+    def set_schedule(self, schedule=None, **fields):
+        """Set the launch schedule from a dict and/or keyword fields, the unnamed fields kept;
+        set_schedule(None) with no fields restores the default."""
+        if schedule is None and not fields:
+            check(self._lib.sgpe_set_schedule(self._ctx, None), "sgpe_set_schedule")
+            return self
+        cur = self.get_schedule()
+        cur.update(schedule or {})
+        cur.update(fields)
+        sc = Schedule(**{k: int(v) for k, v in cur.items()})
+        check(self._lib.sgpe_set_schedule(self._ctx, ctypes.byref(sc)), "sgpe_set_schedule")
+        return self
+
     def set_col_tile(self, columns):
         check(self._lib.sgpe_set_col_tile(self._ctx, int(columns)), "sgpe_set_col_tile")
+        return self
 
 
 def device_count() -> int:

@@ -191,6 +191,35 @@ def test_column_tile_variants(Solver, nx, ny):
             assert rel_l2(i, ref_imag) < 1e-6, cols
 
 
+@pytest.mark.parametrize("name,nx,ny", [("realtime_512", 1024, 1024), ("realtime_512", 512, 2048),
+                                         ("ground_2048", 1024, 1024)])
+def test_pipeline_depth_variants(Solver, name, nx, ny):
+    # One or two row groups / column tiles per workgroup (the next one prefetched) changes only
+    # which workgroup does the work: real-time results are bit-identical, imaginary-time results
+    # differ only through the grouping of the fp64 norm partials.
+    p = preset(name, nx=nx, ny=ny)
+    psi0 = initial_state(p, "tf", seed=5)
+    ref_real, ref_imag, done = None, None, 0
+    for ri in (1, 2):
+        for ci in (1, 2):
+            s = Solver(p)
+            try:
+                s.set_schedule(row_iters=ri, col_iters=ci, row_points=16, col_points=16)
+            except Exception:
+                continue
+            s.set_psi(psi0).step_real(10)
+            r = s.get_psi()
+            s.step_imag(10)
+            i = s.get_psi()
+            done += 1
+            if ref_real is None:
+                ref_real, ref_imag = r, i
+            else:
+                assert np.array_equal(r, ref_real), (ri, ci)
+                assert rel_l2(i, ref_imag) < 1e-6, (ri, ci)
+    assert done >= 2
+
+
 def test_energy_and_norm_of_arbitrary_states(Solver):
     for (nx, ny, seed) in [(64, 64, 1), (256, 128, 2), (512, 1024, 3)]:
         p = Params(nx=nx, ny=ny, xmax=7.0, ymax=9.0, g_uu=5.0, g_dd=2.0, g_ud=3.0, k_l=1.1,
