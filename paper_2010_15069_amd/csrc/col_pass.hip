@@ -50,16 +50,27 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) 
   const uint32_t tile_stride = 16u * static_cast<uint32_t>(C);
   uint32_t off = static_cast<uint32_t>(t) * rstride + 16u * static_cast<uint32_t>(x0) + 8u * comp;
 
+  // The k_y operator row is staged in LDS (loaded per point after the forward transform, its
+  // latency would sit in the middle of the pass).  Its loads go out first, into registers (at
+  // most P/2 per thread: a workgroup has at least 2N/P threads), so writing them to LDS waits for
+  // them alone and not for the data behind them.
+  constexpr int KY_MAX = P / 2;
+  const int nth = blockDim.x;
+  float2 kyv[KY_MAX];
+#pragma unroll
+  for (int k = 0; k < KY_MAX; ++k)
+    if (k * nth < N) kyv[k] = a.ky_tab[min(tid + k * nth, N - 1)];
   float2 v[P], nxt[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + off + mstride * m);
   // this component's row of M' - 1 at k_x: {d_own, d_other}
   float4 d = a.kx_tab[2 * x0 + comp], dn = d;
-  // stage the k_y operator row in LDS now, so no global load waits in the middle of the pass
-  float2* __restrict__ kyl = lds_raw + 2 * C * (N + N / 16);
-  for (int i = tid; i < N; i += blockDim.x) kyl[i] = a.ky_tab[i];
   TwPlain<N, P> tr;
   load_twiddles<N>(tr, t, a.tw);
+  float2* __restrict__ kyl = lds_raw + 2 * C * (N + N / 16);
+#pragma unroll
+  for (int k = 0; k < KY_MAX; ++k)
+    if (k * nth < N && tid + k * nth < N) kyl[tid + k * nth] = kyv[k];
 
   double acc = 0.0;
 #pragma unroll

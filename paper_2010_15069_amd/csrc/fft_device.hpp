@@ -458,6 +458,15 @@ constexpr int tw_count_p() {
   else return here + tw_count_p<N, P, L * R>();
 }
 
+// Radix of the last stage of a length-N transform with P points per thread (radix-P stages,
+// then the remainder).
+template <int N, int P, int L = 1>
+constexpr int last_radix() {
+  constexpr int REM = N / L;
+  if constexpr (REM <= P) return REM;
+  else return last_radix<N, P, L * P>();
+}
+
 // Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and the low part
 // (cos, sin) eta of its exact inverse; table entries are float4 {cos, sin, cos eta, sin eta} of
 // exp(-2 pi i j / N).  Loaded once per kernel (they depend only on the thread index).

@@ -32,8 +32,9 @@ bool col_cols_supported(int nx, int ny, int cols, int iters, int points, size_t 
 int col_default_cols(int nx, int ny, int points, size_t max_lds) {
   int c = 128 * points / ny;  // 256 threads
   if (c < 1) c = 1;
-  // prefer at least 4 columns (64-byte row segments) while threads and LDS allow it
-  int want = 4;
+  // prefer 64-byte row segments (4 columns) for 16 points per lane, 32-byte ones (2 columns) for
+  // the small-grid schedules (measured), while threads and LDS allow it
+  int want = points == 16 ? 4 : 2;
   while (want > c && !col_cols_supported(nx, ny, want, 1, points, max_lds)) want >>= 1;
   if (want > c) c = want;
   while (c > 1 && !col_cols_supported(nx, ny, c, 1, points, max_lds)) c >>= 1;

@@ -28,14 +28,39 @@ namespace sgpe {
 
 // -------------------------------------------------------------------------------------------
 // Sum of the previous column pass's partials -> scale for the row pass.  Every wave computes
-// the same sum in the same order, so every workgroup applies bit-identical scales.
+// the same sum in the same order (lane l adds partials l, l + 64, ... in turn, then a fixed
+// butterfly across the wave), so every workgroup applies bit-identical scales.  Up to 256
+// partials are loaded at kernel start as four masked loads per lane, ahead of the data (a
+// runtime-length loop of loads would make the wave wait for every outstanding load); more
+// partials, or workgroups narrower than a wave, take the loop after the inverse transform.
 // -------------------------------------------------------------------------------------------
-__device__ __forceinline__ float row_scale(const RowArgs& a) {
+constexpr int kPrefetchPartials = 256;
+
+__device__ __forceinline__ void prefetch_partials(const RowArgs& a, double (&pv)[4]) {
+  const int lane = threadIdx.x & 63;
+  // a uniform branch around unconditional loads (indices clamped into range; the surplus
+  // masked out at the sum), so no lane-dependent control flow waits on a load
+  if (a.partials != nullptr && a.n_partials <= kPrefetchPartials && blockDim.x >= 64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[k] = a.partials[min(lane + 64 * k, a.n_partials - 1)];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[k] = 0.0;
+  }
+}
+
+__device__ __forceinline__ float row_scale(const RowArgs& a, const double (&pv)[4]) {
   if (a.partials == nullptr) return a.scale;
   double s = 0.0;
   if (blockDim.x >= 64) {
-    const int lane = threadIdx.x & 63;
-    for (int i = lane; i < a.n_partials; i += 64) s += a.partials[i];
+    if (a.n_partials <= kPrefetchPartials) {
+      const int lane = threadIdx.x & 63;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += (lane + 64 * k < a.n_partials) ? pv[k] : 0.0;
+    } else {
+      const int lane = threadIdx.x & 63;
+      for (int i = lane; i < a.n_partials; i += 64) s += a.partials[i];
+    }
     s = wave_sum(s);
   } else {
     for (int i = 0; i < a.n_partials; ++i) s += a.partials[i];
@@ -197,26 +222,37 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) 
   const uint32_t lane_off = static_cast<uint32_t>(t) * 16u + 8u * comp;
   const uint32_t group_stride = static_cast<uint32_t>(a.rows_per_block) * (16u * N);
 
+  double pv[4];
+  if constexpr (MODE != ROW_FWD) prefetch_partials(a, pv);
   float2 v[P], nxt[P];
   uint32_t off = static_cast<uint32_t>(row0) * (16u * N) + lane_off;
+  // Load order: the inverse transform starts with the last forward stage, whose butterfly u
+  // takes positions u + U k; issuing those loads together lets it start before the rest land.
+  constexpr int RL = MODE == ROW_FWD ? P : last_radix<N, P>();
+  constexpr int UL = P / RL;
 #pragma unroll
-  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + off + 16u * T * m);
+  for (int i = 0; i < P; ++i) {
+    const int m = i / RL + UL * (i % RL);
+    v[m] = *reinterpret_cast<const float2*>(base + off + 16u * T * m);
+  }
   TwPlain<N, P> tr;
   load_twiddles<N>(tr, t, a.tw);
   float s = 1.0f;
-  if constexpr (MODE != ROW_FWD) s = row_scale(a);
 
 #pragma unroll
   for (int it = 0; it < ITERS; ++it) {
     if (it + 1 < ITERS) {
 #pragma unroll
-      for (int m = 0; m < P; ++m)
+      for (int i = 0; i < P; ++i) {
+        const int m = i / RL + UL * (i % RL);
         nxt[m] = *reinterpret_cast<const float2*>(base + off + group_stride + 16u * T * m);
+      }
     }
     if constexpr (MODE == ROW_FWD) {
       fwd_pass<N>(v, lds, t, tr);
     } else {
       inv_pass<N>(v, lds, t, tr);
+      if (it == 0) s = row_scale(a, pv);
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
       if constexpr (MODE == ROW_STEP) {
