@@ -11,8 +11,9 @@ in batches of 100 (one step_imag(100) call each) with HIP events; value = K / to
 Prints one JSON line.  Also reports: the dominant kernel's HBM roofline fraction (algorithmic bytes
 over its mean launch time, from back-to-back launches between HIP events on the solver's stream);
 the same physics at 512^2 and 2048^2; the ground-state time-to-solution (wall time until the
-energy is within 1e-6 of the FP64 oracle's converged value, 256^2); and the FP64 oracle's
-throughput on a bounded sample of the 1024^2 workload on the host cores.
+energy is within 1e-6 of the FP64 oracle's converged value, 256^2); the batched parameter sweep
+(96 instances of three sizes, one graph-captured call); and the FP64 oracle's throughput on a
+bounded sample of the 1024^2 workload on the host cores.
 """
 from __future__ import annotations
 
@@ -92,6 +93,49 @@ def other_grids(torch, stream, timed, p, steps=500, warmup=50):
     return res
 
 
+def batched_sweep(torch, stream, steps=500, tune_steps=5):
+    """The batched parameter sweep: 96 instances (32 each of 128^2, 256^2, 512^2; g, Omega,
+    delta drawn from seed 0), 500 imaginary-time steps of all of them in one call.  The per-class
+    schedules come from the library's autotuner; the first call captures the graph, the timed
+    call replays it.  Reported: instance-steps/s, and the roofline fraction on B_alg summed over
+    the instances; the same call with direct launches beside it."""
+    from paper_2010_15069_amd import Batch
+    from workloads import initial_state, sweep_instances
+    ps = sweep_instances(seed=0)
+    b = Batch(ps, stream=stream.cuda_stream)
+    for i, p in enumerate(ps):
+        b.set_psi(i, initial_state(p, "tf", seed=i))
+    t0 = time.perf_counter()
+    tuned_ms = b.autotune(tune_steps)
+    tune_s = time.perf_counter() - t0
+    schedules = {f"{nx}x{ny}": b.get_schedule(k) for k, (nx, ny, _) in enumerate(b.classes())}
+
+    def timed_call():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        b.step_imag(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    t_capture = timed_call()             # captures and runs the graph
+    t_graph = timed_call()               # replays it
+    b.use_graph(False)
+    t_direct = timed_call()
+    pts = sum(p.nx * p.ny for p in ps)
+    e = [b.energy(i) for i in (0, 32, 64)]
+    b.close()
+    return {"workload": "96 instances: 32 x 128^2, 32 x 256^2, 32 x 512^2, g ~ U[1,100], Omega ~ U[0,3], "
+                        "delta ~ U[-0.5,0.5] (seed 0), k_L = 2, imaginary time dt = 1e-3, Thomas-Fermi starts",
+            "steps": steps, "seconds_graph": t_graph, "seconds_direct": t_direct,
+            "seconds_first_call_with_capture": t_capture,
+            "instance_steps_per_s": len(ps) * steps / t_graph,
+            "hbm_roofline_frac": BYTES_PER_POINT_STEP * pts * steps / t_graph / (HBM_PEAK_GBS * 1e9),
+            "autotune_seconds": tune_s, "schedules": schedules,
+            "tuned_ms_per_step_per_class": tuned_ms, "energies_sample": e}
+
+
 def ground_state_time(torch, stream, check_every=50, max_steps=200000):
     """Wall time from set_psi (Thomas-Fermi start) until the energy is within 1e-6 (relative) of
     the FP64 oracle's converged imaginary-time energy for the same workload and time step
@@ -137,6 +181,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ground", action="store_true", help="skip the ground-state time-to-solution")
     ap.add_argument("--no-other-grids", action="store_true", help="skip the 512^2 and 2048^2 lines")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched parameter sweep")
     ap.add_argument("--workload", default="metric_1024")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the HBM "
@@ -255,6 +300,8 @@ def main():
         out["other_grids"] = other_grids(torch, stream, timed, p)
     if not args.no_ground:
         out["ground_state"] = ground_state_time(torch, stream)
+    if not args.no_batch:
+        out["batched_sweep"] = batched_sweep(torch, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -164,6 +164,62 @@ sgpe_status sgpe_get_schedule(sgpe_ctx* ctx, sgpe_schedule* out);
  * compute-unit count).  An unsupported schedule returns SGPE_EINVAL and changes nothing. */
 sgpe_status sgpe_set_schedule(sgpe_ctx* ctx, const sgpe_schedule* schedule);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched parameter sweeps: many independent instances, any mix of grid shapes, stepped
+ * together.  Each instance is a full solver of its own (its parameters, state, norm); instances
+ * of one grid shape and real-space operator form make a class, and each pass of a class is one
+ * launch over all of its members, so classes of small grids fill the device.  Classes run
+ * concurrently on internal streams forked from and joined to the batch stream.  With graphs on
+ * (the default), the launches of a step_* call are captured once per (n, real/imag) into a HIP
+ * graph and replayed on later calls with the same n.
+ *
+ * Results: every instance computes exactly what a single context (sgpe_create) with the same
+ * parameters and schedule computes -- bit-identical.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct sgpe_batch sgpe_batch;
+
+/* count (1..65535) instances with params[i]; the same error cases as sgpe_create for each.
+ * hip_stream as in sgpe_create.  Per-class schedules start at the single-instance defaults for
+ * the class's total point count (row_iters = col_iters = 1: batched launches take one row group
+ * / column tile per workgroup). */
+sgpe_status sgpe_batch_create(const sgpe_params* params, int32_t count, void* hip_stream, sgpe_batch** out);
+void sgpe_batch_destroy(sgpe_batch* batch);
+
+int32_t sgpe_batch_size(const sgpe_batch* batch);          /* instances; 0 for NULL */
+int32_t sgpe_batch_class_count(const sgpe_batch* batch);   /* classes; 0 for NULL */
+/* grid shape and member count of class k; any output may be NULL */
+sgpe_status sgpe_batch_class_info(const sgpe_batch* batch, int32_t k, int32_t* nx, int32_t* ny, int32_t* members);
+/* the class of instance `index` */
+sgpe_status sgpe_batch_instance_class(const sgpe_batch* batch, int32_t index, int32_t* k);
+
+/* Per instance, as sgpe_set_psi / sgpe_get_psi / sgpe_energy / sgpe_norm (index out of range:
+ * SGPE_EINVAL). */
+sgpe_status sgpe_batch_set_psi(sgpe_batch* batch, int32_t index, const double* psi);
+sgpe_status sgpe_batch_get_psi(sgpe_batch* batch, int32_t index, double* psi);
+sgpe_status sgpe_batch_energy(sgpe_batch* batch, int32_t index, double* e_per_particle);
+sgpe_status sgpe_batch_norm(sgpe_batch* batch, int32_t index, double* norm);
+
+/* n steps of every instance (all must have a state: else SGPE_ESTATE); asynchronous on the batch
+ * stream. */
+sgpe_status sgpe_batch_step_real(sgpe_batch* batch, int64_t n);
+sgpe_status sgpe_batch_step_imag(sgpe_batch* batch, int64_t n);
+sgpe_status sgpe_batch_synchronize(sgpe_batch* batch);
+
+/* Graph capture of step calls on (1, default) or off (0: launches are issued directly). */
+sgpe_status sgpe_batch_use_graph(sgpe_batch* batch, int32_t on);
+
+/* Schedule of class k (see sgpe_schedule; row_iters and col_iters must be 1).  NULL restores the
+ * class default.  Synchronises; an unsupported schedule returns SGPE_EINVAL and changes nothing. */
+sgpe_status sgpe_batch_get_schedule(const sgpe_batch* batch, int32_t k, sgpe_schedule* out);
+sgpe_status sgpe_batch_set_schedule(sgpe_batch* batch, int32_t k, const sgpe_schedule* schedule);
+
+/* Autotuner: for every class, time `steps` real-time steps under each supported schedule (points
+ * per lane 4/8/16 in each pass, column tiles 1..16) and keep the fastest.  The instances' states
+ * are saved before and restored after (so results do not depend on tuning); the captured graphs
+ * are dropped.  best_ms, if not NULL, receives one value per class: the chosen schedule's time per
+ * step of that class in milliseconds.  Synchronises. */
+sgpe_status sgpe_batch_autotune(sgpe_batch* batch, int32_t steps, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

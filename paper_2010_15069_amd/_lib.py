@@ -56,6 +56,11 @@ EXPORTS = [
     "sgpe_get_psi", "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
     "sgpe_synchronize", "sgpe_profile_steps", "sgpe_profile_kernels", "sgpe_strerror",
     "sgpe_set_col_tile", "sgpe_get_schedule", "sgpe_set_schedule",
+    "sgpe_batch_create", "sgpe_batch_destroy", "sgpe_batch_size", "sgpe_batch_class_count",
+    "sgpe_batch_class_info", "sgpe_batch_instance_class", "sgpe_batch_set_psi", "sgpe_batch_get_psi",
+    "sgpe_batch_energy", "sgpe_batch_norm", "sgpe_batch_step_real", "sgpe_batch_step_imag",
+    "sgpe_batch_synchronize", "sgpe_batch_use_graph", "sgpe_batch_get_schedule",
+    "sgpe_batch_set_schedule", "sgpe_batch_autotune",
 ]
 
 
@@ -119,6 +124,30 @@ def _lib():
     lib.sgpe_strerror.restype = ctypes.c_char_p
     lib.sgpe_set_col_tile.argtypes = [vp, ctypes.c_int32]
     lib.sgpe_set_col_tile.restype = st
+    i32, i64, PI32 = ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32)
+    batch_sigs = {
+        "sgpe_batch_create": ([P(SgpeParams), i32, vp, P(vp)], st),
+        "sgpe_batch_destroy": ([vp], None),
+        "sgpe_batch_size": ([vp], i32),
+        "sgpe_batch_class_count": ([vp], i32),
+        "sgpe_batch_class_info": ([vp, i32, PI32, PI32, PI32], st),
+        "sgpe_batch_instance_class": ([vp, i32, PI32], st),
+        "sgpe_batch_set_psi": ([vp, i32, vp], st),
+        "sgpe_batch_get_psi": ([vp, i32, vp], st),
+        "sgpe_batch_energy": ([vp, i32, P(ctypes.c_double)], st),
+        "sgpe_batch_norm": ([vp, i32, P(ctypes.c_double)], st),
+        "sgpe_batch_step_real": ([vp, i64], st),
+        "sgpe_batch_step_imag": ([vp, i64], st),
+        "sgpe_batch_synchronize": ([vp], st),
+        "sgpe_batch_use_graph": ([vp, i32], st),
+        "sgpe_batch_get_schedule": ([vp, i32, P(Schedule)], st),
+        "sgpe_batch_set_schedule": ([vp, i32, P(Schedule)], st),
+        "sgpe_batch_autotune": ([vp, i32, P(ctypes.c_double)], st),
+    }
+    for name, (args, res) in batch_sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
     _LIB = lib
     return lib
 

@@ -79,9 +79,10 @@ def build(verbose: bool = False) -> str:
         for src in ("row_pass.hip", "col_pass.hip", "reductions.hip"):
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             jobs.append(([hipcc, "-c"] + HIP_FLAGS + incs + [os.path.join(CSRC, src), "-o", obj], obj))
-        obj = os.path.join(tmp, "api.o")
-        jobs.append(([hipcc, "-c", "-x", "c++"] + HOST_FLAGS + incs +
-                     [os.path.join(CSRC, "api.cpp"), "-o", obj], obj))
+        for src in ("api.cpp", "batch.cpp"):
+            obj = os.path.join(tmp, src.replace(".cpp", ".o"))
+            jobs.append(([hipcc, "-c", "-x", "c++"] + HOST_FLAGS + incs +
+                         [os.path.join(CSRC, src), "-o", obj], obj))
         procs = []
         for cmd, name in jobs:
             if verbose:

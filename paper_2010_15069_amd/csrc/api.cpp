@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "host_internal.hpp"
 #include "sgpe_internal.hpp"
 
 using sgpe::ColArgs;
@@ -19,46 +20,14 @@ namespace {
 
 constexpr int kMinN = 16;
 constexpr int kMaxN = 4096;
-constexpr int kMaxPartials = 4096;
 
 bool is_pow2(int32_t n) { return n > 0 && (n & (n - 1)) == 0; }
 bool is_finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
-struct sgpe_ctx {
-  sgpe_params p{};
-  int device = 0;
-  hipStream_t stream = nullptr;
-  float4* psi = nullptr;
-  bool own_psi = false;
-  float4* scratch = nullptr;
-  float4* tw_x = nullptr;   // compensated roots (energy kernels)
-  float4* tw_y = nullptr;
-  float4* twp_x = nullptr;  // fp32-rounded roots with modulus corrections (step kernels)
-  float4* twp_y = nullptr;
-  // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
-  float4* kx_tab[4] = {nullptr, nullptr, nullptr, nullptr};
-  float2* ky_tab[4] = {nullptr, nullptr, nullptr, nullptr};
-  float* hbx = nullptr;  // dt * Omega(x_j) / 2, only with a spatial Raman coupling
-  double* partials = nullptr;
-  double* epart = nullptr;  // energy partials (row: 2 per block, then col: 1 per block)
-  double* npart = nullptr;  // norm partials
-  size_t max_lds = 0;       // dynamic LDS bytes available per workgroup
-  int rows = 1;             // rows per row-pass workgroup
-  int cols = 1;             // columns per column-pass workgroup
-  int row_iters = 1;        // row groups per row-pass workgroup (the next one prefetched)
-  int col_iters = 1;        // column tiles per column-pass workgroup
-  int row_points = 16;      // points per lane of the x transforms
-  int col_points = 16;      // points per lane of the y transforms
-  int n_cu = 1;             // compute units of the device
-  bool full2x2 = false;
-  bool has_state = false;
-  sgpe_status latched = SGPE_OK;
-  std::vector<void*> allocations;
-};
 
-namespace {
+namespace sgpe_host {
 
 sgpe_status dev_alloc(sgpe_ctx* c, void** ptr, size_t bytes) {
   *ptr = nullptr;
@@ -194,6 +163,34 @@ void default_schedule(sgpe_ctx* c) {
 
 int col_groups(const sgpe_ctx* c) { return c->p.nx / (c->cols * c->col_iters); }
 
+sgpe_status apply_schedule(sgpe_ctx* c, const sgpe_schedule& s) {
+  const sgpe_params& p = c->p;
+  if (s.row_points != 4 && s.row_points != 8 && s.row_points != 16) return SGPE_EINVAL;
+  if (s.col_tile < 1) return SGPE_EINVAL;
+  const int rows = sgpe::row_rows_per_block(p.nx, p.ny, s.row_points, c->max_lds);
+  if (!sgpe::schedule_supported(p.nx, rows, s.row_iters, s.row_points) || p.ny % (rows * s.row_iters) != 0 ||
+      sgpe::row_lds_bytes(p.nx, rows) > c->max_lds)
+    return SGPE_EINVAL;
+  if (!sgpe::col_cols_supported(p.nx, p.ny, s.col_tile, s.col_iters, s.col_points, c->max_lds)) return SGPE_EINVAL;
+  c->rows = rows;
+  c->cols = s.col_tile;
+  c->row_iters = s.row_iters;
+  c->col_iters = s.col_iters;
+  c->row_points = s.row_points;
+  c->col_points = s.col_points;
+  return SGPE_OK;
+}
+
+sgpe_schedule get_schedule(const sgpe_ctx* c) {
+  sgpe_schedule s;
+  s.col_tile = c->cols;
+  s.row_iters = c->row_iters;
+  s.col_iters = c->col_iters;
+  s.row_points = c->row_points;
+  s.col_points = c->col_points;
+  return s;
+}
+
 sgpe_status status_of(hipError_t e) {
   if (e == hipSuccess) return SGPE_OK;
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SGPE_ENOMEM;
@@ -304,7 +301,9 @@ sgpe_status sync_and_latch(sgpe_ctx* c) {
   return c->latched;
 }
 
-}  // namespace
+}  // namespace sgpe_host
+
+using namespace sgpe_host;
 
 extern "C" {
 
@@ -451,11 +450,7 @@ sgpe_status sgpe_set_col_tile(sgpe_ctx* c, int32_t columns) {
 
 sgpe_status sgpe_get_schedule(sgpe_ctx* c, sgpe_schedule* out) {
   if (!c || !out) return SGPE_EINVAL;
-  out->col_tile = c->cols;
-  out->row_iters = c->row_iters;
-  out->col_iters = c->col_iters;
-  out->row_points = c->row_points;
-  out->col_points = c->col_points;
+  *out = get_schedule(c);
   return SGPE_OK;
 }
 
@@ -465,21 +460,7 @@ sgpe_status sgpe_set_schedule(sgpe_ctx* c, const sgpe_schedule* s) {
     default_schedule(c);
     return SGPE_OK;
   }
-  const sgpe_params& p = c->p;
-  if (s->row_points != 4 && s->row_points != 8 && s->row_points != 16) return SGPE_EINVAL;
-  if (s->col_tile < 1) return SGPE_EINVAL;
-  const int rows = sgpe::row_rows_per_block(p.nx, p.ny, s->row_points, c->max_lds);
-  if (!sgpe::schedule_supported(p.nx, rows, s->row_iters, s->row_points) || p.ny % (rows * s->row_iters) != 0 ||
-      sgpe::row_lds_bytes(p.nx, rows) > c->max_lds)
-    return SGPE_EINVAL;
-  if (!sgpe::col_cols_supported(p.nx, p.ny, s->col_tile, s->col_iters, s->col_points, c->max_lds)) return SGPE_EINVAL;
-  c->rows = rows;
-  c->cols = s->col_tile;
-  c->row_iters = s->row_iters;
-  c->col_iters = s->col_iters;
-  c->row_points = s->row_points;
-  c->col_points = s->col_points;
-  return SGPE_OK;
+  return apply_schedule(c, *s);
 }
 
 sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {

@@ -1,0 +1,440 @@
+// Host side of batched parameter sweeps: many independent instances, any mix of grid shapes,
+// stepped together.
+//
+// Instances of one grid shape and one real-space operator form (diagonal, or full 2x2 with a
+// spatial Raman coupling) form a class.  Each pass of a class is one launch over all of its
+// members (blockIdx.y = member), the members' arguments read from a device table, so a class of
+// small grids fills the device where one instance cannot.  Classes run on streams of their own,
+// forked from and joined back to the batch stream, so classes of different sizes overlap.  A
+// call's whole launch sequence can be captured once into a HIP graph and replayed.  Each member
+// computes exactly what a single context with the same schedule computes (the same kernels body,
+// the same arguments, the same order of launches).
+#include "sgpe.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "host_internal.hpp"
+#include "sgpe_internal.hpp"
+
+using sgpe::ColArgs;
+using sgpe::RowArgs;
+using namespace sgpe_host;
+
+namespace {
+
+// Argument table layout of a class with `count` members.
+enum RowVariant { ROWTAB_FWD = 0, ROWTAB_SCALE = 1, ROWTAB_PARTIALS = 2, ROWTAB_N = 3 };
+// column variants: index 2 * imag + half (half: the K(dt/2) of a call's first and last step)
+constexpr int COLTAB_N = 4;
+
+struct BatchClass {
+  int nx = 0, ny = 0;
+  bool full2x2 = false;
+  std::vector<int> members;
+  RowArgs* row_tab = nullptr;   // device, [ROWTAB_N][count]
+  ColArgs* col_tab = nullptr;   // device, [COLTAB_N][count]
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct sgpe_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;       // the caller's stream (may be the null stream)
+  hipStream_t graph_stream = nullptr; // graphs are captured and replayed here, ordered after and
+                                      // before the caller's stream by events (the null stream
+                                      // cannot be captured)
+  std::vector<sgpe_ctx*> inst;
+  std::vector<BatchClass> cls;
+  hipEvent_t fork = nullptr;
+  hipEvent_t enter = nullptr, leave = nullptr;
+  bool use_graph = true;
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (steps, imag) -> executable graph
+};
+
+namespace {
+
+sgpe_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return SGPE_OK;
+  (void)hipGetLastError();
+  return status_of(e);
+}
+
+void drop_graphs(sgpe_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
+// Fill the class's argument tables from its members' contexts (which hold the class schedule).
+sgpe_status build_tables(BatchClass& k, const std::vector<sgpe_ctx*>& inst) {
+  const size_t n = k.members.size();
+  std::vector<RowArgs> rows(ROWTAB_N * n);
+  std::vector<ColArgs> cols(COLTAB_N * n);
+  for (size_t j = 0; j < n; ++j) {
+    const sgpe_ctx* c = inst[k.members[j]];
+    const RowArgs a = row_args(c);
+    RowArgs sc = a;
+    sc.scale = float(1.0 / (double(c->p.nx) * double(c->p.ny)));  // exact: a power of two
+    RowArgs pa = sc;
+    pa.partials = c->partials;
+    pa.n_partials = col_groups(c);
+    rows[ROWTAB_FWD * n + j] = a;
+    rows[ROWTAB_SCALE * n + j] = sc;
+    rows[ROWTAB_PARTIALS * n + j] = pa;
+    for (int imag = 0; imag < 2; ++imag)
+      for (int half = 0; half < 2; ++half) cols[(2 * imag + half) * n + j] = col_args(c, imag != 0, half != 0);
+  }
+  if (hipMemcpy(k.row_tab, rows.data(), rows.size() * sizeof(RowArgs), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(k.col_tab, cols.data(), cols.size() * sizeof(ColArgs), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  return SGPE_OK;
+}
+
+// The fused schedule of n steps for every member of a class, on stream s (the same launch
+// sequence as a single context's).
+hipError_t enqueue_class(const sgpe_batch* b, const BatchClass& k, int64_t n, bool imag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int cnt = int(k.members.size());
+  const sgpe_ctx* c0 = b->inst[k.members[0]];
+  const RowArgs shape_r = row_args(c0);
+  const ColArgs shape_c = col_args(c0, imag, false);
+  const int rp = c0->row_points, cp = c0->col_points;
+  const RowArgs* t_fwd = k.row_tab + ROWTAB_FWD * cnt;
+  const RowArgs* t_sc = k.row_tab + ROWTAB_SCALE * cnt;
+  const RowArgs* t_pa = k.row_tab + ROWTAB_PARTIALS * cnt;
+  auto ctab = [&](bool half) { return k.col_tab + (2 * int(imag) + int(half)) * cnt; };
+  hipError_t e = sgpe::launch_row_batch(shape_r, t_fwd, cnt, sgpe::ROW_FWD, false, false, rp, s);
+  if (e == hipSuccess) e = sgpe::launch_col_batch(shape_c, ctab(true), cnt, sgpe::NORM_NONE, cp, s);
+  for (int64_t i = 1; i <= n && e == hipSuccess; ++i) {
+    e = sgpe::launch_row_batch(shape_r, (imag && i > 1) ? t_pa : t_sc, cnt, sgpe::ROW_STEP, imag, k.full2x2, rp, s);
+    const bool last = (i == n);
+    const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
+    if (e == hipSuccess) e = sgpe::launch_col_batch(shape_c, ctab(last), cnt, nm, cp, s);
+  }
+  if (e == hipSuccess) e = sgpe::launch_row_batch(shape_r, imag ? t_pa : t_sc, cnt, sgpe::ROW_INV, false, false, rp, s);
+  return e;
+}
+
+// All classes, each on its own stream, forked from and joined back to stream `origin`.
+hipError_t enqueue_all(sgpe_batch* b, int64_t n, bool imag, hipStream_t origin) {
+  hipError_t e = hipEventRecord(b->fork, origin);
+  for (auto& k : b->cls) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(k.stream, b->fork, 0);
+    if (e == hipSuccess) e = enqueue_class(b, k, n, imag, k.stream);
+    if (e == hipSuccess) e = hipEventRecord(k.done, k.stream);
+  }
+  for (auto& k : b->cls)
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, k.done, 0);
+  return e;
+}
+
+sgpe_status run(sgpe_batch* b, int64_t n, bool imag) {
+  if (n < 0) return SGPE_EINVAL;
+  if (n == 0) return SGPE_OK;
+  for (const sgpe_ctx* c : b->inst)
+    if (!c->has_state) return SGPE_ESTATE;
+  if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
+  if (!b->use_graph) return hip_status(enqueue_all(b, n, imag, b->stream));
+  const auto key = std::make_pair(n, int(imag));
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->graph_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_status(e);
+    hipError_t e2 = enqueue_all(b, n, imag, b->graph_stream);
+    e = hipStreamEndCapture(b->graph_stream, &g);
+    if (e2 != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_status(e2 != hipSuccess ? e2 : e);
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_status(e);
+    it = b->graphs.emplace(key, x).first;
+  }
+  hipError_t e = hipEventRecord(b->enter, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->graph_stream, b->enter, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(it->second, b->graph_stream);
+  if (e == hipSuccess) e = hipEventRecord(b->leave, b->graph_stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->leave, 0);
+  return hip_status(e);
+}
+
+bool valid_index(const sgpe_batch* b, int32_t i) { return b && i >= 0 && size_t(i) < b->inst.size(); }
+bool valid_class(const sgpe_batch* b, int32_t k) { return b && k >= 0 && size_t(k) < b->cls.size(); }
+
+// Apply one schedule to every member of a class (all or none), then rebuild its tables.
+sgpe_status set_class_schedule(sgpe_batch* b, BatchClass& k, const sgpe_schedule& s) {
+  if (s.row_iters != 1 || s.col_iters != 1) return SGPE_EINVAL;  // batched launches: one tile per workgroup
+  std::vector<sgpe_schedule> old;
+  for (int m : k.members) old.push_back(get_schedule(b->inst[m]));
+  for (size_t j = 0; j < k.members.size(); ++j) {
+    if (apply_schedule(b->inst[k.members[j]], s) != SGPE_OK) {
+      for (size_t r = 0; r < j; ++r) (void)apply_schedule(b->inst[k.members[r]], old[r]);
+      return SGPE_EINVAL;
+    }
+  }
+  drop_graphs(b);
+  return build_tables(k, b->inst);
+}
+
+// Default for a class: the single-instance rule applied to the class's total point count.
+sgpe_schedule class_default(const sgpe_ctx* c0, size_t members) {
+  const size_t total = members * size_t(c0->p.nx) * size_t(c0->p.ny);
+  sgpe_schedule s;
+  s.row_points = default_points(c0->p.nx, total);
+  s.col_points = default_points(c0->p.ny, total);
+  s.row_iters = 1;
+  s.col_iters = 1;
+  s.col_tile = sgpe::col_default_cols(c0->p.nx, c0->p.ny, s.col_points, c0->max_lds);
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+sgpe_status sgpe_batch_create(const sgpe_params* params, int32_t count, void* hip_stream, sgpe_batch** out) {
+  if (!out) return SGPE_EINVAL;
+  *out = nullptr;
+  if (!params || count < 1 || count > 65535) return SGPE_EINVAL;
+  for (int32_t i = 0; i < count; ++i) {
+    const sgpe_status st = sgpe_validate_params(&params[i]);
+    if (st != SGPE_OK) return st;
+  }
+  sgpe_batch* b = new (std::nothrow) sgpe_batch();
+  if (!b) return SGPE_ENOMEM;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  auto fail = [&](sgpe_status s) {
+    sgpe_batch_destroy(b);
+    return s;
+  };
+  for (int32_t i = 0; i < count; ++i) {
+    sgpe_ctx* c = nullptr;
+    const sgpe_status st = sgpe_create(&params[i], hip_stream, nullptr, &c);
+    if (st != SGPE_OK) return fail(st);
+    b->inst.push_back(c);
+  }
+  b->device = b->inst[0]->device;
+  // classes: same grid shape and the same real-space operator form
+  for (int32_t i = 0; i < count; ++i) {
+    const sgpe_ctx* c = b->inst[i];
+    auto it = std::find_if(b->cls.begin(), b->cls.end(), [&](const BatchClass& k) {
+      return k.nx == c->p.nx && k.ny == c->p.ny && k.full2x2 == c->full2x2;
+    });
+    if (it == b->cls.end()) {
+      BatchClass k;
+      k.nx = c->p.nx;
+      k.ny = c->p.ny;
+      k.full2x2 = c->full2x2;
+      b->cls.push_back(k);
+      it = b->cls.end() - 1;
+    }
+    it->members.push_back(i);
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->enter, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->leave, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->graph_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SGPE_EDEVICE);
+  }
+  for (auto& k : b->cls) {
+    const size_t n = k.members.size();
+    if (hipStreamCreateWithFlags(&k.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&k.done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k.row_tab), ROWTAB_N * n * sizeof(RowArgs)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k.col_tab), COLTAB_N * n * sizeof(ColArgs)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SGPE_EDEVICE);
+    }
+    const sgpe_status st = set_class_schedule(b, k, class_default(b->inst[k.members[0]], n));
+    if (st != SGPE_OK) return fail(st);
+  }
+  *out = b;
+  return SGPE_OK;
+}
+
+void sgpe_batch_destroy(sgpe_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  for (auto& k : b->cls) {
+    if (k.stream) (void)hipStreamSynchronize(k.stream);
+    if (k.row_tab) (void)hipFree(k.row_tab);
+    if (k.col_tab) (void)hipFree(k.col_tab);
+    if (k.done) (void)hipEventDestroy(k.done);
+    if (k.stream) (void)hipStreamDestroy(k.stream);
+  }
+  if (b->graph_stream) {
+    (void)hipStreamSynchronize(b->graph_stream);
+    (void)hipStreamDestroy(b->graph_stream);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->enter) (void)hipEventDestroy(b->enter);
+  if (b->leave) (void)hipEventDestroy(b->leave);
+  for (sgpe_ctx* c : b->inst) sgpe_destroy(c);
+  (void)hipGetLastError();
+  delete b;
+}
+
+int32_t sgpe_batch_size(const sgpe_batch* b) { return b ? int32_t(b->inst.size()) : 0; }
+int32_t sgpe_batch_class_count(const sgpe_batch* b) { return b ? int32_t(b->cls.size()) : 0; }
+
+sgpe_status sgpe_batch_class_info(const sgpe_batch* b, int32_t k, int32_t* nx, int32_t* ny, int32_t* members) {
+  if (!valid_class(b, k)) return SGPE_EINVAL;
+  if (nx) *nx = b->cls[k].nx;
+  if (ny) *ny = b->cls[k].ny;
+  if (members) *members = int32_t(b->cls[k].members.size());
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_batch_instance_class(const sgpe_batch* b, int32_t index, int32_t* k) {
+  if (!valid_index(b, index) || !k) return SGPE_EINVAL;
+  for (size_t c = 0; c < b->cls.size(); ++c)
+    for (int m : b->cls[c].members)
+      if (m == index) {
+        *k = int32_t(c);
+        return SGPE_OK;
+      }
+  return SGPE_EINVAL;
+}
+
+sgpe_status sgpe_batch_set_psi(sgpe_batch* b, int32_t index, const double* psi) {
+  if (!valid_index(b, index)) return SGPE_EINVAL;
+  return sgpe_set_psi(b->inst[index], psi);
+}
+
+sgpe_status sgpe_batch_get_psi(sgpe_batch* b, int32_t index, double* psi) {
+  if (!valid_index(b, index)) return SGPE_EINVAL;
+  return sgpe_get_psi(b->inst[index], psi);
+}
+
+sgpe_status sgpe_batch_step_real(sgpe_batch* b, int64_t n) { return b ? run(b, n, false) : SGPE_EINVAL; }
+sgpe_status sgpe_batch_step_imag(sgpe_batch* b, int64_t n) { return b ? run(b, n, true) : SGPE_EINVAL; }
+
+sgpe_status sgpe_batch_energy(sgpe_batch* b, int32_t index, double* e) {
+  if (!valid_index(b, index)) return SGPE_EINVAL;
+  return sgpe_energy(b->inst[index], e);
+}
+
+sgpe_status sgpe_batch_norm(sgpe_batch* b, int32_t index, double* n) {
+  if (!valid_index(b, index)) return SGPE_EINVAL;
+  return sgpe_norm(b->inst[index], n);
+}
+
+sgpe_status sgpe_batch_synchronize(sgpe_batch* b) {
+  if (!b) return SGPE_EINVAL;
+  if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
+  return hip_status(hipStreamSynchronize(b->stream));
+}
+
+sgpe_status sgpe_batch_use_graph(sgpe_batch* b, int32_t on) {
+  if (!b) return SGPE_EINVAL;
+  b->use_graph = (on != 0);
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_batch_get_schedule(const sgpe_batch* b, int32_t k, sgpe_schedule* out) {
+  if (!valid_class(b, k) || !out) return SGPE_EINVAL;
+  *out = get_schedule(b->inst[b->cls[k].members[0]]);
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_batch_set_schedule(sgpe_batch* b, int32_t k, const sgpe_schedule* s) {
+  if (!valid_class(b, k)) return SGPE_EINVAL;
+  if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return hip_status(hipErrorUnknown);
+  BatchClass& c = b->cls[k];
+  return set_class_schedule(b, c, s ? *s : class_default(b->inst[c.members[0]], c.members.size()));
+}
+
+sgpe_status sgpe_batch_autotune(sgpe_batch* b, int32_t steps, double* best_ms) {
+  if (!b || steps < 1) return SGPE_EINVAL;
+  for (const sgpe_ctx* c : b->inst)
+    if (!c->has_state) return SGPE_ESTATE;
+  if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_status(hipErrorOutOfMemory);
+  }
+  sgpe_status st = SGPE_OK;
+  for (size_t ci = 0; ci < b->cls.size() && st == SGPE_OK; ++ci) {
+    BatchClass& k = b->cls[ci];
+    const sgpe_ctx* c0 = b->inst[k.members[0]];
+    const size_t bytes = size_t(c0->p.nx) * size_t(c0->p.ny) * sizeof(float4);
+    // keep the members' states: tuning runs real steps on them
+    std::vector<void*> saved(k.members.size(), nullptr);
+    for (size_t j = 0; j < k.members.size() && st == SGPE_OK; ++j) {
+      if (hipMalloc(&saved[j], bytes) != hipSuccess ||
+          hipMemcpyAsync(saved[j], b->inst[k.members[j]]->psi, bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+        st = hip_status(hipErrorOutOfMemory);
+    }
+    const sgpe_schedule start = get_schedule(c0);
+    sgpe_schedule best = start;
+    float best_t = -1.0f;
+    const int pts[3] = {4, 8, 16};
+    const int tiles[5] = {1, 2, 4, 8, 16};
+    for (int rp : pts)
+      for (int cp : pts)
+        for (int ct : tiles) {
+          if (st != SGPE_OK) break;
+          sgpe_schedule s;
+          s.col_tile = ct;
+          s.row_iters = 1;
+          s.col_iters = 1;
+          s.row_points = rp;
+          s.col_points = cp;
+          if (hipStreamSynchronize(b->stream) != hipSuccess) {
+            st = hip_status(hipErrorUnknown);
+            break;
+          }
+          if (set_class_schedule(b, k, s) != SGPE_OK) continue;  // not valid for this shape
+          hipError_t e = enqueue_class(b, k, 2, false, b->stream);
+          if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+          if (e == hipSuccess) e = enqueue_class(b, k, steps, false, b->stream);
+          if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(t1);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+          if (e != hipSuccess) {
+            st = hip_status(e);
+            break;
+          }
+          if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            best = s;
+          }
+        }
+    if (st == SGPE_OK) st = set_class_schedule(b, k, best_t < 0.0f ? start : best);
+    if (best_ms && best_t >= 0.0f) best_ms[ci] = double(best_t) / double(steps);
+    for (size_t j = 0; j < k.members.size(); ++j) {
+      if (saved[j]) {
+        if (st == SGPE_OK &&
+            hipMemcpyAsync(b->inst[k.members[j]]->psi, saved[j], bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+          st = hip_status(hipErrorUnknown);
+        if (hipStreamSynchronize(b->stream) != hipSuccess && st == SGPE_OK) st = hip_status(hipErrorUnknown);
+        (void)hipFree(saved[j]);
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  drop_graphs(b);
+  return st;
+}
+
+}  // extern "C"

@@ -28,7 +28,7 @@ __device__ __forceinline__ int col_group(int b, int ngroups) {
 // data is loaded into registers before the current tile is transformed.  P points per lane:
 // T = N / P lanes per transform.
 template <int N, int NORM, int ITERS, int P>
-__global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) {
+__device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) {
   extern __shared__ float2 lds_raw[];
   __shared__ double red[64];
   constexpr int T = N / P;
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) 
   const int pair = tid >> 1;
   const int cc = pair & (C - 1);
   const int t = pair / C;
-  const int tile0 = col_group(blockIdx.x, a.nx / (C * ITERS)) * ITERS;
+  const int tile0 = col_group(wg, ngroups) * ITERS;
   const int x0 = tile0 * C + cc;
   const LdsView<float2> lds{lds_raw + 2 * cc + comp, 1 + __builtin_ctz(C)};
   // element (row y) of this lane's component is at byte offset 16 (y nx + x) + 8 comp; 32-bit
@@ -115,19 +115,37 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) 
   }
   if constexpr (NORM != NORM_NONE) {
     const double sum = block_sum(acc, red);
-    if (tid == 0) a.partials[blockIdx.x] = sum;
+    if (tid == 0) a.partials[wg] = sum;
   }
+}
+
+// One instance: workgroup blockIdx.x of the pass.  A batch of instances of one grid shape:
+// instance blockIdx.y, its arguments from a device table.
+template <int N, int NORM, int ITERS, int P>
+__global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) {
+  col_body<N, NORM, ITERS, P>(a, blockIdx.x, gridDim.x);
+}
+
+template <int N, int NORM, int P>
+__global__ void __launch_bounds__(512) col_kernel_batch(const ColArgs* __restrict__ tab) {
+  col_body<N, NORM, 1, P>(tab[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // -------------------------------------------------------------------------------------------
 // Launcher
 // -------------------------------------------------------------------------------------------
 template <int N, int NORM>
-static hipError_t col_launch_t(const ColArgs& a, int iters, int points, hipStream_t s) {
+static hipError_t col_launch_t(const ColArgs& a, const ColArgs* tab, int count, int iters, int points, hipStream_t s) {
   const dim3 block(2 * a.cols * (N / points));
-  const dim3 grid(a.nx / (a.cols * iters));
+  const dim3 grid(a.nx / (a.cols * iters), tab ? count : 1);
   const size_t lds = col_lds_bytes(N, a.cols);
-  if (points == 16) {
+  if (tab) {
+    if (points == 16) hipLaunchKernelGGL((col_kernel_batch<N, NORM, 16>), grid, block, lds, s, tab);
+    else if constexpr (N <= kMaxNSmallP) {
+      if (points == 8) hipLaunchKernelGGL((col_kernel_batch<N, NORM, 8>), grid, block, lds, s, tab);
+      else hipLaunchKernelGGL((col_kernel_batch<N, NORM, 4>), grid, block, lds, s, tab);
+    }
+  } else if (points == 16) {
     if (iters == 2) hipLaunchKernelGGL((col_kernel<N, NORM, 2, 16>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((col_kernel<N, NORM, 1, 16>), grid, block, lds, s, a);
   } else if constexpr (N <= kMaxNSmallP) {
@@ -138,30 +156,42 @@ static hipError_t col_launch_t(const ColArgs& a, int iters, int points, hipStrea
 }
 
 template <int N>
-static hipError_t col_launch_n(const ColArgs& a, int norm, int iters, int points, hipStream_t s) {
+static hipError_t col_launch_n(const ColArgs& a, const ColArgs* tab, int count, int norm, int iters, int points,
+                               hipStream_t s) {
   switch (norm) {
-    case NORM_NONE: return col_launch_t<N, NORM_NONE>(a, iters, points, s);
-    case NORM_DOT: return col_launch_t<N, NORM_DOT>(a, iters, points, s);
-    case NORM_SQ: return col_launch_t<N, NORM_SQ>(a, iters, points, s);
+    case NORM_NONE: return col_launch_t<N, NORM_NONE>(a, tab, count, iters, points, s);
+    case NORM_DOT: return col_launch_t<N, NORM_DOT>(a, tab, count, iters, points, s);
+    case NORM_SQ: return col_launch_t<N, NORM_SQ>(a, tab, count, iters, points, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t col_dispatch(const ColArgs& a, const ColArgs* tab, int count, int norm, int iters, int points,
+                               hipStream_t s) {
+  if (!schedule_supported(a.ny, a.cols, iters, points)) return hipErrorInvalidValue;
+  if (a.nx % (a.cols * iters) != 0) return hipErrorInvalidValue;
+  if (tab && (iters != 1 || count < 1 || count > 65535)) return hipErrorInvalidValue;
+  switch (a.ny) {
+    case 16: return col_launch_n<16>(a, tab, count, norm, iters, points, s);
+    case 32: return col_launch_n<32>(a, tab, count, norm, iters, points, s);
+    case 64: return col_launch_n<64>(a, tab, count, norm, iters, points, s);
+    case 128: return col_launch_n<128>(a, tab, count, norm, iters, points, s);
+    case 256: return col_launch_n<256>(a, tab, count, norm, iters, points, s);
+    case 512: return col_launch_n<512>(a, tab, count, norm, iters, points, s);
+    case 1024: return col_launch_n<1024>(a, tab, count, norm, iters, points, s);
+    case 2048: return col_launch_n<2048>(a, tab, count, norm, iters, points, s);
+    case 4096: return col_launch_n<4096>(a, tab, count, norm, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_col(const ColArgs& a, int norm, int iters, int points, hipStream_t s) {
-  if (!schedule_supported(a.ny, a.cols, iters, points)) return hipErrorInvalidValue;
-  if (a.nx % (a.cols * iters) != 0) return hipErrorInvalidValue;
-  switch (a.ny) {
-    case 16: return col_launch_n<16>(a, norm, iters, points, s);
-    case 32: return col_launch_n<32>(a, norm, iters, points, s);
-    case 64: return col_launch_n<64>(a, norm, iters, points, s);
-    case 128: return col_launch_n<128>(a, norm, iters, points, s);
-    case 256: return col_launch_n<256>(a, norm, iters, points, s);
-    case 512: return col_launch_n<512>(a, norm, iters, points, s);
-    case 1024: return col_launch_n<1024>(a, norm, iters, points, s);
-    case 2048: return col_launch_n<2048>(a, norm, iters, points, s);
-    case 4096: return col_launch_n<4096>(a, norm, iters, points, s);
-    default: return hipErrorInvalidValue;
-  }
+  return col_dispatch(a, nullptr, 1, norm, iters, points, s);
+}
+
+hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count, int norm, int points, hipStream_t s) {
+  if (!tab) return hipErrorInvalidValue;
+  return col_dispatch(shape, tab, count, norm, 1, points, s);
 }
 
 }  // namespace sgpe

@@ -1,0 +1,62 @@
+// Host-side internals shared by the single-instance API (api.cpp) and the batch API (batch.cpp):
+// the context of one solver instance and the helpers that build its launch arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "sgpe.h"
+#include "sgpe_internal.hpp"
+
+// One solver instance: its parameters, device buffers and tables, and its launch schedule.
+struct sgpe_ctx {
+  sgpe_params p{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  float4* psi = nullptr;
+  bool own_psi = false;
+  float4* scratch = nullptr;
+  float4* tw_x = nullptr;   // compensated roots (energy kernels)
+  float4* tw_y = nullptr;
+  float4* twp_x = nullptr;  // fp32-rounded roots with modulus corrections (step kernels)
+  float4* twp_y = nullptr;
+  // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
+  float4* kx_tab[4] = {nullptr, nullptr, nullptr, nullptr};
+  float2* ky_tab[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* hbx = nullptr;  // dt * Omega(x_j) / 2, only with a spatial Raman coupling
+  double* partials = nullptr;
+  double* epart = nullptr;  // energy partials (row: 2 per block, then col: 1 per block)
+  double* npart = nullptr;  // norm partials
+  size_t max_lds = 0;       // dynamic LDS bytes available per workgroup
+  int rows = 1;             // rows per row-pass workgroup
+  int cols = 1;             // columns per column-pass workgroup
+  int row_iters = 1;        // row groups per row-pass workgroup (the next one prefetched)
+  int col_iters = 1;        // column tiles per column-pass workgroup
+  int row_points = 16;      // points per lane of the x transforms
+  int col_points = 16;      // points per lane of the y transforms
+  int n_cu = 1;             // compute units of the device
+  bool full2x2 = false;
+  bool has_state = false;
+  sgpe_status latched = SGPE_OK;
+  std::vector<void*> allocations;
+};
+
+namespace sgpe_host {
+
+constexpr int kMaxPartials = 4096;   // norm partials per column pass (one per workgroup)
+
+sgpe_status dev_alloc(sgpe_ctx* c, void** ptr, size_t bytes);
+sgpe_status status_of(hipError_t e);
+void default_schedule(sgpe_ctx* c);
+int default_points(int n, size_t npts);   // points per lane for a transform of length n, npts points in all
+int col_groups(const sgpe_ctx* c);
+sgpe_status apply_schedule(sgpe_ctx* c, const sgpe_schedule& s);   // validated; EINVAL changes nothing
+sgpe_schedule get_schedule(const sgpe_ctx* c);
+sgpe::RowArgs row_args(const sgpe_ctx* c);
+sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
+sgpe_status check_ctx(sgpe_ctx* c);
+sgpe_status sync_and_latch(sgpe_ctx* c);
+
+}  // namespace sgpe_host

@@ -204,7 +204,7 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
 // data is loaded into registers before the current group is transformed, so its memory latency
 // hides behind this group's arithmetic.  P points per lane: T = N / P lanes per transform.
 template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
-__global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) {
+__device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
   extern __shared__ float2 lds_raw[];
   constexpr int T = N / P;
   constexpr int SLOTS = N + N / 16;
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) 
   const int pair = tid >> 1;
   const int rloc = pair / T;
   const int t = pair - rloc * T;
-  const int row0 = blockIdx.x * ITERS * a.rows_per_block + rloc;
+  const int row0 = wg * ITERS * a.rows_per_block + rloc;
   const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
   // element `pos` of this lane's component is at byte offset 16 pos from the row start; 32-bit
   // offsets from a wave-uniform base
@@ -270,15 +270,33 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) 
   }
 }
 
+// One instance: workgroup blockIdx.x of the pass.  A batch of instances of one grid shape:
+// instance blockIdx.y, its arguments from a device table.
+template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
+__global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) {
+  row_body<N, MODE, IMAG, FULL, ITERS, P>(a, blockIdx.x);
+}
+
+template <int N, int MODE, bool IMAG, bool FULL, int P>
+__global__ void __launch_bounds__(512) row_kernel_batch(const RowArgs* __restrict__ tab) {
+  row_body<N, MODE, IMAG, FULL, 1, P>(tab[blockIdx.y], blockIdx.x);
+}
+
 // -------------------------------------------------------------------------------------------
 // Launcher
 // -------------------------------------------------------------------------------------------
 template <int N, int MODE, bool IMAG, bool FULL>
-static hipError_t row_launch_t(const RowArgs& a, int iters, int points, hipStream_t s) {
+static hipError_t row_launch_t(const RowArgs& a, const RowArgs* tab, int count, int iters, int points, hipStream_t s) {
   const dim3 block(2 * a.rows_per_block * (N / points));
-  const dim3 grid(a.ny / (a.rows_per_block * iters));
+  const dim3 grid(a.ny / (a.rows_per_block * iters), tab ? count : 1);
   const size_t lds = row_lds_bytes(N, a.rows_per_block);
-  if (points == 16) {
+  if (tab) {
+    if (points == 16) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 16>), grid, block, lds, s, tab);
+    else if constexpr (N <= kMaxNSmallP) {
+      if (points == 8) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 8>), grid, block, lds, s, tab);
+      else hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 4>), grid, block, lds, s, tab);
+    }
+  } else if (points == 16) {
     if (iters == 2) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 2, 16>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 16>), grid, block, lds, s, a);
   } else if constexpr (N <= kMaxNSmallP) {
@@ -289,34 +307,47 @@ static hipError_t row_launch_t(const RowArgs& a, int iters, int points, hipStrea
 }
 
 template <int N>
-static hipError_t row_launch_n(const RowArgs& a, int mode, bool imag, bool full, int iters, int points, hipStream_t s) {
+static hipError_t row_launch_n(const RowArgs& a, const RowArgs* tab, int count, int mode, bool imag, bool full,
+                               int iters, int points, hipStream_t s) {
   switch (mode) {
-    case ROW_FWD: return row_launch_t<N, ROW_FWD, false, false>(a, iters, points, s);
-    case ROW_INV: return row_launch_t<N, ROW_INV, false, false>(a, iters, points, s);
+    case ROW_FWD: return row_launch_t<N, ROW_FWD, false, false>(a, tab, count, iters, points, s);
+    case ROW_INV: return row_launch_t<N, ROW_INV, false, false>(a, tab, count, iters, points, s);
     case ROW_STEP:
-      if (imag) return full ? row_launch_t<N, ROW_STEP, true, true>(a, iters, points, s)
-                            : row_launch_t<N, ROW_STEP, true, false>(a, iters, points, s);
-      return full ? row_launch_t<N, ROW_STEP, false, true>(a, iters, points, s)
-                  : row_launch_t<N, ROW_STEP, false, false>(a, iters, points, s);
+      if (imag) return full ? row_launch_t<N, ROW_STEP, true, true>(a, tab, count, iters, points, s)
+                            : row_launch_t<N, ROW_STEP, true, false>(a, tab, count, iters, points, s);
+      return full ? row_launch_t<N, ROW_STEP, false, true>(a, tab, count, iters, points, s)
+                  : row_launch_t<N, ROW_STEP, false, false>(a, tab, count, iters, points, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t row_dispatch(const RowArgs& a, const RowArgs* tab, int count, int mode, bool imag, bool full,
+                               int iters, int points, hipStream_t s) {
+  if (!schedule_supported(a.nx, a.rows_per_block, iters, points)) return hipErrorInvalidValue;
+  if (a.ny % (a.rows_per_block * iters) != 0) return hipErrorInvalidValue;
+  if (tab && (iters != 1 || count < 1 || count > 65535)) return hipErrorInvalidValue;
+  switch (a.nx) {
+    case 16: return row_launch_n<16>(a, tab, count, mode, imag, full, iters, points, s);
+    case 32: return row_launch_n<32>(a, tab, count, mode, imag, full, iters, points, s);
+    case 64: return row_launch_n<64>(a, tab, count, mode, imag, full, iters, points, s);
+    case 128: return row_launch_n<128>(a, tab, count, mode, imag, full, iters, points, s);
+    case 256: return row_launch_n<256>(a, tab, count, mode, imag, full, iters, points, s);
+    case 512: return row_launch_n<512>(a, tab, count, mode, imag, full, iters, points, s);
+    case 1024: return row_launch_n<1024>(a, tab, count, mode, imag, full, iters, points, s);
+    case 2048: return row_launch_n<2048>(a, tab, count, mode, imag, full, iters, points, s);
+    case 4096: return row_launch_n<4096>(a, tab, count, mode, imag, full, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full, int iters, int points, hipStream_t s) {
-  if (!schedule_supported(a.nx, a.rows_per_block, iters, points)) return hipErrorInvalidValue;
-  if (a.ny % (a.rows_per_block * iters) != 0) return hipErrorInvalidValue;
-  switch (a.nx) {
-    case 16: return row_launch_n<16>(a, mode, imag, full, iters, points, s);
-    case 32: return row_launch_n<32>(a, mode, imag, full, iters, points, s);
-    case 64: return row_launch_n<64>(a, mode, imag, full, iters, points, s);
-    case 128: return row_launch_n<128>(a, mode, imag, full, iters, points, s);
-    case 256: return row_launch_n<256>(a, mode, imag, full, iters, points, s);
-    case 512: return row_launch_n<512>(a, mode, imag, full, iters, points, s);
-    case 1024: return row_launch_n<1024>(a, mode, imag, full, iters, points, s);
-    case 2048: return row_launch_n<2048>(a, mode, imag, full, iters, points, s);
-    case 4096: return row_launch_n<4096>(a, mode, imag, full, iters, points, s);
-    default: return hipErrorInvalidValue;
-  }
+  return row_dispatch(a, nullptr, 1, mode, imag, full, iters, points, s);
+}
+
+hipError_t launch_row_batch(const RowArgs& shape, const RowArgs* tab, int count, int mode, bool imag, bool full,
+                            int points, hipStream_t s) {
+  if (!tab) return hipErrorInvalidValue;
+  return row_dispatch(shape, tab, count, mode, imag, full, 1, points, s);
 }
 
 }  // namespace sgpe

@@ -82,6 +82,13 @@ inline bool schedule_supported(int n, int groups, int iters, int points) {
 
 hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full2x2, int iters, int points, hipStream_t s);
 hipError_t launch_col(const ColArgs& a, int norm_mode, int iters, int points, hipStream_t s);
+// Batches of instances of one grid shape: `shape` gives the geometry (every table entry must
+// share nx, ny, rows_per_block / cols); instance i's arguments are tab[i] (device memory), and
+// it is blockIdx.y = i of one launch.  One row group / column tile per workgroup.
+hipError_t launch_row_batch(const RowArgs& shape, const RowArgs* tab, int count, int mode, bool imag, bool full2x2,
+                            int points, hipStream_t s);
+hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count, int norm_mode, int points,
+                            hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 

@@ -122,6 +122,114 @@ class Solver:
         return self
 
 
+class Batch:
+    """Many independent solver instances (any mix of grid shapes) stepped together; see the
+    sgpe_batch_* calls in include/sgpe.h.  ``params``: a sequence of parameter objects/dicts."""
+
+    def __init__(self, params, stream=None):
+        self._lib = lib()
+        self.params = list(params)
+        n = len(self.params)
+        arr = (SgpeParams * n)(*[SgpeParams.from_obj(p) for p in self.params])
+        self._shapes = [(int(a.ny), int(a.nx)) for a in arr]
+        self._b = ctypes.c_void_p()
+        check(self._lib.sgpe_batch_create(arr, n, ctypes.c_void_p(stream or 0), ctypes.byref(self._b)),
+              "sgpe_batch_create")
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._lib.sgpe_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return int(self._lib.sgpe_batch_size(self._b))
+
+    def classes(self):
+        """[(nx, ny, members)] per class."""
+        out = []
+        for k in range(int(self._lib.sgpe_batch_class_count(self._b))):
+            nx, ny, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            check(self._lib.sgpe_batch_class_info(self._b, k, ctypes.byref(nx), ctypes.byref(ny),
+                                                  ctypes.byref(m)), "sgpe_batch_class_info")
+            out.append((nx.value, ny.value, m.value))
+        return out
+
+    def instance_class(self, i):
+        k = ctypes.c_int32()
+        check(self._lib.sgpe_batch_instance_class(self._b, int(i), ctypes.byref(k)), "sgpe_batch_instance_class")
+        return k.value
+
+    def set_psi(self, i, psi):
+        ny, nx = self._shapes[i]
+        a = np.ascontiguousarray(np.asarray(psi), dtype=np.complex128)
+        if a.shape != (2, ny, nx):
+            raise ValueError(f"psi must have shape (2, {ny}, {nx}), got {a.shape}")
+        check(self._lib.sgpe_batch_set_psi(self._b, int(i), a.ctypes.data_as(ctypes.c_void_p)), "sgpe_batch_set_psi")
+        return self
+
+    def get_psi(self, i):
+        ny, nx = self._shapes[i]
+        out = np.empty((2, ny, nx), dtype=np.complex128)
+        check(self._lib.sgpe_batch_get_psi(self._b, int(i), out.ctypes.data_as(ctypes.c_void_p)),
+              "sgpe_batch_get_psi")
+        return out
+
+    def step_real(self, n):
+        check(self._lib.sgpe_batch_step_real(self._b, int(n)), "sgpe_batch_step_real")
+        return self
+
+    def step_imag(self, n):
+        check(self._lib.sgpe_batch_step_imag(self._b, int(n)), "sgpe_batch_step_imag")
+        return self
+
+    def synchronize(self):
+        check(self._lib.sgpe_batch_synchronize(self._b), "sgpe_batch_synchronize")
+        return self
+
+    def energy(self, i) -> float:
+        v = ctypes.c_double()
+        check(self._lib.sgpe_batch_energy(self._b, int(i), ctypes.byref(v)), "sgpe_batch_energy")
+        return v.value
+
+    def norm(self, i) -> float:
+        v = ctypes.c_double()
+        check(self._lib.sgpe_batch_norm(self._b, int(i), ctypes.byref(v)), "sgpe_batch_norm")
+        return v.value
+
+    def use_graph(self, on=True):
+        check(self._lib.sgpe_batch_use_graph(self._b, 1 if on else 0), "sgpe_batch_use_graph")
+        return self
+
+    def get_schedule(self, k) -> dict:
+        sc = Schedule()
+        check(self._lib.sgpe_batch_get_schedule(self._b, int(k), ctypes.byref(sc)), "sgpe_batch_get_schedule")
+        return {name: int(getattr(sc, name)) for name, _ in Schedule._fields_}
+
+    def set_schedule(self, k, schedule=None, **fields):
+        if schedule is None and not fields:
+            check(self._lib.sgpe_batch_set_schedule(self._b, int(k), None), "sgpe_batch_set_schedule")
+            return self
+        cur = self.get_schedule(k)
+        cur.update(schedule or {})
+        cur.update(fields)
+        sc = Schedule(**{key: int(v) for key, v in cur.items()})
+        check(self._lib.sgpe_batch_set_schedule(self._b, int(k), ctypes.byref(sc)), "sgpe_batch_set_schedule")
+        return self
+
+    def autotune(self, steps=10):
+        """Per class: the fastest schedule over the supported set (states kept); returns the
+        chosen per-class time per step in ms."""
+        ms = (ctypes.c_double * max(1, len(self.classes())))()
+        check(self._lib.sgpe_batch_autotune(self._b, int(steps), ms), "sgpe_batch_autotune")
+        return list(ms)
+
+
 def device_count() -> int:
     return int(lib().sgpe_device_count())
 

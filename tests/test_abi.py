@@ -123,3 +123,43 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libsgpe.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_schedule_struct_matches_header():
+    from paper_2010_15069_amd._lib import Schedule
+    body = re.search(r"typedef struct \{([^{}]*)\} sgpe_schedule;", open(HEADER).read()).group(1)
+    names = [n.strip() for n in re.findall(r"^\s*int32_t\s+([^;]+);", body, flags=re.M)]
+    assert names == [f[0] for f in Schedule._fields_]
+    assert ctypes.sizeof(Schedule) == 4 * len(names)
+
+
+def test_batch_null_and_invalid_arguments(lib):
+    from paper_2010_15069_amd import SgpeParams
+    out = ctypes.c_void_p(1234)
+    assert lib.sgpe_batch_create(None, 1, None, ctypes.byref(out)) == 1
+    p = (SgpeParams * 2)(SgpeParams.from_obj(Params()), SgpeParams.from_obj(Params(nx=100)))
+    out = ctypes.c_void_p(1234)
+    assert lib.sgpe_batch_create(p, 2, None, ctypes.byref(out)) == 1      # second instance invalid
+    assert out.value is None
+    assert lib.sgpe_batch_create(p, 0, None, ctypes.byref(out)) == 1      # empty batch
+    lib.sgpe_batch_destroy(None)
+    assert lib.sgpe_batch_size(None) == 0 and lib.sgpe_batch_class_count(None) == 0
+    assert lib.sgpe_batch_step_imag(None, 1) == 1
+    assert lib.sgpe_batch_step_real(None, 1) == 1
+    assert lib.sgpe_batch_synchronize(None) == 1
+    assert lib.sgpe_batch_set_psi(None, 0, None) == 1
+    d = ctypes.c_double()
+    assert lib.sgpe_batch_energy(None, 0, ctypes.byref(d)) == 1
+    assert lib.sgpe_batch_autotune(None, 1, None) == 1
+
+
+def test_sweep_instances_are_seeded_and_in_range():
+    from workloads import sweep_instances
+    a, b = sweep_instances(seed=4), sweep_instances(seed=4)
+    assert [x.as_dict() for x in a] == [x.as_dict() for x in b]
+    assert [p.nx for p in a] == [128] * 32 + [256] * 32 + [512] * 32
+    for p in a:
+        assert 1.0 <= p.g_uu <= 100.0 and p.g_uu == p.g_dd == p.g_ud
+        assert 0.0 <= p.omega <= 3.0 and -0.5 <= p.delta <= 0.5
+        assert p.k_l == 2.0 and p.dt == 1e-3 and p.omega_r0 == 0.0
+    assert len({p.g_uu for p in a}) == 96

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Params", "PRESETS", "preset", "grid_axes",
-    "gaussian_state", "thomas_fermi_state", "initial_state", "round_to_c64",
+    "gaussian_state", "thomas_fermi_state", "initial_state", "round_to_c64", "sweep_instances",
 ]
 
 
@@ -156,3 +156,20 @@ def initial_state(p: Params, kind: str = "tf", seed: int = 0, noise: float = 1e-
     else:
         raise ValueError(f"unknown initial state kind {kind!r}")
     return round_to_c64(psi)
+
+
+def sweep_instances(seed: int = 0, sizes=(128, 256, 512), per_size: int = 32) -> list:
+    """A batched parameter sweep: per_size instances of each grid size (n x n on [-8, 8)^2,
+    isotropic trap), in that order.  Per instance, drawn from default_rng(seed) in the order
+    (g, Omega, delta): one interaction strength g ~ U[1, 100] for all three couplings, a uniform
+    Raman coupling Omega ~ U[0, 3] (k-space), a detuning delta ~ U[-0.5, 0.5]; k_L = 2 and
+    imaginary-time step 1e-3 for all."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        for _ in range(per_size):
+            g = float(rng.uniform(1.0, 100.0))
+            om = float(rng.uniform(0.0, 3.0))
+            de = float(rng.uniform(-0.5, 0.5))
+            out.append(Params(nx=n, ny=n, g_uu=g, g_dd=g, g_ud=g, k_l=2.0, omega=om, delta=de, dt=1e-3))
+    return out
