@@ -143,7 +143,7 @@ sgpe_status sgpe_set_col_tile(sgpe_ctx* ctx, int32_t columns);
  * schedule; imaginary-time results differ only in the grouping of the fp64 norm partials.
  *   col_tile    columns per column-pass workgroup (power of two)
  *   row_iters   row groups per row-pass workgroup, 1 or 2: with 2, the next group's data is loaded
- *               while the current one is transformed (16 points per lane, <= 256 threads)
+ *               while the current one is transformed (8 or 16 points per lane, <= 256 threads)
  *   col_iters   the same for column tiles
  *   row_points  points per lane of the x transforms: 16, or 8 / 4 when nx <= 1024
  *   col_points  the same for the y transforms and ny

@@ -149,7 +149,8 @@ static hipError_t col_launch_t(const ColArgs& a, const ColArgs* tab, int count, 
     if (iters == 2) hipLaunchKernelGGL((col_kernel<N, NORM, 2, 16>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((col_kernel<N, NORM, 1, 16>), grid, block, lds, s, a);
   } else if constexpr (N <= kMaxNSmallP) {
-    if (points == 8) hipLaunchKernelGGL((col_kernel<N, NORM, 1, 8>), grid, block, lds, s, a);
+    if (points == 8 && iters == 2) hipLaunchKernelGGL((col_kernel<N, NORM, 2, 8>), grid, block, lds, s, a);
+    else if (points == 8) hipLaunchKernelGGL((col_kernel<N, NORM, 1, 8>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((col_kernel<N, NORM, 1, 4>), grid, block, lds, s, a);
   }
   return hipGetLastError();

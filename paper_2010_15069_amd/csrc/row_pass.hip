@@ -300,7 +300,8 @@ static hipError_t row_launch_t(const RowArgs& a, const RowArgs* tab, int count, 
     if (iters == 2) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 2, 16>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 16>), grid, block, lds, s, a);
   } else if constexpr (N <= kMaxNSmallP) {
-    if (points == 8) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 8>), grid, block, lds, s, a);
+    if (points == 8 && iters == 2) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 2, 8>), grid, block, lds, s, a);
+    else if (points == 8) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 8>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 1, 4>), grid, block, lds, s, a);
   }
   return hipGetLastError();

@@ -69,13 +69,13 @@ struct EnergyArgs {
 // Pass geometry.  points: points per lane of the transforms (16; 8 or 4 for lengths up to
 // kMaxNSmallP, where more lanes shorten each lane's instruction stream); groups: rows (row pass)
 // or columns (column pass) per workgroup; iters: row groups / column tiles per workgroup, 1 or 2
-// (the next one prefetched while this one runs; 16 points per lane, at most 256 threads).
+// (the next one prefetched while this one runs; 8 or 16 points per lane, at most 256 threads).
 constexpr int kMaxNSmallP = 1024;
 inline bool schedule_supported(int n, int groups, int iters, int points) {
   if (points != 16 && !((points == 8 || points == 4) && n <= kMaxNSmallP)) return false;
   if (n < points || groups < 1 || (groups & (groups - 1)) != 0) return false;
   if (iters != 1 && iters != 2) return false;
-  if (iters == 2 && points != 16) return false;
+  if (iters == 2 && points == 4) return false;
   const int threads = 2 * groups * (n / points);
   return threads <= (iters == 2 ? 256 : 512);
 }
