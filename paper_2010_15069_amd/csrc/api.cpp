@@ -65,17 +65,17 @@ std::vector<float4> twiddles(int n) {
   return t;
 }
 
-// Roots exp(-2 pi i j / n) rounded once to fp32 as {cos, sin, cos eta, sin eta}, where
+// Roots exp(-2 pi i j / n) rounded once to fp32 as {cos, sin, eta, 0}, where
 // 1 + eta = 1 / (cos^2 + sin^2) of the rounded pair (evaluated in fp64): the step kernels'
 // forward transform multiplies by the rounded root, their exact inverse by conj(root)(1 + eta),
-// whose low part conj(root) eta is the second pair.
+// whose low part conj(root) eta they form from cos, sin and eta.
 std::vector<float4> twiddles_plain(int n) {
   std::vector<float4> t(n);
   for (int j = 0; j < n; ++j) {
     const double a = 2.0 * M_PI * double(j) / double(n);
     const float c = float(std::cos(a)), s = float(std::sin(a));
     const double eta = 1.0 / (double(c) * double(c) + double(s) * double(s)) - 1.0;
-    t[j] = make_float4(c, s, float(double(c) * eta), float(double(s) * eta));
+    t[j] = make_float4(c, s, float(eta), 0.0f);
   }
   return t;
 }

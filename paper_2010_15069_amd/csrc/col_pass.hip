@@ -62,7 +62,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
     if (k * nth < N) kyv[k] = a.ky_tab[min(tid + k * nth, N - 1)];
   float2 v[P], nxt[P];
 #pragma unroll
-  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + off + mstride * m);
+  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + (off + mstride * m));
   // this component's row of M' - 1 at k_x: {d_own, d_other}
   float4 d = a.kx_tab[2 * x0 + comp], dn = d;
   TwPlain<N, P> tr;
@@ -78,7 +78,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m)
-        nxt[m] = *reinterpret_cast<const float2*>(base + off + tile_stride + mstride * m);
+        nxt[m] = *reinterpret_cast<const float2*>(base + (off + tile_stride + mstride * m));
       dn = a.kx_tab[2 * (x0 + (it + 1) * C) + comp];
     }
     fwd_pass<N>(v, lds, t, tr);
@@ -105,7 +105,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
     inv_pass<N>(v, lds, t, tr);
 
 #pragma unroll
-    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + off + mstride * m) = v[m];
+    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + (off + mstride * m)) = v[m];
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = nxt[m];

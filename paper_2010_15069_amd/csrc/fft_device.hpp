@@ -467,14 +467,16 @@ constexpr int last_radix() {
   else return last_radix<N, P, L * P>();
 }
 
-// Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and the low part
-// (cos, sin) eta of its exact inverse; table entries are float4 {cos, sin, cos eta, sin eta} of
-// exp(-2 pi i j / N).  Loaded once per kernel (they depend only on the thread index).
+// Per-thread stage roots for the step kernels: fp32 (cos, sin) of each root and eta, where
+// 1 + eta = 1/|root|^2 of the rounded pair; the inverse forms its low part (cos, sin) eta with two
+// products at use (its rounding, ~1e-15, lies far below the fp32 rounding it feeds).  Table
+// entries are float4 {cos, sin, eta, 0} of exp(-2 pi i j / N).  Loaded once per kernel (they
+// depend only on the thread index); three registers per root.
 template <int N, int P = 16>
 struct TwPlain {
   static constexpr int COUNT = tw_count_p<N, P>() > 0 ? tw_count_p<N, P>() : 1;
   float2 cs[COUNT];
-  float2 lo[COUNT];
+  float eta[COUNT];
 };
 
 template <int N, int P, int L = 1, int BASE = 0>
@@ -493,7 +495,7 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N, P>& tr, int t, const fl
       for (int r = 1; r < R; ++r) {
         const float4 w = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(tw) + o * r);
         tr.cs[BASE + u * (R - 1) + (r - 1)] = make_float2(w.x, w.y);
-        tr.lo[BASE + u * (R - 1) + (r - 1)] = make_float2(w.z, w.w);
+        tr.eta[BASE + u * (R - 1) + (r - 1)] = w.z;
       }
     }
   }
@@ -534,22 +536,8 @@ __device__ __forceinline__ void pf_stage(float2 (&v)[P], const LdsView<float2>& 
   }
 }
 
-// Ordering of the LDS exchanges between stages: a workgroup barrier, or -- when every transform
-// lies inside one wave (WSYNC) -- a wave-level fence: one wave's LDS operations complete in
-// issue order, so only the compiler's reordering has to be prevented.
-template <bool WSYNC>
-__device__ __forceinline__ void lds_sync() {
-  if constexpr (WSYNC) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
 // Forward length-N transform (positions t + T*m in and out), plain roots.
-template <int N, bool WSYNC = false, int L = 1, int BASE = 0, int P>
+template <int N, int L = 1, int BASE = 0, int P>
 __device__ __forceinline__ void fwd_pass(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= P ? P : REM;
@@ -557,12 +545,12 @@ __device__ __forceinline__ void fwd_pass(float2 (&v)[P], const LdsView<float2>& 
   constexpr int T = N / P;
   pf_stage<N, P, R, L, LAST, BASE>(v, lds, t, tr);
   if constexpr (!LAST) {
-    lds_sync<WSYNC>();
+    __syncthreads();
 #pragma unroll
     for (int m = 0; m < P; ++m) v[m] = lds.at(t + T * m);
-    lds_sync<WSYNC>();
+    __syncthreads();
     constexpr int NEXT = BASE + (L > 1 ? (P / R) * (R - 1) : 0);
-    fwd_pass<N, WSYNC, L * R, NEXT>(v, lds, t, tr);
+    fwd_pass<N, L * R, NEXT>(v, lds, t, tr);
   }
 }
 
@@ -590,8 +578,8 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[P], const LdsView<float2>& 
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const float2 w = tr.cs[BASE + u * (R - 1) + (r - 1)];
-        const float2 l = tr.lo[BASE + u * (R - 1) + (r - 1)];
-        a[r] = pi_cmul(a[r], w.x, w.y, l.x, l.y);
+        const float eta = tr.eta[BASE + u * (R - 1) + (r - 1)];
+        a[r] = pi_cmul(a[r], w.x, w.y, w.x * eta, w.y * eta);
       }
     }
 #pragma unroll
@@ -601,7 +589,7 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[P], const LdsView<float2>& 
 
 // Exact inverse of fwd_pass, times N: the stages undone in reverse order.  All threads of the
 // workgroup call it; on return every LDS read is complete.
-template <int N, bool WSYNC = false, int L = 1, int BASE = 0, int P>
+template <int N, int L = 1, int BASE = 0, int P>
 __device__ __forceinline__ void inv_pass(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= P ? P : REM;
@@ -611,13 +599,13 @@ __device__ __forceinline__ void inv_pass(float2 (&v)[P], const LdsView<float2>& 
     pi_stage<N, P, R, L, true, BASE>(v, lds, t, tr);
   } else {
     constexpr int NEXT = BASE + (L > 1 ? (P / R) * (R - 1) : 0);
-    inv_pass<N, WSYNC, L * R, NEXT>(v, lds, t, tr);
+    inv_pass<N, L * R, NEXT>(v, lds, t, tr);
     // undo "read positions t + T m from LDS", then this stage
 #pragma unroll
     for (int m = 0; m < P; ++m) lds.at(t + T * m) = v[m];
-    lds_sync<WSYNC>();
+    __syncthreads();
     pi_stage<N, P, R, L, false, BASE>(v, lds, t, tr);
-    lds_sync<WSYNC>();
+    __syncthreads();
   }
 }
 

@@ -233,7 +233,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int m = i / RL + UL * (i % RL);
-    v[m] = *reinterpret_cast<const float2*>(base + off + 16u * T * m);
+    v[m] = *reinterpret_cast<const float2*>(base + (off + 16u * T * m));
   }
   TwPlain<N, P> tr;
   load_twiddles<N>(tr, t, a.tw);
@@ -245,7 +245,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const int m = i / RL + UL * (i % RL);
-        nxt[m] = *reinterpret_cast<const float2*>(base + off + group_stride + 16u * T * m);
+        nxt[m] = *reinterpret_cast<const float2*>(base + (off + group_stride + 16u * T * m));
       }
     }
     if constexpr (MODE == ROW_FWD) {
@@ -261,7 +261,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
       }
     }
 #pragma unroll
-    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + off + 16u * T * m) = v[m];
+    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + (off + 16u * T * m)) = v[m];
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = nxt[m];
