@@ -5,5 +5,6 @@ package.  It shares no code with the HIP path; both sides only share the seeded 
 generators in ``workloads``.
 """
 from .gpe import OracleGPE, exp2x2, apply2x2
+from .observables import phase_separation, population_radius, winding
 
-__all__ = ["OracleGPE", "exp2x2", "apply2x2"]
+__all__ = ["OracleGPE", "exp2x2", "apply2x2", "phase_separation", "population_radius", "winding"]

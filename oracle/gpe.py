@@ -28,7 +28,7 @@ Readings where the paper is silent or inconsistent (each one is exercised by a p
 3. Spin-momentum term: +k_L k_x sigma_z, so the up component's minimum sits at k_x = -k_L and the
    down component's at +k_L (the text of Sec. 3.1 and Sec. 6).
 4. A spatially uniform Raman coupling Omega is part of the k-space 2x2 propagator; a spatially
-   varying Omega(x) and the detuning delta are part of the real-space exponential.
+   varying Omega(x, y) and the detuning delta are part of the real-space exponential.
 5. The real-space exponential freezes the densities at the start of the sub-step and
    exponentiates the full 2x2 real-space Hamiltonian in closed form.
 6. Normalisation is of the total (both components) to norm0, after each full imaginary step.
@@ -131,6 +131,24 @@ class OracleGPE:
 
     def get_psi(self):
         return self.psi.copy()
+
+    def set_raman_profile(self, omega_x=None, omega_y=None):
+        """Spatially varying Raman coupling of Eq. (H4) as a sum of profiles along the two axes,
+        Omega(x, y) = Omega_x(x_j) + Omega_y(y_i) (Sec. 6 imposes one along y, Eq. (Omega)).  None
+        stands for a zero profile.  Replaces the tanh profile of the parameters."""
+        ox = np.zeros(self.nx) if omega_x is None else np.asarray(omega_x, dtype=np.float64)
+        oy = np.zeros(self.ny) if omega_y is None else np.asarray(omega_y, dtype=np.float64)
+        if ox.shape != (self.nx,) or oy.shape != (self.ny,):
+            raise ValueError("profile lengths must be nx and ny")
+        self.omega_r = ox[np.newaxis, :] + oy[:, np.newaxis]
+
+    def add_noise(self, xi, amplitude):
+        """Annealing update of Sec. 6: the state plus `amplitude` times the given noise field
+        (drawn by the caller), with no renormalisation."""
+        xi = np.asarray(xi, dtype=np.complex128)
+        if xi.shape != self.psi.shape:
+            raise ValueError("noise must have the state's shape")
+        self.psi = self.psi + float(amplitude) * xi
 
     # -- sub-steps --------------------------------------------------------------------------
     def _fft2(self, f):

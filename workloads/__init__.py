@@ -17,7 +17,8 @@ Parameter meaning (the same fields, in the same order, as the C struct ``sgpe_pa
 * ``delta``         -- spatially uniform detuning delta of Eq. (H2): the term +delta/2 sigma_z.
 * ``wx, wy``        -- harmonic trap V = (wx^2 x^2 + wy^2 y^2) / 2 (Eq. (H2)).
 * ``omega_r0, omega_rw`` -- spatially varying Raman coupling Omega(x) = omega_r0 tanh(x / omega_rw)
-  (Eq. (H4) with Omega(r)); omega_r0 = 0 disables it.
+  (Eq. (H4) with Omega(r)); omega_r0 = 0 disables it.  (Other profiles, such as the Sec. 6 one
+  along y, are passed to the solvers as tables; see ``spin_hall_profile``.)
 * ``dt``            -- time step (real time), or imaginary-time step d(tau).
 * ``norm0``         -- atom number the imaginary-time state is normalised to (Sec. 3.2).
 """
@@ -31,6 +32,8 @@ import numpy as np
 __all__ = [
     "Params", "PRESETS", "preset", "grid_axes",
     "gaussian_state", "thomas_fermi_state", "initial_state", "round_to_c64", "sweep_instances",
+    "SPIN_HALL_G", "SPIN_HALL_FIELD", "spin_hall_params", "spin_hall_profile", "vortex_state",
+    "complex_noise",
 ]
 
 
@@ -173,3 +176,77 @@ def sweep_instances(seed: int = 0, sizes=(128, 256, 512), per_size: int = 32) ->
             de = float(rng.uniform(-0.5, 0.5))
             out.append(Params(nx=n, ny=n, g_uu=g, g_dd=g, g_ud=g, k_l=2.0, omega=om, delta=de, dt=1e-3))
     return out
+
+
+# --- Spin-Hall ground states (Sec. 6) ---------------------------------------------------------
+# Readings of what Sec. 6 leaves open:
+# * g: 10^4 atoms of 87Rb (a_s = 100 Bohr radii; the species is not named) in a trap with
+#   omega_z / omega_perp = 2000 / 50, so a_z = a_0 / sqrt(40) and g = sqrt(8 pi) N a_s / a_z
+#   = 1.10e3 in units of hbar omega_perp a_0^2 with the state normalised to one.
+# * The Raman profile of Eq. (Omega) is applied along y through the coordinate
+#   u = clamp(2 + y / ell, 0, 4): the double-well minima move from +-k_L at u = 0 to 0 at u = 4,
+#   the gauge potential A*(u) = k_L (1 - u / 4) is linear there, and ell = k_L / (4 |B*|) gives
+#   the printed field |B*| = 0.369 hbar / (q a_0^2).  k_L = 3 (ell = 2.03): the linear strip
+#   |y| <= 2 ell spans three quarters of the cloud's diameter, while the dressed-state potential
+#   -Omega^2 / (16 E_L) that a varying Omega brings with it (depth E_L = 4.5 over the strip) moves
+#   the cloud by about 0.6 a_0.  A wider strip needs a larger k_L and a deeper potential, which
+#   pulls the cloud out of the field (k_L = 5); y in units of a_0 (k_L = 1.476) leaves a 4 a_0
+#   strip with hardly any vortices.
+# * Box [-16, 16)^2 (dx = 1/32 at 1024^2, several points per healing length); uniform Omega = 0,
+#   delta = 0, isotropic trap; imaginary-time step 1e-3.
+SPIN_HALL_G = 1.10e3
+SPIN_HALL_FIELD = 0.369
+
+
+def spin_hall_params(n: int = 1024, ratio: float = 0.1, g: float = SPIN_HALL_G, k_l: float = 3.0,
+                     xmax: float = 16.0, dt: float = 1e-3) -> Params:
+    """The spin-Hall system of Sec. 6: g_uu = g_dd = g, g_ud = ratio * g, spin-momentum k_L, no
+    uniform Raman coupling (the coupling is the spatial profile of ``spin_hall_profile``)."""
+    return Params(nx=n, ny=n, xmax=xmax, ymax=xmax, g_uu=g, g_dd=g, g_ud=ratio * g, k_l=k_l,
+                  omega=0.0, delta=0.0, wx=1.0, wy=1.0, omega_r0=0.0, omega_rw=1.0, dt=dt, norm0=1.0)
+
+
+def spin_hall_profile(p: Params, field: float = SPIN_HALL_FIELD) -> np.ndarray:
+    """Omega(y_i), length ny: Eq. (Omega), hbar Omega / E_L = sqrt(8 u - u^2) with E_L = k_L^2 / 2,
+    u = clamp(2 + y / ell, 0, 4), ell = k_L / (4 field)."""
+    _, y, _, _ = grid_axes(p)
+    ell = p.k_l / (4.0 * field)
+    u = np.clip(2.0 + y / ell, 0.0, 4.0)
+    e_l = 0.5 * p.k_l * p.k_l
+    return e_l * np.sqrt(np.maximum(8.0 * u - u * u, 0.0))
+
+
+def vortex_state(p: Params, n_vortices: int = 50, seed: int = 0, spread: float = 0.8,
+                 core: float | None = None) -> np.ndarray:
+    """Thomas-Fermi amplitudes (no noise) with n_vortices singly quantised vortices imprinted in
+    each component (Sec. 6): positions uniform in the disc of radius spread * R_TF about the
+    centre, drawn from default_rng(seed) for the up component (radius, then angle, per vortex) and
+    then the down one; winding +1 in the up component and -1 in the down one; each vortex
+    multiplies by (z - z_k) / sqrt(|z - z_k|^2 + core^2), z = x +- i y (default core: the healing
+    length 1 / sqrt(2 mu)).  Normalised to norm0, rounded to complex64."""
+    base = thomas_fermi_state(p, seed=0, noise=0.0)
+    gu = p.g_uu + p.g_ud
+    mu = math.sqrt(p.norm0 * p.wx * p.wy * gu / (2.0 * math.pi))
+    r_tf = math.sqrt(2.0 * mu) / max(p.wx, p.wy)
+    if core is None:
+        core = 1.0 / math.sqrt(2.0 * mu)
+    x, y, dx, dy = grid_axes(p)
+    X, Y = np.meshgrid(x, y)
+    rng = np.random.default_rng(seed)
+    psi = base.copy()
+    for c, sign in ((0, 1.0), (1, -1.0)):
+        for _ in range(n_vortices):
+            r = spread * r_tf * math.sqrt(float(rng.uniform()))
+            a = 2.0 * math.pi * float(rng.uniform())
+            zx, zy = X - r * math.cos(a), Y - r * math.sin(a)
+            psi[c] *= (zx + 1j * sign * zy) / np.sqrt(zx * zx + zy * zy + core * core)
+    total = dx * dy * float(np.sum(np.abs(psi) ** 2))
+    psi *= math.sqrt(p.norm0 / total)
+    return round_to_c64(psi)
+
+
+def complex_noise(p: Params, seed: int) -> np.ndarray:
+    """Complex Gaussian field of shape (2, ny, nx): real and imaginary parts ~ N(0, 1), drawn from
+    default_rng(seed) as one (2, ny, nx, 2) array."""
+    a = np.random.default_rng(seed).standard_normal((2, p.ny, p.nx, 2))
+    return a[..., 0] + 1j * a[..., 1]
