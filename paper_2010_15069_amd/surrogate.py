@@ -1,0 +1,195 @@
+"""Learned initial state for imaginary-time relaxation: a small Fourier neural operator (FNO).
+
+It maps the problem's parameters on the grid to a two-component order parameter that starts the
+plain split-step relaxation closer to the ground state.  The solver stays the judge: a predicted
+state is only a starting point, and the imaginary-time steps that follow are the ordinary ones.
+
+Model (one instance of the neural-operator family: lift, Fourier layers, project):
+  * input channels on the n x n grid: V / max V, g / 100, Omega / 3, delta / 0.5, x / xmax,
+    y / ymax, and the Thomas-Fermi amplitudes of both components (scaled to unit maximum);
+  * lift: pointwise linear to `width` channels;
+  * `layers` Fourier layers: u <- GELU(K u + W u), where K keeps the lowest `modes` x `modes`
+    Fourier modes of u (both signs of k_y, k_x >= 0 of the real transform) and mixes channels per
+    mode with a learned complex matrix, and W is pointwise linear;
+  * project: pointwise linear (width -> 128 -> 4): re and im of the up and down components;
+  * the output is normalised to the atom number.
+The spectral channel mixing is one batched complex matrix product over the kept modes; the
+pointwise layers run under bfloat16 autocast (matrix cores) with fp32 accumulation.
+
+Training minimises the phase-invariant infidelity 1 - |<p, t>|^2 / (<p, p> <t, t>) between the
+predicted and the relaxed states (both components, one global phase), so the arbitrary global phase
+of a ground state does not enter.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from workloads import Params, grid_axes, thomas_fermi_state
+
+IN_CHANNELS = 8
+
+
+def encode(params_list, device) -> torch.Tensor:
+    """(B, IN_CHANNELS, ny, nx) float32 input maps for a list of same-grid parameter sets."""
+    maps = []
+    for p in params_list:
+        x, y, _, _ = grid_axes(p)
+        X, Y = np.meshgrid(x, y)
+        V = 0.5 * (p.wx ** 2 * X ** 2 + p.wy ** 2 * Y ** 2)
+        tf = thomas_fermi_state(p, seed=0, noise=0.0)
+        amp = np.abs(tf)
+        amp = amp / max(float(amp.max()), 1e-30)
+        ones = np.ones_like(X)
+        maps.append(np.stack([V / V.max(), ones * p.g_uu / 100.0, ones * p.omega / 3.0, ones * p.delta / 0.5,
+                              X / p.xmax, Y / p.ymax, amp[0], amp[1]]).astype(np.float32))
+    return torch.from_numpy(np.stack(maps)).to(device)
+
+
+def to_psi(out: torch.Tensor, params_list) -> list:
+    """Network output (B, 4, ny, nx) -> list of (2, ny, nx) complex128 states normalised to norm0."""
+    o = out.detach().float().cpu().numpy().astype(np.float64)
+    res = []
+    for b, p in enumerate(params_list):
+        _, _, dx, dy = grid_axes(p)
+        psi = np.stack([o[b, 0] + 1j * o[b, 1], o[b, 2] + 1j * o[b, 3]])
+        nrm = dx * dy * float(np.sum(np.abs(psi) ** 2))
+        res.append(psi * math.sqrt(p.norm0 / max(nrm, 1e-300)))
+    return res
+
+
+def to_channels(psi_list, device) -> torch.Tensor:
+    """List of (2, ny, nx) complex states -> (B, 4, ny, nx) float32 targets."""
+    a = np.stack([np.stack([s[0].real, s[0].imag, s[1].real, s[1].imag]) for s in psi_list]).astype(np.float32)
+    return torch.from_numpy(a).to(device)
+
+
+class SpectralConv2d(torch.nn.Module):
+    """Channel mixing of the lowest modes x modes Fourier modes (k_y of both signs)."""
+
+    def __init__(self, cin: int, cout: int, modes: int):
+        super().__init__()
+        self.cin, self.cout, self.modes = cin, cout, modes
+        scale = 1.0 / (cin * cout)
+        # [2 * modes (k_y: 0..m-1 and -m..-1), modes (k_x), cin, cout], complex
+        self.weight = torch.nn.Parameter(scale * torch.randn(2 * modes, modes, cin, cout, dtype=torch.cfloat))
+
+    def forward(self, u: torch.Tensor) -> torch.Tensor:
+        b, c, h, w = u.shape
+        m = self.modes
+        uh = torch.fft.rfft2(u.float())                                   # (b, c, h, w//2+1)
+        sel = torch.cat([uh[:, :, :m, :m], uh[:, :, h - m:, :m]], dim=2)  # (b, c, 2m, m)
+        # per mode: (b, cin) @ (cin, cout) as one batched product over the 2m*m modes
+        a = sel.permute(2, 3, 0, 1).reshape(2 * m * m, b, c).contiguous()
+        wmat = self.weight.reshape(2 * m * m, c, self.cout).contiguous()
+        prod = torch.bmm(a, wmat).reshape(2 * m, m, b, self.cout).permute(2, 3, 0, 1)
+        out = torch.zeros(b, self.cout, h, w // 2 + 1, dtype=torch.cfloat, device=u.device)
+        out[:, :, :m, :m] = prod[:, :, :m]
+        out[:, :, h - m:, :m] = prod[:, :, m:]
+        return torch.fft.irfft2(out, s=(h, w))
+
+
+class FNO2d(torch.nn.Module):
+    def __init__(self, width: int = 32, modes: int = 16, layers: int = 4):
+        super().__init__()
+        self.width, self.modes, self.layers = width, modes, layers
+        self.lift = torch.nn.Conv2d(IN_CHANNELS, width, 1)
+        self.spectral = torch.nn.ModuleList([SpectralConv2d(width, width, modes) for _ in range(layers)])
+        self.pointwise = torch.nn.ModuleList([torch.nn.Conv2d(width, width, 1) for _ in range(layers)])
+        self.proj1 = torch.nn.Conv2d(width, 128, 1)
+        self.proj2 = torch.nn.Conv2d(128, 4, 1)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        dev = x.device.type
+        with torch.autocast(device_type=dev, dtype=torch.bfloat16, enabled=(dev == "cuda")):
+            u = self.lift(x)
+        for k in range(self.layers):
+            s = self.spectral[k](u)
+            with torch.autocast(device_type=dev, dtype=torch.bfloat16, enabled=(dev == "cuda")):
+                u = torch.nn.functional.gelu(s + self.pointwise[k](u).float())
+        with torch.autocast(device_type=dev, dtype=torch.bfloat16, enabled=(dev == "cuda")):
+            u = self.proj2(torch.nn.functional.gelu(self.proj1(u)))
+        return u.float()
+
+    def config(self) -> dict:
+        return {"width": self.width, "modes": self.modes, "layers": self.layers}
+
+
+def infidelity(pred: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """Mean over the batch of 1 - |<p, t>|^2 / (<p, p> <t, t>) for (B, 4, ny, nx) real channels
+    holding (re, im) of two components."""
+    pr, pi = pred[:, 0::2], pred[:, 1::2]
+    tr, ti = target[:, 0::2], target[:, 1::2]
+    dims = (1, 2, 3)
+    re = (pr * tr + pi * ti).sum(dims)
+    im = (pr * ti - pi * tr).sum(dims)
+    pp = (pr * pr + pi * pi).sum(dims)
+    tt = (tr * tr + ti * ti).sum(dims)
+    return (1.0 - (re * re + im * im) / (pp * tt)).mean()
+
+
+def train(model: FNO2d, inputs: torch.Tensor, targets: torch.Tensor, epochs: int = 30, batch: int = 16,
+          lr: float = 2e-3, log=print, seed: int = 0) -> list:
+    """Adam with a cosine learning-rate schedule on the infidelity; returns the per-epoch mean loss."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    opt = torch.optim.Adam(model.parameters(), lr=lr)
+    n = inputs.shape[0]
+    steps_total = epochs * ((n + batch - 1) // batch)
+    sched = torch.optim.lr_scheduler.OneCycleLR(opt, max_lr=lr, total_steps=steps_total, pct_start=0.1)
+    hist = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g)
+        tot = 0.0
+        for i in range(0, n, batch):
+            idx = perm[i:i + batch].to(inputs.device)
+            loss = infidelity(model(inputs[idx]), targets[idx])
+            opt.zero_grad(set_to_none=True)
+            loss.backward()
+            opt.step()
+            sched.step()
+            tot += float(loss.detach()) * len(idx)
+        hist.append(tot / n)
+        log(f"  epoch {ep + 1}/{epochs}: infidelity {hist[-1]:.3e} ({time.perf_counter() - t0:.0f} s)")
+    return hist
+
+
+def save(model: FNO2d, path: str, dtype=torch.float16) -> None:
+    """Weights as safetensors in `dtype` (complex spectral weights stored as real/imag pairs);
+    `load` widens them to fp32."""
+    from safetensors.torch import save_file
+    tensors = {}
+    for k, v in model.state_dict().items():
+        v = v.detach().cpu()
+        if v.is_complex():
+            tensors[k + ".re"] = v.real.to(dtype).contiguous()
+            tensors[k + ".im"] = v.imag.to(dtype).contiguous()
+        else:
+            tensors[k] = v.to(dtype).contiguous()
+    meta = {k: str(v) for k, v in model.config().items()}
+    save_file(tensors, path, metadata=meta)
+
+
+def load(path: str, device="cpu") -> FNO2d:
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        meta = f.metadata()
+        tensors = {k: f.get_tensor(k) for k in f.keys()}
+    model = FNO2d(width=int(meta["width"]), modes=int(meta["modes"]), layers=int(meta["layers"]))
+    sd = {}
+    for k in model.state_dict():
+        if k + ".re" in tensors:
+            sd[k] = torch.complex(tensors[k + ".re"].float(), tensors[k + ".im"].float())
+        else:
+            sd[k] = tensors[k].float()
+    model.load_state_dict(sd)
+    return model.to(device).eval()
+
+
+def predict(model: FNO2d, params_list, device) -> list:
+    """Initial states (complex128, normalised) for a list of same-grid parameter sets."""
+    with torch.no_grad():
+        return to_psi(model(encode(params_list, device)), params_list)

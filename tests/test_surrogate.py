@@ -1,0 +1,71 @@
+"""CPU checks of the learned-initial-state model (paper_2010_15069_amd.surrogate): its spectral layer
+against the plain definition written out with NumPy's FFT, the loss's phase invariance, the
+weights round trip and the input encoding."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2010_15069_amd import surrogate
+from workloads import Params, sweep_instances
+
+
+def test_spectral_layer_matches_its_definition():
+    torch.manual_seed(0)
+    cin, cout, m, h, w = 3, 2, 3, 16, 12
+    layer = surrogate.SpectralConv2d(cin, cout, m)
+    u = torch.randn(2, cin, h, w)
+    got = layer(u).detach().numpy()
+    # definition: real FFT over (y, x); keep k_y in {0..m-1} and {h-m..h-1}, k_x in {0..m-1};
+    # out_hat[o] = sum_i u_hat[i] W[k, i, o] there, zero elsewhere; inverse real FFT
+    U = np.fft.rfft2(u.numpy().astype(np.float64))
+    W = layer.weight.detach().numpy().astype(np.complex128)   # [2m, m, cin, cout]
+    O = np.zeros((2, cout, h, w // 2 + 1), dtype=np.complex128)
+    rows = list(range(m)) + list(range(h - m, h))
+    for b in range(2):
+        for r_i, ky in enumerate(rows):
+            for kx in range(m):
+                O[b, :, ky, kx] = U[b, :, ky, kx] @ W[r_i, kx]
+    ref = np.fft.irfft2(O, s=(h, w))
+    assert np.allclose(got, ref, atol=1e-5 * np.abs(ref).max())
+
+
+def test_infidelity_is_zero_for_the_same_state_up_to_a_global_phase():
+    torch.manual_seed(1)
+    t = torch.randn(3, 4, 8, 8)
+    phase = 0.7
+    c, s = np.cos(phase), np.sin(phase)
+    p = t.clone()
+    p[:, 0::2] = c * t[:, 0::2] - s * t[:, 1::2]
+    p[:, 1::2] = s * t[:, 0::2] + c * t[:, 1::2]
+    assert float(surrogate.infidelity(2.5 * p, t)) < 1e-6
+    q = torch.randn(3, 4, 8, 8)
+    assert 0.5 < float(surrogate.infidelity(q, t)) <= 1.0
+
+
+def test_weights_round_trip(tmp_path):
+    torch.manual_seed(2)
+    model = surrogate.FNO2d(width=8, modes=4, layers=2)
+    x = torch.randn(1, surrogate.IN_CHANNELS, 16, 16)
+    path = str(tmp_path / "w32.safetensors")
+    surrogate.save(model, path, dtype=torch.float32)
+    back = surrogate.load(path)
+    assert torch.equal(model(x), back(x))
+    assert back.config() == {"width": 8, "modes": 4, "layers": 2}
+    path = str(tmp_path / "w16.safetensors")
+    surrogate.save(model, path)          # default: fp16 storage
+    back = surrogate.load(path)
+    ref = model(x)
+    assert torch.allclose(back(x), ref, atol=2e-3 * float(ref.abs().max()))
+
+
+def test_encoding_and_prediction_shapes():
+    ps = sweep_instances(seed=5, sizes=(32,), per_size=3)
+    x = surrogate.encode(ps, "cpu")
+    assert x.shape == (3, surrogate.IN_CHANNELS, 32, 32) and x.dtype == torch.float32
+    assert torch.isfinite(x).all()
+    model = surrogate.FNO2d(width=8, modes=4, layers=2)
+    psi = surrogate.predict(model, ps, "cpu")
+    for p, s in zip(ps, psi):
+        dx = 2 * p.xmax / p.nx
+        assert s.shape == (2, 32, 32)
+        assert abs(dx * dx * np.sum(np.abs(s) ** 2) - p.norm0) < 1e-9
