@@ -11,8 +11,10 @@ in batches of 100 (one step_imag(100) call each) with HIP events; value = K / to
 Prints one JSON line.  Also reports: the dominant kernel's HBM roofline fraction (algorithmic bytes
 over its mean launch time in the real schedule, from HIP events on the solver's stream);
 the same physics at 512^2 and 2048^2; the ground-state time-to-solution (wall time until the
-energy is within 1e-6 of the FP64 oracle's converged value, 256^2); the batched parameter sweep
-(96 instances of three sizes, one graph-captured call); and the FP64 oracle's throughput on a
+energy is within 1e-6 of the FP64 oracle's converged value, 256^2), from the Thomas-Fermi start
+and from the learned (neural-operator) start; the learned start against the plain one on held-out
+parameter sets; the batched parameter sweep (96 instances of three sizes, one graph-captured call);
+one spin-Hall trial (Sec. 6, 2 x 60000 steps at 1024^2); and the FP64 oracle's throughput on a
 bounded sample of the 1024^2 workload on the host cores.
 """
 from __future__ import annotations
@@ -171,6 +173,108 @@ def ground_state_time(torch, stream, check_every=50, max_steps=200000):
             "reached": abs(e - e_ref) <= 1e-6 * abs(e_ref)}
 
 
+def _load_surrogate(torch):
+    """The learned-start model (weights shipped with the package), warmed up once."""
+    from paper_2010_15069_amd import surrogate
+    from paper_2010_15069_amd.train_surrogate import WEIGHTS
+    from workloads import sweep_instances
+    if not os.path.exists(WEIGHTS):
+        return None
+    model = surrogate.load(WEIGHTS, "cuda")
+    # warm-up at the batch sizes used below (library plans and kernel choices are per shape)
+    for count in (1, 64):
+        surrogate.predict(model, sweep_instances(seed=3, sizes=(256,), per_size=count), "cuda")
+    torch.cuda.synchronize()
+    return model
+
+
+def ground_state_learned(torch, stream, model, check_every=50, max_steps=200000):
+    """The ground-state time-to-solution of the same workload from the learned start: the timed
+    region holds the input encoding, the network's forward pass, set_psi and the checked steps."""
+    from paper_2010_15069_amd import Solver, surrogate
+    from workloads import preset
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "ground_energy.json")))
+    p = preset(ref["workload"])
+    e_ref = float(ref["energy"])
+    s = Solver(p, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi0 = surrogate.predict(model, [p], "cuda")[0]
+    t_inf = time.perf_counter() - t0
+    s.set_psi(psi0)
+    steps, e = 0, s.energy()
+    while abs(e - e_ref) > 1e-6 * abs(e_ref) and steps < max_steps:
+        s.step_imag(check_every)
+        steps += check_every
+        e = s.energy()
+    el = time.perf_counter() - t0
+    s.close()
+    return {"time_to_1e-6_s": el, "inference_s": t_inf, "steps": steps, "energy": e,
+            "rel_error": abs(e - e_ref) / abs(e_ref), "reached": abs(e - e_ref) <= 1e-6 * abs(e_ref)}
+
+
+def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_every=50):
+    """Held-out parameter sets (seed 2 of the sweep distribution at 256^2), each relaxed from the
+    plain Thomas-Fermi start and from the learned start, all sets of one arm in one batch, the
+    energy checked every 50 steps.  E_ref per set: the lower of the two arms' final energies.
+    Reported per arm: steps and batch wall time until each set is within 1e-6 (medians)."""
+    import numpy as np
+    from paper_2010_15069_amd import Batch, surrogate
+    from workloads import initial_state, sweep_instances
+    ps = sweep_instances(seed=2, sizes=(256,), per_size=n_sets)
+
+    def arm(starts_fn):
+        b = Batch(ps, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, psi in enumerate(starts_fn()):
+            b.set_psi(i, psi)
+        trace, clock = [], []
+        for _ in range(steps // check_every):
+            b.step_imag(check_every)
+            trace.append([b.energy(i) for i in range(len(ps))])
+            clock.append(time.perf_counter() - t0)
+        b.close()
+        return np.array(trace), np.array(clock)
+
+    tr_p, ck_p = arm(lambda: [initial_state(p, "tf", seed=10000 + i) for i, p in enumerate(ps)])
+    tr_l, ck_l = arm(lambda: surrogate.predict(model, ps, "cuda"))
+    e_ref = np.minimum(tr_p[-1], tr_l[-1])
+
+    def first(trace, clock):
+        st, sec = [], []
+        for i in range(len(ps)):
+            ok = np.nonzero(np.abs(trace[:, i] - e_ref[i]) <= 1e-6 * abs(e_ref[i]))[0]
+            if len(ok):
+                st.append((ok[0] + 1) * check_every)
+                sec.append(float(clock[ok[0]]))
+        return st, sec
+
+    sp, tp = first(tr_p, ck_p)
+    sl, tl = first(tr_l, ck_l)
+    med = lambda v: float(np.median(v)) if v else None  # noqa: E731
+    return {"workload": f"{n_sets} held-out sets (seed 2): 256^2, g ~ U[1,100] (all couplings), Omega ~ U[0,3], "
+                        f"delta ~ U[-0.5,0.5], k_L = 2, dt = 1e-3; one batch per arm; energy every {check_every} steps",
+            "max_steps": steps,
+            "plain": {"reached": len(sp), "steps_median": med(sp), "batch_seconds_median": med(tp)},
+            "learned": {"reached": len(sl), "steps_median": med(sl), "batch_seconds_median": med(tl)}}
+
+
+def spin_hall_trial(torch):
+    """One spin-Hall trial (Sec. 6) at 1024^2: vortex-seeded start, 60000 annealed and 60000
+    plain imaginary-time steps with the Raman profile Omega(y), then the observables."""
+    from paper_2010_15069_amd.spin_hall import run_trial
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = run_trial(ratio=0.1, seed=0, n=1024)
+    res["wall_seconds"] = time.perf_counter() - t0
+    res["steps_per_s"] = res["steps"] / res["seconds"]
+    res["workload"] = ("spin-Hall trial: 1024^2 x 2, g = 1100, g_ud / g = 0.1, k_L = 3, Omega(y) of Eq. (Omega), "
+                       "50 seeded vortices per component, 2 x 60000 imaginary-time steps (dt = 1e-3), "
+                       "30 noise anneals in the first segment")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +286,7 @@ def main():
     ap.add_argument("--no-ground", action="store_true", help="skip the ground-state time-to-solution")
     ap.add_argument("--no-other-grids", action="store_true", help="skip the 512^2 and 2048^2 lines")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched parameter sweep")
+    ap.add_argument("--no-spin-hall", action="store_true", help="skip the spin-Hall trial")
     ap.add_argument("--workload", default="metric_1024")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the HBM "
@@ -298,8 +403,16 @@ def main():
         out["other_grids"] = other_grids(torch, stream, timed, p)
     if not args.no_ground:
         out["ground_state"] = ground_state_time(torch, stream)
+        model = _load_surrogate(torch)
+        if model is not None:
+            out["ground_state"]["learned_start"] = ground_state_learned(torch, stream, model)
+            if not args.no_batch:
+                out["learned_start_sweep"] = learned_start_sweep(torch, stream, model)
+            del model
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(torch, stream)
+    if not args.no_spin_hall:
+        out["spin_hall_trial"] = spin_hall_trial(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

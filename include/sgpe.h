@@ -14,7 +14,9 @@
  *   - i d/dt psi = H psi; real-time propagators exp(-i H dt), imaginary-time exp(-H dtau);
  *   - H_K(k) = |k|^2/2 * 1 + k_L k_x sigma_z + (Omega/2) sigma_x  (k-space 2x2, uniform Omega);
  *   - H_R(r) = V(r) 1 + (delta/2) sigma_z + diag(g_uu n_u + g_ud n_d, g_dd n_d + g_ud n_u)
- *              + (Omega(x)/2) sigma_x,  V = (wx^2 x^2 + wy^2 y^2)/2, Omega(x) = omega_r0 tanh(x/omega_rw);
+ *              + (Omega(x, y)/2) sigma_x,  V = (wx^2 x^2 + wy^2 y^2)/2, with the spatial coupling
+ *              Omega(x, y) = omega_r0 tanh(x/omega_rw), or Omega_x(x) + Omega_y(y) as given to
+ *              sgpe_set_raman_profile;
  *   - one step = K(dt/2) R(dt) K(dt/2); R exponentiates H_R with the densities of its input;
  *   - imaginary time rescales the total (both components) to norm0 after every step;
  *   - grid x_j = -xmax + j*dx, dx = 2*xmax/nx (periodic, endpoint excluded), k_x in FFT order
@@ -129,6 +131,48 @@ sgpe_status sgpe_profile_steps(sgpe_ctx* ctx, int32_t imag, int64_t n,
  * buffer on first use.  Synchronises.  Either output pointer may be NULL. */
 sgpe_status sgpe_profile_kernels(sgpe_ctx* ctx, int32_t imag, int64_t n,
                                  double* row_ms, double* col_ms);
+
+/* Spatially varying Raman coupling Omega(x, y) = Omega_x(x) + Omega_y(y) of the real-space
+ * Hamiltonian ((Omega/2) sigma_x in H_R, Eq. (H4) with a position-dependent Omega; Sec. 6 uses a
+ * profile along y, Eq. (Omega)).  omega_x: host array of nx values Omega_x(x_j); omega_y: host
+ * array of ny values Omega_y(y_i); either may be NULL for a zero profile; both NULL switches the
+ * spatial coupling off.  The arrays are copied (the caller keeps ownership) and replace the
+ * profile that omega_r0/omega_rw gave at creation.  Waits for the stream's queued work first.
+ * Errors: SGPE_EINVAL (non-finite value), SGPE_EDEVICE, SGPE_ENOMEM. */
+sgpe_status sgpe_set_raman_profile(sgpe_ctx* ctx, const double* omega_x, const double* omega_y);
+
+/* Annealing update (Sec. 6): psi <- psi + amplitude * xi at every point and both components.
+ * xi: host array in the layout of sgpe_set_psi (complex128, shape (2, ny, nx)), rounded once to
+ * complex64; the caller draws it (e.g. complex Gaussian noise) and keeps ownership.  No
+ * renormalisation (the next imaginary-time step does it).  Allocates the state-sized scratch
+ * buffer on first use.  Synchronises.
+ * Errors: SGPE_EINVAL (NULL, non-finite amplitude), SGPE_ENONFINITE (NaN/Inf in xi; the state is
+ * unchanged), SGPE_ESTATE (no state). */
+sgpe_status sgpe_add_noise(sgpe_ctx* ctx, const double* xi_host, double amplitude);
+
+/* System-averaged phase-separation parameter of the current state (Sec. 6, Eq. (s)):
+ * s = 1 - sum n_u n_d / sqrt(sum n_u^2 * sum n_d^2), sums over all grid points, n = |psi|^2,
+ * accumulated in fp64.  0 for proportional densities, 1 for disjoint ones.  Synchronises.
+ * Errors: SGPE_EINVAL (NULL), SGPE_ESTATE (no state, or a component that is zero everywhere). */
+sgpe_status sgpe_phase_separation(sgpe_ctx* ctx, double* s);
+
+/* Radius of the smallest disc about the origin (x = y = 0) that holds at least `fraction` of the
+ * total population sum (n_u + n_d): the smallest grid-point radius r_k with
+ * sum_{x^2 + y^2 <= r_k^2} (n_u + n_d) >= fraction * total, found by bisection to within
+ * 1e-12 relative (about 60 fp64 reductions on the device).  Sec. 6 uses fraction = 0.99 for the
+ * contour of the circulation.  Synchronises.
+ * Errors: SGPE_EINVAL (NULL, fraction outside (0, 1]), SGPE_ESTATE (no state or zero population). */
+sgpe_status sgpe_population_radius(sgpe_ctx* ctx, double fraction, double* radius);
+
+/* Circulation of each component along the circle of `radius` about the origin, counter-clockwise
+ * (Sec. 6, Eq. (Lz)): the closed lattice path through p_k, k = 0..m-1, the grid point nearest to
+ * (radius cos t_k, radius sin t_k), t_k = 2 pi k / m, m = max(256, ceil(4 pi radius / min(dx, dy)))
+ * (so that consecutive points are equal or neighbours); raw[c] = (1 / 2 pi) sum_k
+ * arg(psi_c(p_{k+1}) conj(psi_c(p_k))) with p_m = p_0, each increment in (-pi, pi], in fp64; n[c] =
+ * raw[c] rounded to the nearest integer, the winding number (L_z per particle in units of hbar).
+ * n: int32[2] (up, down); raw: double[2] or NULL.  Synchronises.
+ * Errors: SGPE_EINVAL (NULL n, radius not in (0, min(xmax, ymax))), SGPE_ESTATE (no state). */
+sgpe_status sgpe_winding(sgpe_ctx* ctx, double radius, int32_t* n, double* raw);
 
 /* Static description of a status code.  Never NULL. */
 const char* sgpe_strerror(sgpe_status s);

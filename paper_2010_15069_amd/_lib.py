@@ -61,6 +61,8 @@ EXPORTS = [
     "sgpe_batch_energy", "sgpe_batch_norm", "sgpe_batch_step_real", "sgpe_batch_step_imag",
     "sgpe_batch_synchronize", "sgpe_batch_use_graph", "sgpe_batch_get_schedule",
     "sgpe_batch_set_schedule", "sgpe_batch_autotune",
+    "sgpe_set_raman_profile", "sgpe_add_noise", "sgpe_phase_separation", "sgpe_population_radius",
+    "sgpe_winding",
 ]
 
 
@@ -144,6 +146,13 @@ def _lib():
         "sgpe_batch_set_schedule": ([vp, i32, P(Schedule)], st),
         "sgpe_batch_autotune": ([vp, i32, P(ctypes.c_double)], st),
     }
+    batch_sigs.update({
+        "sgpe_set_raman_profile": ([vp, vp, vp], st),
+        "sgpe_add_noise": ([vp, vp, ctypes.c_double], st),
+        "sgpe_phase_separation": ([vp, P(ctypes.c_double)], st),
+        "sgpe_population_radius": ([vp, ctypes.c_double, P(ctypes.c_double)], st),
+        "sgpe_winding": ([vp, ctypes.c_double, PI32, P(ctypes.c_double)], st),
+    })
     for name, (args, res) in batch_sigs.items():
         f = getattr(lib, name)
         f.argtypes = args

@@ -76,7 +76,7 @@ def build(verbose: bool = False) -> str:
     with tempfile.TemporaryDirectory(prefix="sgpe_build_") as tmp:
         objs = []
         jobs = []
-        for src in ("row_pass.hip", "col_pass.hip", "reductions.hip"):
+        for src in ("row_pass.hip", "col_pass.hip", "reductions.hip", "observables.hip"):
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             jobs.append(([hipcc, "-c"] + HIP_FLAGS + incs + [os.path.join(CSRC, src), "-o", obj], obj))
         for src in ("api.cpp", "batch.cpp"):

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -50,6 +51,41 @@ sgpe_status upload(sgpe_ctx* c, T** dst, const std::vector<T>& host) {
     return SGPE_EDEVICE;
   }
   *dst = static_cast<T*>(p);
+  return SGPE_OK;
+}
+
+// Tables of the spatial Raman coupling Omega_x(x_j) + Omega_y(y_i) (Eq. (H4) with Omega(r)): the
+// step kernels' half-angles dt Omega / 2 in fp32 and the energy kernel's Omega in fp64.  NULL
+// stands for a zero profile.  Allocated on first use, overwritten in place afterwards.
+sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y) {
+  const sgpe_params& p = c->p;
+  sgpe_status st;
+  void* ptr = nullptr;
+  if (!c->hbx) {
+    if ((st = dev_alloc(c, &ptr, size_t(p.nx) * sizeof(float))) != SGPE_OK) return st;
+    c->hbx = static_cast<float*>(ptr);
+    if ((st = dev_alloc(c, &ptr, size_t(p.ny) * sizeof(float))) != SGPE_OK) return st;
+    c->hby = static_cast<float*>(ptr);
+    if ((st = dev_alloc(c, &ptr, size_t(p.nx) * sizeof(double))) != SGPE_OK) return st;
+    c->omx = static_cast<double*>(ptr);
+    if ((st = dev_alloc(c, &ptr, size_t(p.ny) * sizeof(double))) != SGPE_OK) return st;
+    c->omy = static_cast<double*>(ptr);
+  }
+  std::vector<double> ox(p.nx, 0.0), oy(p.ny, 0.0);
+  if (om_x) ox.assign(om_x, om_x + p.nx);
+  if (om_y) oy.assign(om_y, om_y + p.ny);
+  std::vector<float> hx(p.nx), hy(p.ny);
+  for (int j = 0; j < p.nx; ++j) hx[j] = float(0.5 * p.dt * ox[j]);
+  for (int i = 0; i < p.ny; ++i) hy[i] = float(0.5 * p.dt * oy[i]);
+  // the stream's queued steps may still read the old tables
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(c->hbx, hx.data(), hx.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->hby, hy.data(), hy.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->omx, ox.data(), ox.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->omy, oy.data(), oy.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
   return SGPE_OK;
 }
 
@@ -225,6 +261,7 @@ RowArgs row_args(const sgpe_ctx* c) {
   a.hg_dd = float(h * p.g_dd);
   a.hg_ud = float(h * p.g_ud);
   a.hbx = c->hbx;
+  a.hby = c->hby;
   return a;
 }
 
@@ -404,13 +441,10 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
     }
   }
   if (c->full2x2) {
-    std::vector<float> hb(p->nx);
+    std::vector<double> om(p->nx);
     const double dx = 2.0 * p->xmax / p->nx;
-    for (int j = 0; j < p->nx; ++j) {
-      const double x = -p->xmax + dx * j;
-      hb[j] = float(0.5 * p->dt * p->omega_r0 * std::tanh(x / p->omega_rw));
-    }
-    if ((st = upload(c, &c->hbx, hb)) != SGPE_OK) return fail(st);
+    for (int j = 0; j < p->nx; ++j) om[j] = p->omega_r0 * std::tanh((-p->xmax + dx * j) / p->omega_rw);
+    if ((st = raman_tables(c, om.data(), nullptr)) != SGPE_OK) return fail(st);
   }
   void* ptr = nullptr;
   if ((st = dev_alloc(c, &ptr, kMaxPartials * sizeof(double))) != SGPE_OK) return fail(st);
@@ -552,6 +586,155 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
   return c->latched;
 }
 
+sgpe_status sgpe_set_raman_profile(sgpe_ctx* c, const double* omega_x, const double* omega_y) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  const sgpe_params& p = c->p;
+  if (omega_x)
+    for (int j = 0; j < p.nx; ++j)
+      if (!std::isfinite(omega_x[j])) return SGPE_EINVAL;
+  if (omega_y)
+    for (int i = 0; i < p.ny; ++i)
+      if (!std::isfinite(omega_y[i])) return SGPE_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  if (!omega_x && !omega_y) {
+    c->full2x2 = false;
+    return SGPE_OK;
+  }
+  if ((st = raman_tables(c, omega_x, omega_y)) != SGPE_OK) return st;
+  c->full2x2 = true;
+  return SGPE_OK;
+}
+
+// Copies nblocks * per_block partials from c->epart to the host and sums each slot in block order.
+static sgpe_status fetch_sums(sgpe_ctx* c, int nblocks, int per_block, double* sums) {
+  std::vector<double> part(size_t(nblocks) * per_block);
+  if (hipMemcpyAsync(part.data(), c->epart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  for (int k = 0; k < per_block; ++k) sums[k] = 0.0;
+  for (int b = 0; b < nblocks; ++b)
+    for (int k = 0; k < per_block; ++k) sums[k] += part[size_t(b) * per_block + k];
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_add_noise(sgpe_ctx* c, const double* xi, double amplitude) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!xi || !std::isfinite(amplitude)) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const size_t npts = size_t(c->p.nx) * size_t(c->p.ny);
+  for (size_t i = 0; i < 4 * npts; ++i)
+    if (!std::isfinite(xi[i])) return SGPE_ENONFINITE;
+  if (!c->scratch) {
+    void* ptr = nullptr;
+    if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return st;
+    c->scratch = static_cast<float4*>(ptr);
+  }
+  std::vector<float4> buf(npts);
+  const double* up = xi;
+  const double* dn = xi + 2 * npts;
+  for (size_t i = 0; i < npts; ++i)
+    buf[i] = make_float4(float(up[2 * i]), float(up[2 * i + 1]), float(dn[2 * i]), float(dn[2 * i + 1]));
+  hipError_t e = hipMemcpyAsync(c->scratch, buf.data(), npts * sizeof(float4), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = sgpe::launch_add_noise(c->psi, c->scratch, float(amplitude), (long long)npts, c->stream);
+  // buf must outlive the copy
+  if (hipStreamSynchronize(c->stream) != hipSuccess || e != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  return c->latched;
+}
+
+sgpe_status sgpe_phase_separation(sgpe_ctx* c, double* out) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!out) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const long long npts = (long long)c->p.nx * c->p.ny;
+  const int nb = sgpe::norm_blocks();
+  hipError_t e = sgpe::launch_moments(c->psi, npts, c->epart, nb, c->stream);
+  if (e != hipSuccess) return status_of(e);
+  double m[sgpe::kMomentParts];
+  if ((st = fetch_sums(c, nb, sgpe::kMomentParts, m)) != SGPE_OK) return st;
+  if (!std::isfinite(m[0] + m[1] + m[2])) {
+    c->latched = SGPE_ENONFINITE;
+    return c->latched;
+  }
+  if (!(m[1] > 0.0) || !(m[2] > 0.0)) return SGPE_ESTATE;
+  *out = 1.0 - m[0] / std::sqrt(m[1] * m[2]);
+  return c->latched;
+}
+
+static sgpe_status disk_population(sgpe_ctx* c, double r2, double* out) {
+  const sgpe_params& p = c->p;
+  const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
+  const int nb = sgpe::norm_blocks();
+  hipError_t e = sgpe::launch_disk_population(c->psi, p.nx, p.ny, -p.xmax, dx, -p.ymax, dy, r2, c->epart, nb,
+                                              c->stream);
+  if (e != hipSuccess) return status_of(e);
+  return fetch_sums(c, nb, 1, out);
+}
+
+sgpe_status sgpe_population_radius(sgpe_ctx* c, double fraction, double* radius) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!radius || !(fraction > 0.0 && fraction <= 1.0)) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const sgpe_params& p = c->p;
+  double total = 0.0;
+  if ((st = disk_population(c, HUGE_VAL, &total)) != SGPE_OK) return st;
+  if (!std::isfinite(total)) {
+    c->latched = SGPE_ENONFINITE;
+    return c->latched;
+  }
+  if (!(total > 0.0)) return SGPE_ESTATE;
+  const double target = fraction * total;
+  // every grid point lies within the corner radius, so the disc of radius hi holds everything
+  double lo = 0.0, hi = std::sqrt(p.xmax * p.xmax + p.ymax * p.ymax);
+  for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    double inside = 0.0;
+    if ((st = disk_population(c, mid * mid, &inside)) != SGPE_OK) return st;
+    if (inside >= target) hi = mid;
+    else lo = mid;
+  }
+  *radius = hi;
+  return c->latched;
+}
+
+sgpe_status sgpe_winding(sgpe_ctx* c, double radius, int32_t* n, double* raw) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  const sgpe_params& p = c->p;
+  if (!n || !(radius > 0.0 && radius < std::min(p.xmax, p.ymax))) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const double d = std::min(2.0 * p.xmax / p.nx, 2.0 * p.ymax / p.ny);
+  const double mm = std::ceil(4.0 * M_PI * radius / d);
+  const int m = mm < 256.0 ? 256 : int(mm);
+  hipError_t e = sgpe::launch_winding(c->psi, p.nx, p.ny, p.xmax, p.ymax, radius, m, c->epart, c->stream);
+  if (e != hipSuccess) return status_of(e);
+  double w[2];
+  if ((st = fetch_sums(c, 1, 2, w)) != SGPE_OK) return st;
+  if (!std::isfinite(w[0]) || !std::isfinite(w[1])) {
+    c->latched = SGPE_ENONFINITE;
+    return c->latched;
+  }
+  n[0] = int32_t(std::lround(w[0]));
+  n[1] = int32_t(std::lround(w[1]));
+  if (raw) {
+    raw[0] = w[0];
+    raw[1] = w[1];
+  }
+  return c->latched;
+}
+
 sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   sgpe_status st = check_ctx(c);
   if (st != SGPE_OK) return st;
@@ -586,8 +769,8 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   a.g_ud = p.g_ud;
   a.k_l = p.k_l;
   a.omega = p.omega;
-  a.omega_r0 = p.omega_r0;
-  a.omega_rw = p.omega_rw;
+  a.om_x = c->full2x2 ? c->omx : nullptr;
+  a.om_y = c->full2x2 ? c->omy : nullptr;
   a.dkx = M_PI / p.xmax;
   a.dky = M_PI / p.ymax;
   const int nrb = p.ny / a.rows_per_block;

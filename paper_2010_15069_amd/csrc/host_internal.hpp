@@ -25,7 +25,11 @@ struct sgpe_ctx {
   // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
   float4* kx_tab[4] = {nullptr, nullptr, nullptr, nullptr};
   float2* ky_tab[4] = {nullptr, nullptr, nullptr, nullptr};
-  float* hbx = nullptr;  // dt * Omega(x_j) / 2, only with a spatial Raman coupling
+  // spatial Raman coupling Omega_x(x) + Omega_y(y), only with one (full2x2):
+  float* hbx = nullptr;     // dt * Omega_x(x_j) / 2
+  float* hby = nullptr;     // dt * Omega_y(y_i) / 2
+  double* omx = nullptr;    // Omega_x(x_j) (energy)
+  double* omy = nullptr;    // Omega_y(y_i)
   double* partials = nullptr;
   double* epart = nullptr;  // energy partials (row: 2 per block, then col: 1 per block)
   double* npart = nullptr;  // norm partials

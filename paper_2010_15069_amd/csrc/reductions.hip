@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   TwRegs<N> tr;
   load_twiddles<N>(tr, t, a.twx);
   const double y = a.ymin + a.dy * row;
+  const double om_row = a.om_y ? a.om_y[row] : 0.0;
   double er = 0.0, nr = 0.0;
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
     const double V = a.wx2h * x * x + a.wy2h * y * y;
     const double ur = v[m].x, ui = v[m].y, dr = v[m].z, di = v[m].w;
     const double nu = ur * ur + ui * ui, nd = dr * dr + di * di;
-    const double om = a.omega_r0 != 0.0 ? a.omega_r0 * tanh(x / a.omega_rw) : 0.0;
+    const double om = a.om_x ? a.om_x[j] + om_row : 0.0;
     er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (ur * dr + ui * di) +
           0.5 * a.g_uu * nu * nu + 0.5 * a.g_dd * nd * nd + a.g_ud * nu * nd;
     nr += nu + nd;

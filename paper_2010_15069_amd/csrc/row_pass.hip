@@ -72,7 +72,7 @@ __device__ __forceinline__ float row_scale(const RowArgs& a, const double (&pv)[
 // -------------------------------------------------------------------------------------------
 // Real-space exponential R(h) (Eqs. (H2)-(H4), densities of the input).  Each lane applies its
 // component's row of the 2x2 exponential to its value w; o is the partner lane's value at the
-// same point.  hv = h V(x, y); hbx = h Omega(x) / 2.
+// same point.  hv = h V(x, y); hbx = h Omega(x, y) / 2 with Omega(x, y) = Omega_x(x) + Omega_y(y).
 // -------------------------------------------------------------------------------------------
 struct RCoef {
   float hd_own;      // +- h delta / 2 for this component
@@ -178,6 +178,8 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
   c.hdelta2 = a.hdelta2;
   const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
   const float hvy = a.hvy * y * y;
+  float hb_row = 0.0f;
+  if constexpr (FULL) hb_row = a.hby[row];
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     const int j = t + T * m;
@@ -190,7 +192,7 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
       if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) v[m] = apply_r_diag<IMAG, true>(v[m], ph);
       else v[m] = apply_r_diag<IMAG, false>(v[m], ph);
     } else {
-      const float hbx = a.hbx[j];
+      const float hbx = a.hbx[j] + hb_row;
       const float2 o = pair_swap(v[m]);
       const float n_oth = fmaf(o.x, o.x, o.y * o.y);
       const RFull f = r_full_angles(n_own, n_oth, hv, c, hbx);

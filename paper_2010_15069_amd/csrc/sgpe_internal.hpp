@@ -36,7 +36,9 @@ struct RowArgs {
   float hvx, hvy;            // h * wx^2 / 2, h * wy^2 / 2
   float hdelta2;             // h * delta / 2
   float hg_uu, hg_dd, hg_ud;
-  const float* hbx;          // h * Omega(x_j) / 2, length nx (full 2x2 variant only)
+  const float* hbx;          // h * Omega_x(x_j) / 2, length nx (full 2x2 variant only)
+  const float* hby;          // h * Omega_y(y_i) / 2, length ny (full 2x2 variant only);
+                             //   the spatial coupling is Omega_x(x) + Omega_y(y)
 };
 
 struct ColArgs {
@@ -59,7 +61,9 @@ struct EnergyArgs {
   double xmin, dx, ymin, dy;
   double wx2h, wy2h;         // wx^2/2, wy^2/2
   double delta, g_uu, g_dd, g_ud;
-  double k_l, omega, omega_r0, omega_rw;
+  double k_l, omega;
+  const double* om_x;        // spatial Raman coupling Omega_x(x_j) (length nx) and Omega_y(y_i)
+  const double* om_y;        //   (length ny); both NULL without one
   double dkx, dky;
   double* row_partials;      // 2 per row block: {real-space energy, norm}
   double* col_partials;      // 1 per column block: k-space quadratic form
@@ -91,6 +95,21 @@ hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count,
                             hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+
+// Observables and state updates (observables.hip).  Grid-stride reductions write one partial (or
+// `kMomentParts` partials) per block, summed on the host in block order.
+constexpr int kMomentParts = 3;
+// psi += amp * xi, both components (xi in the state's layout).
+hipError_t launch_add_noise(float4* psi, const float4* xi, float amp, long long npts, hipStream_t s);
+// per block: sum n_u n_d, sum n_u^2, sum n_d^2
+hipError_t launch_moments(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+// per block: sum of n_u + n_d over the points with x^2 + y^2 <= r2
+hipError_t launch_disk_population(const float4* psi, int nx, int ny, double x0, double dx, double y0, double dy,
+                                  double r2, double* partials, int nblocks, hipStream_t s);
+// Phase increments of both components along the closed lattice path of `m` samples of the circle
+// of this radius about the origin; out[c] = (sum of increments) / (2 pi).  One workgroup.
+hipError_t launch_winding(const float4* psi, int nx, int ny, double xmax, double ymax, double radius, int m,
+                          double* out, hipStream_t s);
 
 // Workgroup geometry helpers (shared with the host so that partial counts match).
 // max_lds: the device's LDS bytes per workgroup (minus the kernels' static LDS).

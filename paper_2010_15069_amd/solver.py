@@ -83,6 +83,51 @@ class Solver:
         check(self._lib.sgpe_norm(self._ctx, ctypes.byref(v)), "sgpe_norm")
         return v.value
 
+    # -- spatial coupling, annealing and observables (Sec. 6) -------------------------------
+    def set_raman_profile(self, omega_x=None, omega_y=None):
+        """Spatial Raman coupling Omega_x(x_j) + Omega_y(y_i) (arrays of nx / ny values, or None
+        for zero); both None switches it off."""
+        def arr(v, n, name):
+            if v is None:
+                return None
+            a = np.ascontiguousarray(np.asarray(v), dtype=np.float64)
+            if a.shape != (n,):
+                raise ValueError(f"{name} must have shape ({n},), got {a.shape}")
+            return a
+        ax, ay = arr(omega_x, self.nx, "omega_x"), arr(omega_y, self.ny, "omega_y")
+        px = ax.ctypes.data_as(ctypes.c_void_p) if ax is not None else None
+        py = ay.ctypes.data_as(ctypes.c_void_p) if ay is not None else None
+        check(self._lib.sgpe_set_raman_profile(self._ctx, px, py), "sgpe_set_raman_profile")
+        return self
+
+    def add_noise(self, xi, amplitude):
+        """psi <- psi + amplitude * xi (xi complex, shape (2, ny, nx))."""
+        a = np.ascontiguousarray(np.asarray(xi), dtype=np.complex128)
+        if a.shape != (2, self.ny, self.nx):
+            raise ValueError(f"xi must have shape (2, {self.ny}, {self.nx}), got {a.shape}")
+        check(self._lib.sgpe_add_noise(self._ctx, a.ctypes.data_as(ctypes.c_void_p), float(amplitude)),
+              "sgpe_add_noise")
+        return self
+
+    def phase_separation(self) -> float:
+        v = ctypes.c_double()
+        check(self._lib.sgpe_phase_separation(self._ctx, ctypes.byref(v)), "sgpe_phase_separation")
+        return v.value
+
+    def population_radius(self, fraction=0.99) -> float:
+        v = ctypes.c_double()
+        check(self._lib.sgpe_population_radius(self._ctx, float(fraction), ctypes.byref(v)),
+              "sgpe_population_radius")
+        return v.value
+
+    def winding(self, radius):
+        """(n_up, n_down, raw_up, raw_down): winding numbers along the circle of this radius and
+        the unrounded phase sums over 2 pi."""
+        n = (ctypes.c_int32 * 2)()
+        raw = (ctypes.c_double * 2)()
+        check(self._lib.sgpe_winding(self._ctx, float(radius), n, raw), "sgpe_winding")
+        return int(n[0]), int(n[1]), float(raw[0]), float(raw[1])
+
     # -- measurement / tuning --------------------------------------------------------------
     def profile_steps(self, n, imag=False):
         """Mean per-launch milliseconds of (row pass, column pass) over n steady-state steps."""
