@@ -165,8 +165,11 @@ __device__ __forceinline__ float2 apply_r_full(float2 w, float2 o, const RFull& 
 // R on the thread's 16 points.  For each point index the wave takes one routine: the short one
 // when every lane's angles allow it (the common case), else the general one -- a wave-uniform
 // branch, so a wave never runs both.
+// hbx_r: this lane's h Omega_x / 2 at its P positions, hb_row: h Omega_y / 2 of the row (full
+// 2x2 variant only; loaded by the caller ahead of the transforms).
 template <int N, bool IMAG, bool FULL, int P>
-__device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, int row, int t, bool up) {
+__device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, int row, int t, bool up,
+                                            const float (&hbx_r)[P], float hb_row) {
   constexpr int T = N / P;
   RCoef c;
   c.sgn = up ? 1.0f : -1.0f;
@@ -178,8 +181,6 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
   c.hdelta2 = a.hdelta2;
   const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
   const float hvy = a.hvy * y * y;
-  float hb_row = 0.0f;
-  if constexpr (FULL) hb_row = a.hby[row];
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     const int j = t + T * m;
@@ -192,7 +193,7 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
       if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) v[m] = apply_r_diag<IMAG, true>(v[m], ph);
       else v[m] = apply_r_diag<IMAG, false>(v[m], ph);
     } else {
-      const float hbx = a.hbx[j] + hb_row;
+      const float hbx = hbx_r[m] + hb_row;
       const float2 o = pair_swap(v[m]);
       const float n_oth = fmaf(o.x, o.x, o.y * o.y);
       const RFull f = r_full_angles(n_own, n_oth, hv, c, hbx);
@@ -239,6 +240,14 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
   }
   TwPlain<N, P> tr;
   load_twiddles<N>(tr, t, a.tw);
+  // spatial Raman tables: the x part is the same for every row of the workgroup
+  float hbx_r[P], hby_r[ITERS];
+  if constexpr (FULL && MODE == ROW_STEP) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) hbx_r[m] = a.hbx[t + T * m];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) hby_r[it] = a.hby[row0 + it * a.rows_per_block];
+  }
   float s = 1.0f;
 
 #pragma unroll
@@ -258,7 +267,8 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
       if constexpr (MODE == ROW_STEP) {
-        row_apply_r<N, IMAG, FULL>(v, a, row0 + it * a.rows_per_block, t, comp == 0);
+        row_apply_r<N, IMAG, FULL>(v, a, row0 + it * a.rows_per_block, t, comp == 0, hbx_r,
+                                   FULL ? hby_r[it] : 0.0f);
         fwd_pass<N>(v, lds, t, tr);
       }
     }
