@@ -15,7 +15,11 @@ Schroedinger equation for simulating 2D spinor BECs"):
   Hamiltonian times the time step; real time, or imaginary time (dt -> -i dtau).
 * Splitting -- Sec. 3.2: Strang splitting of the k-space and real-space pieces; one step is
   K(dt/2) R(dt) K(dt/2), where K is the k-space 2x2 propagator reached through a 2D FFT and R the
-  real-space 2x2 exponential of trap, detuning, mean-field and spatial Raman terms.
+  real-space 2x2 exponential of trap, detuning, mean-field and spatial Raman terms.  Variants
+  (``set_splitting``): the other Strang ordering R(dt/2) K(dt) R(dt/2); and R itself split to
+  second order (Sec. 3.2 asks for it because the real-space pieces need not commute) as
+  N(h/2) L(h) N(h/2), N the mean-field phase with the densities of its input, L the exponential
+  of the linear real-space terms.
 * Normalisation -- Sec. 3.2: in imaginary time the order parameter is rescaled to the atom number
   after every step.
 
@@ -119,6 +123,16 @@ class OracleGPE:
         self.bx_k = np.full_like(KX, 0.5 * p.omega)
         self.psi = np.zeros((2, ny, nx), dtype=np.complex128)
         self._uk_cache = {}
+        self.order = "krk"          # or "rkr"
+        self.real_space = "frozen"  # or "nln"
+
+    def set_splitting(self, order="krk", real_space="frozen"):
+        """Strang ordering of a step ("krk": K(dt/2) R(dt) K(dt/2); "rkr": R(dt/2) K(dt) R(dt/2)) and
+        the form of R ("frozen": one closed-form exponential of H_R with the densities of its input;
+        "nln": N(h/2) L(h) N(h/2))."""
+        if order not in ("krk", "rkr") or real_space not in ("frozen", "nln"):
+            raise ValueError("unknown splitting")
+        self.order, self.real_space = order, real_space
 
     # -- state ------------------------------------------------------------------------------
     def set_psi(self, psi):
@@ -181,15 +195,42 @@ class OracleGPE:
         return 0.5 * (d_up + d_dn), 0.5 * self.omega_r, 0.5 * (d_up - d_dn)
 
     def apply_R(self, psi, h, imag):
-        """R(h): densities frozen at entry, then the closed-form 2x2 exponential per point."""
+        """R(h): densities frozen at entry, then the closed-form 2x2 exponential per point; or,
+        with the "nln" split, N(h/2) L(h) N(h/2)."""
+        if self.real_space == "nln":
+            psi = self.apply_N(psi, 0.5 * h, imag)
+            psi = self.apply_L(psi, h, imag)
+            return self.apply_N(psi, 0.5 * h, imag)
         A, Bx, Bz = self.real_space_hamiltonian(psi)
         return apply2x2(exp2x2(A, Bx, Bz, h, imag), psi)
 
+    def apply_N(self, psi, h, imag):
+        """Mean-field part of Eq. (H3) alone: a diagonal phase (or decay) per component with the
+        densities of the input."""
+        p = self.p
+        nu = np.abs(psi[0]) ** 2
+        nd = np.abs(psi[1]) ** 2
+        d_up = p.g_uu * nu + p.g_ud * nd
+        d_dn = p.g_dd * nd + p.g_ud * nu
+        f = (lambda d: np.exp(-h * d)) if imag else (lambda d: np.exp(-1j * h * d))
+        return np.stack([f(d_up) * psi[0], f(d_dn) * psi[1]])
+
+    def apply_L(self, psi, h, imag):
+        """Linear real-space part: trap and detuning (Eq. (H2)) and spatial Raman coupling (Eq. (H4))
+        as one closed-form 2x2 exponential per point."""
+        return apply2x2(exp2x2(self.V, 0.5 * self.omega_r, np.full_like(self.V, 0.5 * self.p.delta), h, imag),
+                        psi)
+
     def step_once(self, psi, imag):
         dt = self.p.dt
-        psi = self.apply_K(psi, 0.5 * dt, imag)
-        psi = self.apply_R(psi, dt, imag)
-        psi = self.apply_K(psi, 0.5 * dt, imag)
+        if self.order == "rkr":
+            psi = self.apply_R(psi, 0.5 * dt, imag)
+            psi = self.apply_K(psi, dt, imag)
+            psi = self.apply_R(psi, 0.5 * dt, imag)
+        else:
+            psi = self.apply_K(psi, 0.5 * dt, imag)
+            psi = self.apply_R(psi, dt, imag)
+            psi = self.apply_K(psi, 0.5 * dt, imag)
         if imag:
             psi = psi * np.sqrt(self.p.norm0 / self.norm_of(psi))
         return psi
