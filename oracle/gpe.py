@@ -37,7 +37,10 @@ Readings where the paper is silent or inconsistent (each one is exercised by a p
    exponentiates the full 2x2 real-space Hamiltonian in closed form.
 6. Normalisation is of the total (both components) to norm0, after each full imaginary step.
 7. Energy per particle: the standard Gross-Pitaevskii functional (not printed in the paper),
-   with one half on the interaction terms.
+   with one half on the interaction terms, of the state rescaled to norm0 -- the quadratic terms
+   divided by the norm N, the quartic (interaction) terms by N^2 / norm0.  For a state of norm
+   norm0 this is the plain functional over norm0; for others it does not depend on the norm, so a
+   small norm error of a complex64 state does not enter the energy at first order.
 
 Everything here is complex128 / float64 and uses NumPy/SciPy only.
 """
@@ -253,12 +256,12 @@ class OracleGPE:
         return self.norm_of(self.psi)
 
     def energy_of(self, psi):
-        """Energy per particle of the Gross-Pitaevskii functional:
+        """Energy per particle of the Gross-Pitaevskii functional at the state rescaled to norm0:
 
         E = (1/N) { (dx dy / N_pts) sum_k psik^dag H_K(k) psik
-                    + dx dy sum_r [ V (n_u + n_d) + delta/2 (n_u - n_d) + Omega(r) Re(psi_u^* psi_d)
-                                    + g_uu n_u^2 / 2 + g_dd n_d^2 / 2 + g_ud n_u n_d ] }
-        with psik the unnormalised 2D DFT of each component.
+                    + dx dy sum_r [ V (n_u + n_d) + delta/2 (n_u - n_d) + Omega(r) Re(psi_u^* psi_d) ] }
+          + (norm0/N^2) dx dy sum_r [ g_uu n_u^2 / 2 + g_dd n_d^2 / 2 + g_ud n_u n_d ]
+        with psik the unnormalised 2D DFT of each component and N the norm of psi.
         """
         p = self.p
         w = self.dx * self.dy
@@ -271,10 +274,10 @@ class OracleGPE:
         nu = np.abs(psi[0]) ** 2
         nd = np.abs(psi[1]) ** 2
         cross_r = np.real(np.conj(psi[0]) * psi[1])
-        e_r = np.sum(self.V * (nu + nd) + 0.5 * p.delta * (nu - nd) + self.omega_r * cross_r
-                     + 0.5 * p.g_uu * nu * nu + 0.5 * p.g_dd * nd * nd + p.g_ud * nu * nd)
-        total = w / npts * float(e_k) + w * float(e_r)
-        return total / self.norm_of(psi)
+        e_lin = np.sum(self.V * (nu + nd) + 0.5 * p.delta * (nu - nd) + self.omega_r * cross_r)
+        e_int = np.sum(0.5 * p.g_uu * nu * nu + 0.5 * p.g_dd * nd * nd + p.g_ud * nu * nd)
+        nrm = self.norm_of(psi)
+        return (w / npts * float(e_k) + w * float(e_lin)) / nrm + w * float(e_int) * p.norm0 / (nrm * nrm)
 
     def energy(self):
         return self.energy_of(self.psi)

@@ -296,6 +296,9 @@ def test_energy_functional_gaussian_closed_form():
     # the odd Omega(x) and the spin-momentum term average to zero for this even, real state.
     e_exact = 1.0 + p.norm0 * (0.5 * gu + 0.5 * gd + gud) / (8 * math.pi) + 0.5 * om
     assert abs(o.energy() - e_exact) < 1e-11
+    # the energy is that of the state rescaled to norm0: any other norm gives the same value
+    o.set_psi(1.7 * np.stack([phi, phi]).astype(complex))
+    assert abs(o.energy() - e_exact) < 1e-11
     # Detuning: +delta/2 (N_up - N_dn) / N.
     p2 = p.replace(delta=0.6)
     o2 = OracleGPE(p2)
