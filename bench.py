@@ -58,10 +58,9 @@ def _traffic_record(kernel_name, workload):
         return None
 
 
-def cpu_baseline(p, psi0, seconds):
+def _oracle_rate(p, psi0, seconds, workers):
     from oracle import OracleGPE
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    o = OracleGPE(p, workers=cores)
+    o = OracleGPE(p, workers=workers)
     o.set_psi(psi0)
     o.step_imag(1)  # warm-up (plans, caches)
     n, t0 = 0, time.perf_counter()
@@ -70,10 +69,18 @@ def cpu_baseline(p, psi0, seconds):
         n += 1
         el = time.perf_counter() - t0
         if el >= seconds:
-            break
+            return n, el
+
+
+def cpu_baseline(p, psi0, seconds, single_seconds):
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    n, el = _oracle_rate(p, psi0, seconds, cores)
+    n1, el1 = _oracle_rate(p, psi0, single_seconds, 1)
     return {"value": n / el, "unit": "split-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} imaginary-time steps of the 1024^2 x 2 workload in complex128 "
-                      f"({el:.1f} s, scipy.fft workers={cores})"}
+                      f"({el:.1f} s, scipy.fft workers={cores})",
+            "single_thread": {"value": n1 / el1, "unit": "split-steps/s", "cores": 1,
+                              "sample": f"{n1} steps ({el1:.1f} s, workers=1)"}}
 
 
 def other_grids(torch, stream, timed, p, steps=500, warmup=50):
@@ -188,6 +195,44 @@ def _load_surrogate(torch):
     return model
 
 
+def ground_2048_convergence(torch, stream, every=10, tol=1e-9, max_steps=150000):
+    """The large ground state at full size: 2048^2, Omega(x) = 2 tanh(x/4) in the real-space
+    exponential, g = 50, trap aspect 1.5, Thomas-Fermi start; imaginary-time steps until the first
+    check (every `every` steps) with |E_n - E_{n-every}| < tol |E_n|.  Also reported: the wall
+    time at which the energy first came within 1e-6 of the final one (read off the same checks)."""
+    from paper_2010_15069_amd import Solver
+    from workloads import initial_state, preset
+    p = preset("ground_2048")
+    psi0 = initial_state(p, "tf", seed=0)
+    s = Solver(p, stream=stream.cuda_stream)
+    s.set_psi(psi0)
+    s.step_imag(every)
+    s.energy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_psi(psi0)
+    e_prev, steps, trace = s.energy(), 0, []
+    converged = False
+    while steps < max_steps:
+        s.step_imag(every)
+        steps += every
+        e = s.energy()
+        trace.append((steps, time.perf_counter() - t0, e))
+        if abs(e - e_prev) < tol * abs(e):
+            converged = True
+            break
+        e_prev = e
+    el = time.perf_counter() - t0
+    s.close()
+    e_fin = trace[-1][2]
+    hit = next(((st, t) for st, t, e in trace if abs(e - e_fin) <= 1e-6 * abs(e_fin)), (None, None))
+    return {"workload": "ground_2048: 2048x2048 x 2, Omega(x) = 2 tanh(x/4) (real space), g = 50 (all), "
+                        "k_L = 2, wx = 1, wy = 1.5, imaginary-time dt = 1e-3, Thomas-Fermi start",
+            "stop_rule": f"|E_n - E_(n-{every})| < {tol:g} |E_n|, checked every {every} steps (checks timed)",
+            "converged": converged, "steps": steps, "seconds": el, "energy": e_fin,
+            "steps_to_1e-6_of_final": hit[0], "seconds_to_1e-6_of_final": hit[1]}
+
+
 def ground_state_learned(torch, stream, model, check_every=50, max_steps=200000):
     """The ground-state time-to-solution of the same workload from the learned start: the timed
     region holds the input encoding, the network's forward pass, set_psi and the checked steps."""
@@ -260,6 +305,24 @@ def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_ever
             "learned": {"reached": len(sl), "steps_median": med(sl), "batch_seconds_median": med(tl)}}
 
 
+def splitting_variants(torch, stream, timed, p, p_imag, psi0, steps=600, warmup=30):
+    """Throughput of the splitting variants on the headline workload (1024^2): K-R-K with the
+    N L N real-space split, R-K-R, R-K-R with N L N; imaginary and real time."""
+    from paper_2010_15069_amd import Solver
+    out = {}
+    for order, rs in (("krk", "nln"), ("rkr", "frozen"), ("rkr", "nln")):
+        res = {}
+        for kind, pp in (("imag", p_imag), ("real", p)):
+            s = Solver(pp, stream=stream.cuda_stream).set_splitting(order, rs).set_psi(psi0)
+            step = s.step_imag if kind == "imag" else s.step_real
+            step(warmup)
+            total_ms, _ = timed(step, steps, 100)
+            res[kind] = steps / (total_ms * 1e-3)
+            s.close()
+        out[f"{order}+{rs}"] = {"split_steps_per_s_imag": res["imag"], "split_steps_per_s_real": res["real"]}
+    return out
+
+
 def spin_hall_trial(torch):
     """One spin-Hall trial (Sec. 6) at 1024^2: vortex-seeded start, 60000 annealed and 60000
     plain imaginary-time steps with the Raman profile Omega(y), then the observables."""
@@ -282,11 +345,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-single-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ground", action="store_true", help="skip the ground-state time-to-solution")
     ap.add_argument("--no-other-grids", action="store_true", help="skip the 512^2 and 2048^2 lines")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched parameter sweep")
     ap.add_argument("--no-spin-hall", action="store_true", help="skip the spin-Hall trial")
+    ap.add_argument("--ground-2048", type=int, default=0, metavar="MAX_STEPS",
+                    help="also run the 2048^2 ground state to |dE|/E < 1e-9 per 10 steps (at most MAX_STEPS)")
     ap.add_argument("--workload", default="metric_1024")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the HBM "
@@ -378,6 +444,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "seed": 0,
+        "device": torch.cuda.get_device_name(0),
+        "rocm": getattr(torch.version, "hip", None),
         "config": {
             "workload": f"{args.workload}: {p.nx}x{p.ny} grid x 2 components, complex64 state, "
                         f"imaginary-time Strang split steps with renormalisation, g=10 (all), k_L=2, "
@@ -401,8 +470,11 @@ def main():
     s.close()
     if not args.no_other_grids:
         out["other_grids"] = other_grids(torch, stream, timed, p)
+        out["splitting_variants"] = splitting_variants(torch, stream, timed, p, p_imag, psi0)
     if not args.no_ground:
         out["ground_state"] = ground_state_time(torch, stream)
+        if args.ground_2048:
+            out["ground_2048"] = ground_2048_convergence(torch, stream, max_steps=args.ground_2048)
         model = _load_surrogate(torch)
         if model is not None:
             out["ground_state"]["learned_start"] = ground_state_learned(torch, stream, model)
@@ -414,7 +486,7 @@ def main():
     if not args.no_spin_hall:
         out["spin_hall_trial"] = spin_hall_trial(torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds, args.cpu_single_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -21,8 +21,9 @@
  *   - imaginary time rescales the total (both components) to norm0 after every step;
  *   - grid x_j = -xmax + j*dx, dx = 2*xmax/nx (periodic, endpoint excluded), k_x in FFT order
  *     with the Nyquist bin at -pi/dx; the same along y;
- *   - energy per particle: the Gross-Pitaevskii functional with 1/2 on the interaction terms,
- *     divided by the norm.
+ *   - energy per particle: the Gross-Pitaevskii functional with 1/2 on the interaction terms, of
+ *     the state rescaled to norm0 (quadratic terms over the norm N, interaction terms over
+ *     N^2 / norm0), so that the norm of a complex64 state does not enter at first order.
  *
  * Threading: a context is not thread-safe; distinct contexts are independent.
  * Errors: every call returns a status; nothing aborts and no C++ exception crosses the ABI.
@@ -104,8 +105,9 @@ sgpe_status sgpe_step_real(sgpe_ctx* ctx, int64_t n);
  * (Sec. 3.2).  Asynchronous.  Errors as sgpe_step_real. */
 sgpe_status sgpe_step_imag(sgpe_ctx* ctx, int64_t n);
 
-/* Energy per particle of the current state (Gross-Pitaevskii functional, Eqs. (H1)-(H4) with
- * 1/2 on the interaction terms, divided by the norm).  Accumulated in fp64.  Synchronises. */
+/* Energy per particle of the current state rescaled to norm0 (Gross-Pitaevskii functional, Eqs.
+ * (H1)-(H4) with 1/2 on the interaction terms; quadratic terms over the norm N, interaction terms
+ * over N^2 / norm0).  Accumulated in fp64.  Synchronises. */
 sgpe_status sgpe_energy(sgpe_ctx* ctx, double* e_per_particle);
 
 /* Norm dx dy sum |psi|^2 of the current state (both components), accumulated in fp64.
@@ -131,6 +133,21 @@ sgpe_status sgpe_profile_steps(sgpe_ctx* ctx, int32_t imag, int64_t n,
  * buffer on first use.  Synchronises.  Either output pointer may be NULL. */
 sgpe_status sgpe_profile_kernels(sgpe_ctx* ctx, int32_t imag, int64_t n,
                                  double* row_ms, double* col_ms);
+
+/* Splitting variants (Sec. 3.2).  order: SGPE_SPLIT_KRK, one step = K(dt/2) R(dt) K(dt/2) (the
+ * default), or SGPE_SPLIT_RKR, one step = R(dt/2) K(dt) R(dt/2).  real_space: SGPE_RSPLIT_FROZEN,
+ * R(h) = one closed-form 2x2 exponential of H_R with the densities of its input (the default), or
+ * SGPE_RSPLIT_NLN, R(h) = N(h/2) L(h) N(h/2) with N the mean-field phase (Eq. H3) with the densities
+ * of its input and L the exponential of the linear real-space terms (Eqs. H2, H4) -- second order
+ * also when g_uu != g_dd and a spatial Raman coupling is present.  Imaginary time normalises after
+ * every step in every variant.  Cost per step: two sweeps, except R-K-R in imaginary time (three:
+ * the norm is needed between the two R halves of consecutive steps).  The variants run the
+ * general row pass without prefetching; sgpe_profile_steps and sgpe_profile_kernels measure the
+ * default only and return SGPE_ESTATE under a variant.  Takes effect for the next step call.
+ * Errors: SGPE_EINVAL (NULL context, unknown value). */
+typedef enum { SGPE_SPLIT_KRK = 0, SGPE_SPLIT_RKR = 1 } sgpe_split_order;
+typedef enum { SGPE_RSPLIT_FROZEN = 0, SGPE_RSPLIT_NLN = 1 } sgpe_real_space_split;
+sgpe_status sgpe_set_splitting(sgpe_ctx* ctx, int32_t order, int32_t real_space);
 
 /* Spatially varying Raman coupling Omega(x, y) = Omega_x(x) + Omega_y(y) of the real-space
  * Hamiltonian ((Omega/2) sigma_x in H_R, Eq. (H4) with a position-dependent Omega; Sec. 6 uses a

@@ -89,14 +89,12 @@ sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y) {
   return SGPE_OK;
 }
 
-// Forward roots exp(-2 pi i j / n), each as an fp32 hi part and the fp32 rounding of the rest.
-std::vector<float4> twiddles(int n) {
-  std::vector<float4> t(n);
-  for (int j = 0; j < n; ++j) {
+// Forward roots exp(-2 pi i j / n), j < n / 2, in fp64 (energy kernels).
+std::vector<double2> twiddles64(int n) {
+  std::vector<double2> t(n / 2 > 0 ? n / 2 : 1);
+  for (int j = 0; j < n / 2; ++j) {
     const double a = -2.0 * M_PI * double(j) / double(n);
-    const double c = std::cos(a), s = std::sin(a);
-    const float ch = float(c), sh = float(s);
-    t[j] = make_float4(ch, sh, float(c - double(ch)), float(s - double(sh)));
+    t[j] = make_double2(std::cos(a), std::sin(a));
   }
   return t;
 }
@@ -233,7 +231,7 @@ sgpe_status status_of(hipError_t e) {
   return SGPE_EDEVICE;
 }
 
-RowArgs row_args(const sgpe_ctx* c) {
+RowArgs row_args(const sgpe_ctx* c, double h_sub) {
   const sgpe_params& p = c->p;
   RowArgs a{};
   a.psi = c->psi;
@@ -253,7 +251,8 @@ RowArgs row_args(const sgpe_ctx* c) {
   a.dx = float(dx);
   a.y0 = float(-p.ymax);
   a.dy = float(dy);
-  const double h = p.dt;
+  const double h = h_sub > 0.0 ? h_sub : p.dt;
+  a.hfrac = float(h / p.dt);
   a.hvx = float(0.5 * h * p.wx * p.wx);
   a.hvy = float(0.5 * h * p.wy * p.wy);
   a.hdelta2 = float(0.5 * h * p.delta);
@@ -281,8 +280,14 @@ ColArgs col_args(const sgpe_ctx* c, bool imag, bool half) {
 
 // The fused schedule of n steps: K(dt/2) [R K(dt)]^(n-1) R K(dt/2), with the normalisation of
 // step i applied (as a scale) at the start of the next row pass.
+static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag);
+
 sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev) {
   if (n == 0) return SGPE_OK;
+  if (c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
+    if (ev) return SGPE_ESTATE;
+    return run_steps_variant(c, n, imag);
+  }
   const double npts = double(c->p.nx) * double(c->p.ny);
   const float inv_n = float(1.0 / npts);  // exact: a power of two
   hipStream_t s = c->stream;
@@ -317,6 +322,75 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
     r.n_partials = col_groups(c);
   }
   e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_iters, c->row_points, s);
+  return status_of(e);
+}
+
+// The splitting variants (sgpe_set_splitting), built from the general row pass:
+//   K-R-K with R as N L N:  row FWD; col K(dt/2); n x [row (inv-x, scale, R(dt), fwd-x); col K]; row INV
+//     -- the fused schedule above with the general row pass in place of the step row pass;
+//   R-K-R, real time:       row (R(dt/2), fwd-x); n x [col K(dt); row (inv-x, R(dt/2), R(dt/2), fwd-x)],
+//                           the last row pass (inv-x, R(dt/2)) only;
+//   R-K-R, imaginary time:  the norm falls between the two R halves, so each step's row work takes
+//                           two passes: (inv-x, R(dt/2), norm partials) and (scale, R(dt/2), fwd-x).
+static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag) {
+  if (n == 0) return SGPE_OK;
+  const sgpe_params& p = c->p;
+  const double npts = double(p.nx) * double(p.ny);
+  const float inv_n = float(1.0 / npts);
+  const int rs = c->split_rs;
+  const int row_groups = p.ny / c->rows;
+  hipStream_t s = c->stream;
+  hipError_t e = hipSuccess;
+  auto row = [&](double h, int flags, int nr, const double* parts, int nparts, bool real_space_parts) {
+    RowArgs r = row_args(c, h);
+    r.var_flags = flags;
+    r.var_r = nr;
+    r.var_nln = rs;
+    r.scale = (flags & sgpe::VAR_INV) ? inv_n : 1.0f;
+    r.partials = parts;
+    r.n_partials = nparts;
+    if (real_space_parts) {
+      r.parseval_w = (2.0 * p.xmax / p.nx) * (2.0 * p.ymax / p.ny);
+      r.inv_npts = 1.0;
+    }
+    r.partials_out = c->partials;
+    if (e == hipSuccess) e = sgpe::launch_row(r, sgpe::ROW_VAR, imag, c->full2x2, 1, c->row_points, s);
+  };
+  auto col = [&](bool half, int norm_mode) {
+    if (e == hipSuccess) e = sgpe::launch_col(col_args(c, imag, half), norm_mode, c->col_iters, c->col_points, s);
+  };
+  if (c->split_order == SGPE_SPLIT_KRK) {
+    RowArgs ra = row_args(c);
+    e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_iters, c->row_points, s);
+    col(true, sgpe::NORM_NONE);
+    for (int64_t i = 1; i <= n; ++i) {
+      const bool scaled = imag && i > 1;
+      row(p.dt, sgpe::VAR_INV | sgpe::VAR_FWD, 1, scaled ? c->partials : nullptr, scaled ? col_groups(c) : 0, false);
+      const bool last = (i == n);
+      col(last, imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE);
+    }
+    RowArgs r = ra;
+    r.scale = inv_n;
+    if (imag) {
+      r.partials = c->partials;
+      r.n_partials = col_groups(c);
+    }
+    if (e == hipSuccess) e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_iters, c->row_points, s);
+    return status_of(e);
+  }
+  // R-K-R
+  const double h = 0.5 * p.dt;
+  row(h, sgpe::VAR_FWD, 1, nullptr, 0, false);
+  for (int64_t i = 1; i <= n; ++i) {
+    col(false, sgpe::NORM_NONE);
+    const bool last = (i == n);
+    if (!imag) {
+      row(h, last ? sgpe::VAR_INV : (sgpe::VAR_INV | sgpe::VAR_FWD), last ? 1 : 2, nullptr, 0, false);
+    } else {
+      row(h, sgpe::VAR_INV | sgpe::VAR_NORM_OUT, 1, nullptr, 0, false);
+      row(h, last ? sgpe::VAR_SCALE : (sgpe::VAR_SCALE | sgpe::VAR_FWD), last ? 0 : 1, c->partials, row_groups, true);
+    }
+  }
   return status_of(e);
 }
 
@@ -408,7 +482,8 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
   default_schedule(c);
   c->full2x2 = (p->omega_r0 != 0.0);
-  if (sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds) {
+  if (sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds ||
+      !sgpe::energy_fits(p->nx, p->ny, c->max_lds)) {
     delete c;
     return SGPE_ENOMEM;
   }
@@ -426,8 +501,8 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
     c->psi = static_cast<float4*>(ptr);
     c->own_psi = true;
   }
-  if ((st = upload(c, &c->tw_x, twiddles(p->nx))) != SGPE_OK) return fail(st);
-  if ((st = upload(c, &c->tw_y, twiddles(p->ny))) != SGPE_OK) return fail(st);
+  if ((st = upload(c, &c->twd_x, twiddles64(p->nx))) != SGPE_OK) return fail(st);
+  if ((st = upload(c, &c->twd_y, twiddles64(p->ny))) != SGPE_OK) return fail(st);
   if ((st = upload(c, &c->twp_x, twiddles_plain(p->nx))) != SGPE_OK) return fail(st);
   if ((st = upload(c, &c->twp_y, twiddles_plain(p->ny))) != SGPE_OK) return fail(st);
   for (int imag = 0; imag < 2; ++imag) {
@@ -449,7 +524,9 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
   void* ptr = nullptr;
   if ((st = dev_alloc(c, &ptr, kMaxPartials * sizeof(double))) != SGPE_OK) return fail(st);
   c->partials = static_cast<double*>(ptr);
-  if ((st = dev_alloc(c, &ptr, (2 * size_t(kMaxN) + kMaxPartials) * sizeof(double))) != SGPE_OK) return fail(st);
+  if ((st = dev_alloc(c, &ptr, (sgpe::kEnergyRowParts * size_t(kMaxN) + kMaxPartials) * sizeof(double))) !=
+      SGPE_OK)
+    return fail(st);
   c->epart = static_cast<double*>(ptr);
   if ((st = dev_alloc(c, &ptr, sgpe::norm_blocks() * sizeof(double))) != SGPE_OK) return fail(st);
   c->npart = static_cast<double*>(ptr);
@@ -584,6 +661,18 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
   *out = dx * dy * s;
   if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
   return c->latched;
+}
+
+sgpe_status sgpe_set_splitting(sgpe_ctx* c, int32_t order, int32_t real_space) {
+  if (!c) return SGPE_EINVAL;
+  if ((order != SGPE_SPLIT_KRK && order != SGPE_SPLIT_RKR) ||
+      (real_space != SGPE_RSPLIT_FROZEN && real_space != SGPE_RSPLIT_NLN))
+    return SGPE_EINVAL;
+  const int row_groups = c->p.ny / c->rows;
+  if (order == SGPE_SPLIT_RKR && row_groups > kMaxPartials) return SGPE_EINVAL;
+  c->split_order = order;
+  c->split_rs = real_space;
+  return SGPE_OK;
 }
 
 sgpe_status sgpe_set_raman_profile(sgpe_ctx* c, const double* omega_x, const double* omega_y) {
@@ -742,21 +831,20 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   if (!c->has_state) return SGPE_ESTATE;
   const sgpe_params& p = c->p;
   const size_t npts = size_t(p.nx) * size_t(p.ny);
-  if (!c->scratch) {
+  if (!c->scratch64) {
     void* ptr = nullptr;
-    if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return st;
-    c->scratch = static_cast<float4*>(ptr);
+    if ((st = dev_alloc(c, &ptr, npts * sizeof(double4))) != SGPE_OK) return st;
+    c->scratch64 = static_cast<double4*>(ptr);
   }
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
   EnergyArgs a{};
   a.psi = c->psi;
-  a.scratch = c->scratch;
+  a.scratch = c->scratch64;
   a.nx = p.nx;
   a.ny = p.ny;
-  a.rows_per_block = sgpe::energy_rows_per_block(p.nx, p.ny, c->max_lds);
   a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
-  a.twx = c->tw_x;
-  a.twy = c->tw_y;
+  a.twx = c->twd_x;
+  a.twy = c->twd_y;
   a.xmin = -p.xmax;
   a.dx = dx;
   a.ymin = -p.ymax;
@@ -773,28 +861,32 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   a.om_y = c->full2x2 ? c->omy : nullptr;
   a.dkx = M_PI / p.xmax;
   a.dky = M_PI / p.ymax;
-  const int nrb = p.ny / a.rows_per_block;
+  const int nrb = p.ny;  // one row per row-kernel workgroup
   const int ncb = p.nx / a.cols;
+  constexpr int RP = sgpe::kEnergyRowParts;
   a.row_partials = c->epart;
-  a.col_partials = c->epart + 2 * nrb;
+  a.col_partials = c->epart + RP * nrb;
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e != hipSuccess) return status_of(e);
-  std::vector<double> part(2 * size_t(nrb) + ncb);
+  std::vector<double> part(RP * size_t(nrb) + ncb);
   if (hipMemcpyAsync(part.data(), c->epart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
           hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipGetLastError();
     return SGPE_EDEVICE;
   }
-  double er = 0.0, nr = 0.0, ek = 0.0;
+  double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
   for (int b = 0; b < nrb; ++b) {
-    er += part[2 * b];
-    nr += part[2 * b + 1];
+    er += part[RP * b];
+    ei += part[RP * b + 1];
+    nr += part[RP * b + 2];
   }
-  for (int b = 0; b < ncb; ++b) ek += part[2 * nrb + b];
+  for (int b = 0; b < ncb; ++b) ek += part[RP * nrb + b];
+  // per particle of the state rescaled to norm0: quadratic terms over the norm, the interaction
+  // (quartic) terms over norm^2 / norm0
   const double w = dx * dy;
-  const double total = w / double(npts) * ek + w * er;
-  *out = total / (w * nr);
+  const double nrm = w * nr;
+  *out = (w / double(npts) * ek + w * er) / nrm + w * ei * p.norm0 / (nrm * nrm);
   if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
   return c->latched;
 }
@@ -803,7 +895,7 @@ sgpe_status sgpe_profile_steps(sgpe_ctx* c, int32_t imag, int64_t n, double* row
   sgpe_status st = check_ctx(c);
   if (st != SGPE_OK) return st;
   if (n <= 0) return SGPE_EINVAL;
-  if (!c->has_state) return SGPE_ESTATE;
+  if (!c->has_state || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) return SGPE_ESTATE;
   std::vector<hipEvent_t> ev(3 * size_t(n));
   for (auto& x : ev) {
     if (hipEventCreate(&x) != hipSuccess) {
@@ -834,7 +926,7 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* c, int32_t imag, int64_t n, double* r
   sgpe_status st = check_ctx(c);
   if (st != SGPE_OK) return st;
   if (n <= 0) return SGPE_EINVAL;
-  if (!c->has_state) return SGPE_ESTATE;
+  if (!c->has_state || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) return SGPE_ESTATE;
   const sgpe_params& p = c->p;
   const size_t bytes = size_t(p.nx) * size_t(p.ny) * sizeof(float4);
   if (!c->scratch) {

@@ -1,25 +1,16 @@
-// Device building blocks of the split-step solver: register-resident Stockham FFT passes,
-// compensated (hi + lo) twiddle products, the (U - 1) sine/cosine helper used by the
-// unit-modulus real-space propagators, lane-pair exchange and fp64 reductions.
+// Device building blocks of the split-step solver's step kernels: register-resident Stockham FFT
+// passes, the (U - 1) sine/cosine helpers of the unit-modulus real-space propagators, lane-pair
+// exchange and fp64 reductions.
 //
-// The FFT code is generic over the per-position value type V:
-//   float2 -- one complex number (the step kernels: each thread owns one spinor component and
-//             the neighbouring lane owns the other component of the same positions);
-//   float4 -- both components {re_up, im_up, re_dn, im_dn} of a position (energy kernels).
-//
-// FFT organisation (transform length N = 16^a * r, r in {1, 2, 4, 8}): T = N/16 threads own one
-// transform, thread t holding the 16 positions t + T*m (m = 0..15).  Each Stockham stage of radix
-// R performs 16/R butterflies per thread on registers {u + (16/R) r}; the outputs of every stage
-// but the last go through LDS, and the last stage's outputs land back in the thread's own
-// registers in natural order.  So the first stage reads and the last stage writes the positions
-// t + T*m, which are contiguous across threads: global loads and stores are coalesced and no
-// digit-reversal pass exists.
-//
-// Accuracy: fp32 twiddles rounded once are off the unit circle by ~3e-8, and the same error is
-// re-applied every step, so it accumulates coherently over thousands of steps.  Every
-// non-trivial twiddle -- the stage twiddles from the table and the constants inside the radix-8
-// and radix-16 butterflies -- is therefore applied as z*w_hi + z*w_lo with w_hi + w_lo equal to the
-// exact root of unity to ~1e-15.
+// FFT organisation (transform length N, P points per lane, P in {4, 8, 16}): T = N/P lanes own one
+// transform, lane t holding the P positions t + T*m (m = 0..P-1); in the step kernels each lane
+// owns one spinor component and the neighbouring lane the other component of the same positions.
+// Each Stockham stage of radix R (P, then a smaller remainder) performs P/R butterflies per lane on
+// registers; the outputs of every stage but the last go through LDS, and the last stage's outputs
+// land back in the lane's own registers in natural order.  So the first stage reads and the last
+// stage writes the positions t + T*m, which are contiguous across lanes: global loads and stores
+// are coalesced and no digit-reversal pass exists.  Roots are rounded once to fp32; the inverse
+// transform is the exact inverse of the forward one (see "Step-kernel transforms" below).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,138 +35,6 @@ __device__ __forceinline__ float4 vscale(float4 a, float s) {
   return make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
 }
 
-// Multiply by exp(DIR * i*pi/2) = DIR * i  (DIR = -1: forward transform sign).
-template <int DIR>
-__device__ __forceinline__ float2 rot90(float2 a) {
-  if constexpr (DIR < 0) return make_float2(a.y, -a.x);
-  else return make_float2(-a.y, a.x);
-}
-template <int DIR>
-__device__ __forceinline__ float4 rot90(float4 a) {
-  if constexpr (DIR < 0) return make_float4(a.y, -a.x, a.w, -a.z);
-  else return make_float4(-a.y, a.x, -a.w, a.z);
-}
-
-// z * (c + i*DIR*s) with c = ch + cl and s = sh + sl given as hi/lo pairs; the lo products form
-// the innermost term of each fused multiply-add chain.
-template <int DIR>
-__device__ __forceinline__ float2 cmul_comp(float2 a, float ch, float cl, float sh, float sl) {
-  const float dsh = DIR < 0 ? -sh : sh;
-  const float dsl = DIR < 0 ? -sl : sl;
-  const float lo_r = fmaf(a.x, cl, -a.y * dsl);
-  const float lo_i = fmaf(a.x, dsl, a.y * cl);
-  return make_float2(fmaf(a.x, ch, fmaf(-a.y, dsh, lo_r)), fmaf(a.x, dsh, fmaf(a.y, ch, lo_i)));
-}
-template <int DIR>
-__device__ __forceinline__ float4 cmul_comp(float4 a, float ch, float cl, float sh, float sl) {
-  const float2 u = cmul_comp<DIR>(make_float2(a.x, a.y), ch, cl, sh, sl);
-  const float2 d = cmul_comp<DIR>(make_float2(a.z, a.w), ch, cl, sh, sl);
-  return make_float4(u.x, u.y, d.x, d.y);
-}
-
-// Multiply by a table twiddle w = exp(-2 pi i j / N) stored as {re_hi, im_hi, re_lo, im_lo};
-// the inverse transform (DIR = +1) uses conj(w).
-template <int DIR, class V>
-__device__ __forceinline__ V twmul(V a, float4 w) {
-  return cmul_comp<DIR>(a, w.x, w.z, -w.y, -w.w);
-}
-
-// Compensated split constants (value = hi + lo to fp64 accuracy).
-#define SGPE_R2_HI 0.70710676908493042f   // 1/sqrt(2)
-#define SGPE_R2_LO 1.21016175e-08f
-#define SGPE_C8_HI 0.92387950420379639f   // cos(pi/8)
-#define SGPE_C8_LO 2.83074897e-08f
-#define SGPE_S8_HI 0.38268342614173889f   // sin(pi/8)
-#define SGPE_S8_LO 6.22335072e-09f
-
-__device__ __forceinline__ float r2mul(float s) { return fmaf(s, SGPE_R2_HI, s * SGPE_R2_LO); }
-
-// exp(DIR*i*pi/4) * z = (1 + DIR i)/sqrt(2) * z
-template <int DIR>
-__device__ __forceinline__ float2 rot45(float2 a) {
-  if constexpr (DIR < 0) return make_float2(r2mul(a.x + a.y), r2mul(a.y - a.x));
-  else return make_float2(r2mul(a.x - a.y), r2mul(a.x + a.y));
-}
-template <int DIR>
-__device__ __forceinline__ float4 rot45(float4 a) {
-  const float2 u = rot45<DIR>(make_float2(a.x, a.y));
-  const float2 d = rot45<DIR>(make_float2(a.z, a.w));
-  return make_float4(u.x, u.y, d.x, d.y);
-}
-
-// ---------------------------------------------------------------------------------------------
-// Small DFTs in registers, natural order in and out: y_k = sum_r x_r exp(DIR 2 pi i r k / R).
-// ---------------------------------------------------------------------------------------------
-template <int DIR, class V>
-__device__ __forceinline__ void dft4(V& a0, V& a1, V& a2, V& a3) {
-  const V t0 = vadd(a0, a2), t1 = vsub(a0, a2);
-  const V t2 = vadd(a1, a3), t3 = rot90<DIR>(vsub(a1, a3));
-  a0 = vadd(t0, t2);
-  a2 = vsub(t0, t2);
-  a1 = vadd(t1, t3);
-  a3 = vsub(t1, t3);
-}
-
-template <int DIR, class V>
-__device__ __forceinline__ void dft8(V (&a)[8]) {
-  V e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
-  V o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
-  dft4<DIR>(e0, e1, e2, e3);
-  dft4<DIR>(o0, o1, o2, o3);
-  o1 = rot45<DIR>(o1);
-  o2 = rot90<DIR>(o2);
-  o3 = rot90<DIR>(rot45<DIR>(o3));
-  a[0] = vadd(e0, o0); a[4] = vsub(e0, o0);
-  a[1] = vadd(e1, o1); a[5] = vsub(e1, o1);
-  a[2] = vadd(e2, o2); a[6] = vsub(e2, o2);
-  a[3] = vadd(e3, o3); a[7] = vsub(e3, o3);
-}
-
-// 16-point DFT as 4x4: input index r = r1 + 4 r2, output k = k2 + 4 k1.
-template <int DIR, class V>
-__device__ __forceinline__ void dft16(V (&a)[16]) {
-#pragma unroll
-  for (int r1 = 0; r1 < 4; ++r1) dft4<DIR>(a[r1], a[r1 + 4], a[r1 + 8], a[r1 + 12]);
-  // slot r1 + 4 k2 holds A[r1][k2]; multiply by W16^(r1 k2):
-  // W16^1 = c8 + i DIR s8, W16^2 = rot45, W16^3 = s8 + i DIR c8, W16^4 = rot90,
-  // W16^6 = rot90 rot45, W16^9 = -W16^1.
-  a[5] = cmul_comp<DIR>(a[5], SGPE_C8_HI, SGPE_C8_LO, SGPE_S8_HI, SGPE_S8_LO);    // (1,1): 1
-  a[9] = rot45<DIR>(a[9]);                                                       // (1,2): 2
-  a[13] = cmul_comp<DIR>(a[13], SGPE_S8_HI, SGPE_S8_LO, SGPE_C8_HI, SGPE_C8_LO);  // (1,3): 3
-  a[6] = rot45<DIR>(a[6]);                                                       // (2,1): 2
-  a[10] = rot90<DIR>(a[10]);                                                     // (2,2): 4
-  a[14] = rot90<DIR>(rot45<DIR>(a[14]));                                         // (2,3): 6
-  a[7] = cmul_comp<DIR>(a[7], SGPE_S8_HI, SGPE_S8_LO, SGPE_C8_HI, SGPE_C8_LO);    // (3,1): 3
-  a[11] = rot90<DIR>(rot45<DIR>(a[11]));                                         // (3,2): 6
-  a[15] = vneg(cmul_comp<DIR>(a[15], SGPE_C8_HI, SGPE_C8_LO, SGPE_S8_HI, SGPE_S8_LO));  // (3,3): 9
-#pragma unroll
-  for (int k2 = 0; k2 < 4; ++k2) dft4<DIR>(a[4 * k2], a[4 * k2 + 1], a[4 * k2 + 2], a[4 * k2 + 3]);
-  // slot k1 + 4 k2 now holds y[k2 + 4 k1]: transpose the 4x4 register tile (renaming only).
-  V t[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) t[i] = a[i];
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) a[k2 + 4 * k1] = t[k1 + 4 * k2];
-}
-
-template <int R, int DIR, class V>
-__device__ __forceinline__ void dft(V (&a)[R]) {
-  if constexpr (R == 2) {
-    const V t = a[0];
-    a[0] = vadd(t, a[1]);
-    a[1] = vsub(t, a[1]);
-  } else if constexpr (R == 4) {
-    dft4<DIR>(a[0], a[1], a[2], a[3]);
-  } else if constexpr (R == 8) {
-    dft8<DIR>(a);
-  } else {
-    static_assert(R == 16, "radix");
-    dft16<DIR>(a);
-  }
-}
-
 // ---------------------------------------------------------------------------------------------
 // LDS addressing: a transform's N positions occupy N + N/16 slots (one pad slot per 16
 // positions) and `stride` transforms are interleaved slot by slot, so that lanes which own
@@ -187,94 +46,6 @@ struct LdsView {
   int shift;   // log2 of the number of interleaved transforms (a power of two)
   __device__ __forceinline__ V& at(int pos) const { return base[(pos + (pos >> 4)) << shift]; }
 };
-
-// Stage twiddles a thread needs for a length-N transform: the first stage (L = 1) needs none;
-// a later stage of radix R uses W_N^(s r N/(R L)) for its 16/R butterflies and r = 1..R-1.
-template <int N, int L = 1>
-constexpr int tw_count() {
-  constexpr int REM = N / L;
-  constexpr int R = REM >= 16 ? 16 : REM;
-  constexpr int here = L > 1 ? (16 / R) * (R - 1) : 0;
-  if constexpr (R == REM) return here;
-  else return here + tw_count<N, L * R>();
-}
-
-// Per-thread register copy of those twiddles, loaded once per kernel (they depend only on the
-// thread index) and shared by the forward and inverse transforms (the inverse conjugates).
-template <int N>
-struct TwRegs {
-  static constexpr int COUNT = tw_count<N>() > 0 ? tw_count<N>() : 1;
-  float4 w[COUNT];
-};
-
-template <int N, int L = 1, int BASE = 0>
-__device__ __forceinline__ void load_twiddles(TwRegs<N>& tr, int t, const float4* __restrict__ tw) {
-  constexpr int T = N / 16;
-  constexpr int REM = N / L;
-  constexpr int R = REM >= 16 ? 16 : REM;
-  constexpr int U = 16 / R;
-  constexpr int TW_STRIDE = N / (R * L);
-  if constexpr (L > 1) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int s = (t + T * u) & (L - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) tr.w[BASE + u * (R - 1) + (r - 1)] = tw[s * r * TW_STRIDE];
-    }
-  }
-  if constexpr (R != REM) {
-    constexpr int NEXT = BASE + (L > 1 ? U * (R - 1) : 0);
-    load_twiddles<N, L * R, NEXT>(tr, t, tw);
-  }
-}
-
-// One Stockham stage: radix R, L = product of the radices already applied; its twiddles start at
-// tr.w[BASE].
-template <int N, int R, int L, int DIR, bool LAST, int BASE, class V>
-__device__ __forceinline__ void stockham_stage(V (&v)[16], const LdsView<V>& lds, int t, const TwRegs<N>& tr) {
-  constexpr int T = N / 16;
-  constexpr int U = 16 / R;
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    V a[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = v[u + U * r];
-    const int b = t + T * u;
-    const int s = b & (L - 1);
-    if constexpr (L > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) a[r] = twmul<DIR>(a[r], tr.w[BASE + u * (R - 1) + (r - 1)]);
-    }
-    dft<R, DIR>(a);
-    if constexpr (LAST) {
-#pragma unroll
-      for (int k = 0; k < R; ++k) v[u + U * k] = a[k];
-    } else {
-      const int q = b / L;
-#pragma unroll
-      for (int k = 0; k < R; ++k) lds.at(q * R * L + s + L * k) = a[k];
-    }
-  }
-}
-
-// Full length-N transform of the 16 registers (positions t + T*m) in place.  All threads of the
-// workgroup call it (it contains workgroup barriers); on return every LDS read is complete.
-template <int N, int DIR, int L = 1, int BASE = 0, class V>
-__device__ __forceinline__ void fft_pass(V (&v)[16], const LdsView<V>& lds, int t, const TwRegs<N>& tr) {
-  constexpr int REM = N / L;
-  constexpr int R = REM >= 16 ? 16 : REM;
-  constexpr bool LAST = (R == REM);
-  constexpr int T = N / 16;
-  stockham_stage<N, R, L, DIR, LAST, BASE>(v, lds, t, tr);
-  if constexpr (!LAST) {
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = lds.at(t + T * m);
-    __syncthreads();
-    constexpr int NEXT = BASE + (L > 1 ? (16 / R) * (R - 1) : 0);
-    fft_pass<N, DIR, L * R, NEXT>(v, lds, t, tr);
-  }
-}
 
 // ---------------------------------------------------------------------------------------------
 // Step-kernel transforms: a forward transform with roots rounded once to fp32, and its exact

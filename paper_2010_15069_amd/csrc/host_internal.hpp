@@ -18,8 +18,9 @@ struct sgpe_ctx {
   float4* psi = nullptr;
   bool own_psi = false;
   float4* scratch = nullptr;
-  float4* tw_x = nullptr;   // compensated roots (energy kernels)
-  float4* tw_y = nullptr;
+  double2* twd_x = nullptr; // fp64 roots exp(-2 pi i j / nx), j < nx / 2 (energy kernels)
+  double2* twd_y = nullptr;
+  double4* scratch64 = nullptr;  // fp64 x-transformed state (energy), allocated on first use
   float4* twp_x = nullptr;  // fp32-rounded roots with modulus corrections (step kernels)
   float4* twp_y = nullptr;
   // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
@@ -42,6 +43,8 @@ struct sgpe_ctx {
   int col_points = 16;      // points per lane of the y transforms
   int n_cu = 1;             // compute units of the device
   bool full2x2 = false;
+  int split_order = 0;      // sgpe_split_order
+  int split_rs = 0;         // sgpe_real_space_split
   bool has_state = false;
   sgpe_status latched = SGPE_OK;
   std::vector<void*> allocations;
@@ -58,7 +61,8 @@ int default_points(int n, size_t npts);   // points per lane for a transform of 
 int col_groups(const sgpe_ctx* c);
 sgpe_status apply_schedule(sgpe_ctx* c, const sgpe_schedule& s);   // validated; EINVAL changes nothing
 sgpe_schedule get_schedule(const sgpe_ctx* c);
-sgpe::RowArgs row_args(const sgpe_ctx* c);
+// Row-pass arguments with the real-space coefficients of a sub-step h (h <= 0: h = dt).
+sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
 sgpe_status sync_and_latch(sgpe_ctx* c);

@@ -41,108 +41,121 @@ int col_default_cols(int nx, int ny, int points, size_t max_lds) {
   return c;
 }
 
-// Energy kernels: one lane holds both components of its 16 positions.
-int energy_rows_per_block(int nx, int ny, size_t max_lds) {
-  const int t = nx / 16;
-  int rows = 256 / t;
-  if (rows < 1) rows = 1;
-  if (rows > ny) rows = ny;
-  while (rows > 1 && size_t(rows) * size_t(nx + nx / 16) * 16 > max_lds) rows >>= 1;
-  return rows;
-}
+// Energy kernels (fp64, radix-2 in LDS): one row per row-kernel workgroup (2 nx double2 of LDS);
+// up to 4 columns per column-kernel workgroup (2 ny double2 each) as LDS allows.
+bool energy_fits(int nx, int ny, size_t max_lds) { return size_t(2) * nx * 16 <= max_lds && size_t(2) * ny * 16 <= max_lds; }
 
 int energy_cols_per_block(int nx, int ny, size_t max_lds) {
-  const int t = ny / 16;
-  int c = 256 / t;
-  if (c < 1) c = 1;
-  if (c > nx) c = nx;
-  while (c > 1 && size_t(c) * size_t(ny + ny / 16) * 16 > max_lds) c >>= 1;
+  int c = 4;
+  while (c > 1 && (size_t(2) * c * ny * 16 > max_lds || nx % c != 0)) c >>= 1;
   return c;
 }
 
 int norm_blocks() { return 256; }
 
 // -------------------------------------------------------------------------------------------
-// Energy: real-space terms and norm (row kernel, then x-FFT into scratch), k-space quadratic
-// form (column kernel, y-FFT, no write).  Products and sums in fp64.
+// Energy, in fp64 throughout (it is evaluated on demand, not per step).  Row kernel: the
+// real-space terms and the norm from the loaded values, then the x-DFT of both components into a
+// 32-byte-per-point fp64 scratch; column kernel: the y-DFT and the k-space quadratic form.  The
+// DFTs are in-place radix-2 transforms in LDS: input stored at bit-reversed positions, log2 N
+// butterfly stages, roots exp(-2 pi i j / N) from fp64 host tables.  Exact to fp64 rounding, so
+// the energy of a complex64 state carries no transform error of its own.
 // -------------------------------------------------------------------------------------------
-template <int N>
-__global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
-  extern __shared__ float4 lds_raw[];
-  __shared__ double red[64];
-  constexpr int T = N / 16;
-  constexpr int SLOTS = N + N / 16;
-  const int tid = threadIdx.x;
-  const int rloc = tid / T;
-  const int t = tid - rloc * T;
-  const int row = blockIdx.x * a.rows_per_block + rloc;
-  const LdsView<float4> lds{lds_raw + rloc * SLOTS, 0};
-  const float4* __restrict__ p = a.psi + size_t(row) * N;
-  float4 v[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = p[t + T * m];
-  TwRegs<N> tr;
-  load_twiddles<N>(tr, t, a.twx);
-  const double y = a.ymin + a.dy * row;
-  const double om_row = a.om_y ? a.om_y[row] : 0.0;
-  double er = 0.0, nr = 0.0;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int j = t + T * m;
-    const double x = a.xmin + a.dx * j;
-    const double V = a.wx2h * x * x + a.wy2h * y * y;
-    const double ur = v[m].x, ui = v[m].y, dr = v[m].z, di = v[m].w;
-    const double nu = ur * ur + ui * ui, nd = dr * dr + di * di;
-    const double om = a.om_x ? a.om_x[j] + om_row : 0.0;
-    er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (ur * dr + ui * di) +
-          0.5 * a.g_uu * nu * nu + 0.5 * a.g_dd * nd * nd + a.g_ud * nu * nd;
-    nr += nu + nd;
-  }
-  const double se = block_sum(er, red);
-  const double sn = block_sum(nr, red);
-  if (tid == 0) {
-    a.row_partials[2 * blockIdx.x] = se;
-    a.row_partials[2 * blockIdx.x + 1] = sn;
-  }
-  fft_pass<N, -1>(v, lds, t, tr);
-  float4* __restrict__ q = a.scratch + size_t(row) * N;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) q[t + T * m] = v[m];
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <int N>
-__global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
-  extern __shared__ float4 lds_raw[];
+// `count` independent length-N transforms stored one after another in `buf` (each already in
+// bit-reversed order); all threads of the workgroup take part.
+__device__ __forceinline__ void lds_fft64(double2* buf, int n, int log2n, int count, const double2* __restrict__ w) {
+  const int half_total = count * (n >> 1);
+  for (int s = 1; s <= log2n; ++s) {
+    const int half = 1 << (s - 1);
+    const int tw_step = n >> s;  // root index stride: exp(-2 pi i k / 2^s) = w[k n / 2^s]
+    __syncthreads();
+    for (int b = threadIdx.x; b < half_total; b += blockDim.x) {
+      const int tr = b / (n >> 1);
+      const int q = b - tr * (n >> 1);
+      const int k = q & (half - 1);
+      const int i0 = tr * n + ((q >> (s - 1)) << s) + k;
+      const double2 a0 = buf[i0];
+      const double2 a1 = zmul(buf[i0 + half], w[k * tw_step]);
+      buf[i0] = make_double2(a0.x + a1.x, a0.y + a1.y);
+      buf[i0 + half] = make_double2(a0.x - a1.x, a0.y - a1.y);
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int bitrev(int j, int log2n) { return static_cast<int>(__brev(static_cast<unsigned>(j)) >> (32 - log2n)); }
+
+__global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
+  extern __shared__ double2 elds[];
   __shared__ double red[64];
-  constexpr int T = N / 16;
+  const int n = a.nx, log2n = __builtin_ctz(a.nx);
+  const int row = blockIdx.x;
+  const float4* __restrict__ p = a.psi + size_t(row) * n;
+  const double y = a.ymin + a.dy * row;
+  const double om_row = a.om_y ? a.om_y[row] : 0.0;
+  double er = 0.0, ei = 0.0, nr = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const float4 v = p[j];
+    const double x = a.xmin + a.dx * j;
+    const double V = a.wx2h * x * x + a.wy2h * y * y;
+    const double ur = v.x, ui = v.y, dr = v.z, di = v.w;
+    const double nu = ur * ur + ui * ui, nd = dr * dr + di * di;
+    const double om = a.om_x ? a.om_x[j] + om_row : 0.0;
+    er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (ur * dr + ui * di);
+    ei += 0.5 * a.g_uu * nu * nu + 0.5 * a.g_dd * nd * nd + a.g_ud * nu * nd;
+    nr += nu + nd;
+    const int r = bitrev(j, log2n);
+    elds[r] = make_double2(ur, ui);
+    elds[n + r] = make_double2(dr, di);
+  }
+  const double se = block_sum(er, red);
+  const double si = block_sum(ei, red);
+  const double sn = block_sum(nr, red);
+  if (threadIdx.x == 0) {
+    a.row_partials[kEnergyRowParts * blockIdx.x] = se;
+    a.row_partials[kEnergyRowParts * blockIdx.x + 1] = si;
+    a.row_partials[kEnergyRowParts * blockIdx.x + 2] = sn;
+  }
+  lds_fft64(elds, n, log2n, 2, a.twx);
+  double4* __restrict__ q = a.scratch + size_t(row) * n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double2 u = elds[j], d = elds[n + j];
+    q[j] = make_double4(u.x, u.y, d.x, d.y);
+  }
+}
+
+__global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
+  extern __shared__ double2 elds[];
+  __shared__ double red[64];
+  const int n = a.ny, log2n = __builtin_ctz(a.ny);
   const int C = a.cols;
-  const int tid = threadIdx.x;
-  const int c = tid & (C - 1);
-  const int t = tid / C;
-  const int x = blockIdx.x * C + c;
-  const LdsView<float4> lds{lds_raw + c, __builtin_ctz(C)};
-  const float4* __restrict__ p = a.scratch + x;
-  const size_t rs = size_t(a.nx);
-  float4 v[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = p[size_t(t + T * m) * rs];
-  TwRegs<N> tr;
-  load_twiddles<N>(tr, t, a.twy);
-  fft_pass<N, -1>(v, lds, t, tr);
-  const double kx = (x < a.nx / 2 ? x : x - a.nx) * a.dkx;
-  const double bz = a.k_l * kx;
+  const int x0 = blockIdx.x * C;
+  // columns x0 .. x0 + C - 1: transform 2c (up) and 2c + 1 (down) of column c
+  for (int i = threadIdx.x; i < C * n; i += blockDim.x) {
+    const int c = i % C, iy = i / C;
+    const double4 v = a.scratch[size_t(iy) * a.nx + x0 + c];
+    const int r = bitrev(iy, log2n);
+    elds[(2 * c) * n + r] = make_double2(v.x, v.y);
+    elds[(2 * c + 1) * n + r] = make_double2(v.z, v.w);
+  }
+  lds_fft64(elds, n, log2n, 2 * C, a.twy);
   double acc = 0.0;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int iy = t + T * m;
-    const double ky = (iy < N / 2 ? iy : iy - N) * a.dky;
+  for (int i = threadIdx.x; i < C * n; i += blockDim.x) {
+    const int c = i / n, iy = i - c * n;
+    const int x = x0 + c;
+    const double kx = (x < a.nx / 2 ? x : x - a.nx) * a.dkx;
+    const double ky = (iy < n / 2 ? iy : iy - n) * a.dky;
     const double ak = 0.5 * (kx * kx + ky * ky);
-    const double ur = v[m].x, ui = v[m].y, dr = v[m].z, di = v[m].w;
-    const double pu = ur * ur + ui * ui, pd = dr * dr + di * di;
-    acc += ak * (pu + pd) + bz * (pu - pd) + a.omega * (ur * dr + ui * di);
+    const double2 u = elds[(2 * c) * n + iy], d = elds[(2 * c + 1) * n + iy];
+    const double pu = u.x * u.x + u.y * u.y, pd = d.x * d.x + d.y * d.y;
+    acc += ak * (pu + pd) + a.k_l * kx * (pu - pd) + a.omega * (u.x * d.x + u.y * d.y);
   }
   const double s = block_sum(acc, red);
-  if (tid == 0) a.col_partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) a.col_partials[blockIdx.x] = s;
 }
 
 // -------------------------------------------------------------------------------------------
@@ -161,47 +174,14 @@ __global__ void __launch_bounds__(256) norm_kernel(const float4* __restrict__ ps
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-template <int N>
-static hipError_t energy_row_launch(const EnergyArgs& a, hipStream_t s) {
-  const dim3 block(a.rows_per_block * (N / 16));
-  const dim3 grid(a.ny / a.rows_per_block);
-  hipLaunchKernelGGL((energy_row_kernel<N>), grid, block, size_t(a.rows_per_block) * (N + N / 16) * 16, s, a);
-  return hipGetLastError();
-}
-
-template <int N>
-static hipError_t energy_col_launch(const EnergyArgs& a, hipStream_t s) {
-  const dim3 block(a.cols * (N / 16));
-  const dim3 grid(a.nx / a.cols);
-  hipLaunchKernelGGL((energy_col_kernel<N>), grid, block, size_t(a.cols) * (N + N / 16) * 16, s, a);
-  return hipGetLastError();
-}
-
-#define SGPE_SIZE_SWITCH(n, fn, ...)                      \
-  switch (n) {                                            \
-    case 16: return fn<16>(__VA_ARGS__);                  \
-    case 32: return fn<32>(__VA_ARGS__);                  \
-    case 64: return fn<64>(__VA_ARGS__);                  \
-    case 128: return fn<128>(__VA_ARGS__);                \
-    case 256: return fn<256>(__VA_ARGS__);                \
-    case 512: return fn<512>(__VA_ARGS__);                \
-    case 1024: return fn<1024>(__VA_ARGS__);              \
-    case 2048: return fn<2048>(__VA_ARGS__);              \
-    case 4096: return fn<4096>(__VA_ARGS__);              \
-    default: return hipErrorInvalidValue;                 \
-  }
-
-static hipError_t energy_row_dispatch(const EnergyArgs& a, hipStream_t s) {
-  SGPE_SIZE_SWITCH(a.nx, energy_row_launch, a, s)
-}
-static hipError_t energy_col_dispatch(const EnergyArgs& a, hipStream_t s) {
-  SGPE_SIZE_SWITCH(a.ny, energy_col_launch, a, s)
-}
-
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
-  hipError_t e = energy_row_dispatch(a, s);
+  const size_t row_lds = size_t(2) * a.nx * sizeof(double2);
+  const size_t col_lds = size_t(2) * a.cols * a.ny * sizeof(double2);
+  hipLaunchKernelGGL(energy_row_kernel, dim3(a.ny), dim3(256), row_lds, s, a);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return energy_col_dispatch(a, s);
+  hipLaunchKernelGGL(energy_col_kernel, dim3(a.nx / a.cols), dim3(256), col_lds, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {

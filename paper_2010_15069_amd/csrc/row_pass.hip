@@ -203,6 +203,54 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
   }
 }
 
+// R(h) split to second order as N(h/2) L(h) N(h/2): the mean-field phase with the densities of
+// its input, the exponential of the linear real-space terms (trap, detuning, spatial coupling),
+// the mean-field phase again with the updated densities.  Coefficients as in row_apply_r.
+template <int N, bool IMAG, bool FULL, int P>
+__device__ __forceinline__ void row_apply_r_nln(float2 (&v)[P], const RowArgs& a, int row, int t, bool up,
+                                                const float (&hbx_r)[P], float hb_row) {
+  constexpr int T = N / P;
+  RCoef c;
+  c.sgn = up ? 1.0f : -1.0f;
+  c.hd_own = up ? a.hdelta2 : -a.hdelta2;
+  c.hg_own = up ? a.hg_uu : a.hg_dd;
+  c.hg_ud = a.hg_ud;
+  c.hg_uu = a.hg_uu;
+  c.hg_dd = a.hg_dd;
+  c.hdelta2 = a.hdelta2;
+  const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
+  const float hvy = a.hvy * y * y;
+  auto half_n = [&](float2 w) {
+    const float n_own = fmaf(w.x, w.x, w.y * w.y);
+    const float n_oth = pair_swap(n_own);
+    const float ph = 0.5f * fmaf(c.hg_own, n_own, c.hg_ud * n_oth);
+    if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) return apply_r_diag<IMAG, true>(w, ph);
+    return apply_r_diag<IMAG, false>(w, ph);
+  };
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int j = t + T * m;
+    const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
+    const float hv = fmaf(a.hvx * x, x, hvy);
+    float2 w = half_n(v[m]);
+    if constexpr (!FULL) {
+      const float ph = hv + c.hd_own;
+      if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) w = apply_r_diag<IMAG, true>(w, ph);
+      else w = apply_r_diag<IMAG, false>(w, ph);
+    } else {
+      const float hbx = hbx_r[m] + hb_row;
+      const float2 o = pair_swap(w);
+      RFull f;
+      f.ha = hv;
+      f.hbz = c.hdelta2;
+      f.th = sqrtf(fmaf(hbx, hbx, f.hbz * f.hbz));
+      if (wave_all(r_full_small<IMAG>(f))) w = apply_r_full<IMAG, true>(w, o, f, hbx, c.sgn);
+      else w = apply_r_full<IMAG, false>(w, o, f, hbx, c.sgn);
+    }
+    v[m] = half_n(w);
+  }
+}
+
 // A workgroup handles ITERS groups of rows_per_block rows, one after the other; the next group's
 // data is loaded into registers before the current group is transformed, so its memory latency
 // hides behind this group's arithmetic.  P points per lane: T = N / P lanes per transform.
@@ -282,6 +330,68 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
   }
 }
 
+// The general row pass of the splitting variants (one row group per workgroup); see RowVarFlags.
+template <int N, bool IMAG, bool FULL, int P>
+__device__ __forceinline__ void row_var_body(const RowArgs& a, int wg) {
+  extern __shared__ float2 lds_raw[];
+  __shared__ double red[64];
+  constexpr int T = N / P;
+  constexpr int SLOTS = N + N / 16;
+  const int tid = threadIdx.x;
+  const int comp = tid & 1;
+  const int pair = tid >> 1;
+  const int rloc = pair / T;
+  const int t = pair - rloc * T;
+  const int row = wg * a.rows_per_block + rloc;
+  const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
+  const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
+  char* __restrict__ out = reinterpret_cast<char*>(a.psi);
+  const uint32_t off = static_cast<uint32_t>(row) * (16u * N) + static_cast<uint32_t>(t) * 16u + 8u * comp;
+  const int flags = a.var_flags;
+
+  double pv[4];
+  prefetch_partials(a, pv);
+  float2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + (off + 16u * T * m));
+  TwPlain<N, P> tr;
+  load_twiddles<N>(tr, t, a.tw);
+  float hbx_r[P], hb_row = 0.0f;
+  if constexpr (FULL) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) hbx_r[m] = a.hbx[t + T * m] * a.hfrac;
+    hb_row = a.hby[row] * a.hfrac;
+  }
+  if (flags & (VAR_INV | VAR_SCALE)) {
+    if (flags & VAR_INV) inv_pass<N>(v, lds, t, tr);
+    const float s = row_scale(a, pv);
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
+  }
+  for (int r = 0; r < a.var_r; ++r) {
+    if (a.var_nln) row_apply_r_nln<N, IMAG, FULL>(v, a, row, t, comp == 0, hbx_r, hb_row);
+    else row_apply_r<N, IMAG, FULL>(v, a, row, t, comp == 0, hbx_r, hb_row);
+  }
+  if (flags & VAR_NORM_OUT) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < P; ++m) acc += double(v[m].x) * double(v[m].x) + double(v[m].y) * double(v[m].y);
+    acc = block_sum(acc, red);
+    if (tid == 0) a.partials_out[wg] = acc;
+  }
+  if (flags & VAR_FWD) fwd_pass<N>(v, lds, t, tr);
+#pragma unroll
+  for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + (off + 16u * T * m)) = v[m];
+}
+
+// Row groups are sized for 256 threads (row_rows_per_block); only a 4096-point row at 16 points
+// per lane needs 512.  The tighter bound gives the variants' two real-space routines the
+// registers they need without spilling.
+template <int N, bool IMAG, bool FULL, int P>
+__global__ void __launch_bounds__(2 * N / P > 256 ? 512 : 256) row_var_kernel(RowArgs a) {
+  row_var_body<N, IMAG, FULL, P>(a, blockIdx.x);
+}
+
 // One instance: workgroup blockIdx.x of the pass.  A batch of instances of one grid shape:
 // instance blockIdx.y, its arguments from a device table.
 template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
@@ -302,7 +412,16 @@ static hipError_t row_launch_t(const RowArgs& a, const RowArgs* tab, int count, 
   const dim3 block(2 * a.rows_per_block * (N / points));
   const dim3 grid(a.ny / (a.rows_per_block * iters), tab ? count : 1);
   const size_t lds = row_lds_bytes(N, a.rows_per_block);
-  if (tab) {
+  if constexpr (MODE == ROW_VAR) {
+    if (tab || iters != 1) return hipErrorInvalidValue;
+    if (block.x > static_cast<unsigned>(2 * N / points > 256 ? 512 : 256)) return hipErrorInvalidValue;
+    if (points == 16) hipLaunchKernelGGL((row_var_kernel<N, IMAG, FULL, 16>), grid, block, lds, s, a);
+    else if constexpr (N <= kMaxNSmallP) {
+      if (points == 8) hipLaunchKernelGGL((row_var_kernel<N, IMAG, FULL, 8>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((row_var_kernel<N, IMAG, FULL, 4>), grid, block, lds, s, a);
+    }
+    return hipGetLastError();
+  } else if (tab) {
     if (points == 16) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 16>), grid, block, lds, s, tab);
     else if constexpr (N <= kMaxNSmallP) {
       if (points == 8) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 8>), grid, block, lds, s, tab);
@@ -330,6 +449,11 @@ static hipError_t row_launch_n(const RowArgs& a, const RowArgs* tab, int count, 
                             : row_launch_t<N, ROW_STEP, true, false>(a, tab, count, iters, points, s);
       return full ? row_launch_t<N, ROW_STEP, false, true>(a, tab, count, iters, points, s)
                   : row_launch_t<N, ROW_STEP, false, false>(a, tab, count, iters, points, s);
+    case ROW_VAR:
+      if (imag) return full ? row_launch_t<N, ROW_VAR, true, true>(a, tab, count, iters, points, s)
+                            : row_launch_t<N, ROW_VAR, true, false>(a, tab, count, iters, points, s);
+      return full ? row_launch_t<N, ROW_VAR, false, true>(a, tab, count, iters, points, s)
+                  : row_launch_t<N, ROW_VAR, false, false>(a, tab, count, iters, points, s);
     default: return hipErrorInvalidValue;
   }
 }

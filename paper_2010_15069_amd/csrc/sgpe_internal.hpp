@@ -11,6 +11,17 @@ enum RowMode : int {
   ROW_FWD = 0,   // forward x-FFT only (enter the mixed (k_x, y) representation)
   ROW_INV = 1,   // inverse x-FFT and scale (leave it: real space)
   ROW_STEP = 2,  // inverse x-FFT, scale, real-space exponential R(h), forward x-FFT
+  ROW_VAR = 3,   // the general row pass of the splitting variants, steered by RowArgs::var_*
+};
+
+// Stages of the general row pass (ROW_VAR), run in this order when their flag is set: inverse
+// x-FFT and scale, or only the scale; var_r real-space sub-steps R(h) in turn (each in closed form
+// with frozen densities, or as N(h/2) L(h) N(h/2) when var_nln); the norm partial; forward x-FFT.
+enum RowVarFlags : int {
+  VAR_INV = 1,       // inverse x-FFT, then the scale (`scale`, or from the partials)
+  VAR_SCALE = 2,     // scale only, from the partials (the state is in real space on entry)
+  VAR_NORM_OUT = 4,  // one fp64 partial of sum |psi|^2 per workgroup into partials_out
+  VAR_FWD = 8,       // forward x-FFT
 };
 
 // Column (y) pass norm accumulation.
@@ -39,6 +50,12 @@ struct RowArgs {
   const float* hbx;          // h * Omega_x(x_j) / 2, length nx (full 2x2 variant only)
   const float* hby;          // h * Omega_y(y_i) / 2, length ny (full 2x2 variant only);
                              //   the spatial coupling is Omega_x(x) + Omega_y(y)
+  // general row pass (ROW_VAR) only:
+  int var_flags;             // RowVarFlags
+  int var_r;                 // real-space sub-steps R(h) applied in turn (0, 1 or 2)
+  int var_nln;               // 1: each R(h) as N(h/2) L(h) N(h/2)
+  float hfrac;               // h / dt: scales the hbx / hby tables (built for h = dt)
+  double* partials_out;      // VAR_NORM_OUT: one double per workgroup
 };
 
 struct ColArgs {
@@ -51,13 +68,15 @@ struct ColArgs {
   double* partials;          // one double per workgroup (norm modes)
 };
 
+constexpr int kEnergyRowParts = 3;
+
 struct EnergyArgs {
   const float4* psi;
-  float4* scratch;
+  double4* scratch;          // [ny][nx] x-transformed state in fp64 {re_up, im_up, re_dn, im_dn}
   int nx, ny;
-  int rows_per_block, cols;
-  const float4* twx;         // compensated roots {re_hi, im_hi, re_lo, im_lo}, length nx
-  const float4* twy;         // the same, length ny
+  int cols;                  // columns per column-kernel workgroup
+  const double2* twx;        // roots exp(-2 pi i j / nx), j < nx / 2, fp64
+  const double2* twy;        // the same for ny
   double xmin, dx, ymin, dy;
   double wx2h, wy2h;         // wx^2/2, wy^2/2
   double delta, g_uu, g_dd, g_ud;
@@ -65,7 +84,8 @@ struct EnergyArgs {
   const double* om_x;        // spatial Raman coupling Omega_x(x_j) (length nx) and Omega_y(y_i)
   const double* om_y;        //   (length ny); both NULL without one
   double dkx, dky;
-  double* row_partials;      // 2 per row block: {real-space energy, norm}
+  double* row_partials;      // kEnergyRowParts per row: {linear real-space energy,
+                             //   interaction energy, norm}
   double* col_partials;      // 1 per column block: k-space quadratic form
 };
 
@@ -116,7 +136,7 @@ hipError_t launch_winding(const float4* psi, int nx, int ny, double xmax, double
 int row_rows_per_block(int nx, int ny, int points, size_t max_lds);
 int col_default_cols(int nx, int ny, int points, size_t max_lds);
 bool col_cols_supported(int nx, int ny, int cols, int iters, int points, size_t max_lds);
-int energy_rows_per_block(int nx, int ny, size_t max_lds);
+bool energy_fits(int nx, int ny, size_t max_lds);
 int energy_cols_per_block(int nx, int ny, size_t max_lds);
 size_t row_lds_bytes(int nx, int rows);
 size_t col_lds_bytes(int ny, int cols);

@@ -83,6 +83,15 @@ class Solver:
         check(self._lib.sgpe_norm(self._ctx, ctypes.byref(v)), "sgpe_norm")
         return v.value
 
+    def set_splitting(self, order="krk", real_space="frozen"):
+        """Splitting variant: order "krk" (K(dt/2) R(dt) K(dt/2)) or "rkr" (R(dt/2) K(dt) R(dt/2));
+        real_space "frozen" (one closed-form exponential) or "nln" (N(h/2) L(h) N(h/2))."""
+        orders, splits = {"krk": 0, "rkr": 1}, {"frozen": 0, "nln": 1}
+        if order not in orders or real_space not in splits:
+            raise ValueError(f"unknown splitting {order!r}, {real_space!r}")
+        check(self._lib.sgpe_set_splitting(self._ctx, orders[order], splits[real_space]), "sgpe_set_splitting")
+        return self
+
     # -- spatial coupling, annealing and observables (Sec. 6) -------------------------------
     def set_raman_profile(self, omega_x=None, omega_y=None):
         """Spatial Raman coupling Omega_x(x_j) + Omega_y(y_i) (arrays of nx / ny values, or None

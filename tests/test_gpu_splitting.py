@@ -1,0 +1,165 @@
+"""GPU parity of the splitting variants (Sec. 3.2) against the FP64 oracle, through the C ABI:
+R(dt/2) K(dt) R(dt/2) and the N(h/2) L(h) N(h/2) real-space split, in real and imaginary time,
+with and without the spatial Raman coupling (diagonal and full 2x2 real-space exponentials),
+on square, ragged and full-size grids; call splitting; switching variants; error paths.
+
+Bars: as for the default scheme, psi relative L2 <= 1e-5 (1e-6 after a few full-size steps) and
+energies within 1e-6; except mid-relaxation imaginary-time trajectories of R-K-R, 2e-5 and 5e-6.
+R-K-R stores the state three times per imaginary step instead of twice, and imaginary time carries
+the extra fp32 roundings along its slowest modes (measured on the full-2x2 case after 300 steps:
+2.4e-6 default, 5.1e-6 R-K-R, 4.0e-6 N L N, 1.04e-5 both -- the factors multiply, as rounding
+does; a wrong sub-step would show at the 1e-3 level).  The converged ground-state energies of
+every variant are held to the 1e-6 bar."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import OracleGPE
+from workloads import Params, initial_state, preset
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+VARIANTS = [("krk", "nln"), ("rkr", "frozen"), ("rkr", "nln")]
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    from paper_2010_15069_amd import Solver, device_count
+    if device_count() <= 0:
+        pytest.skip("no HIP device")
+    return Solver
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_pair(Solver, p, psi0, order, rs, ops):
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_splitting(order, rs)
+    o.set_psi(psi0)
+    s = Solver(p)
+    s.set_splitting(order, rs)
+    s.set_psi(psi0)
+    for kind, n in ops:
+        getattr(o, f"step_{kind}")(n)
+        getattr(s, f"step_{kind}")(n)
+    return o, s
+
+
+def _relax(obj, step, tol, every=50, max_steps=40000):
+    e_prev, n = None, 0
+    while n < max_steps:
+        step(every)
+        n += every
+        e = obj.energy()
+        if e_prev is not None and abs(e - e_prev) < tol * abs(e):
+            return e
+        e_prev = e
+    return e_prev
+
+
+def check(o, s, tol, e_tol=1e-6):
+    err = rel_l2(s.get_psi(), o.psi)
+    print(f"psi rel L2 {err:.3e}, energy rel {abs(s.energy() - o.energy()) / abs(o.energy()):.2e}")
+    assert err <= tol, f"psi rel L2 {err:.3e} > {tol:.1e}"
+    eo, eg = o.energy(), s.energy()
+    assert abs(eg - eo) <= e_tol * abs(eo), (eg, eo)
+    no, ng = o.norm(), s.norm()
+    assert abs(ng - no) <= 1e-6 * no, (ng, no)
+
+
+def _unequal_full(n=128):
+    # unequal couplings with a spatial Raman term: where N L N differs from frozen densities
+    return preset("ground_2048", nx=n, ny=n, g_uu=50.0, g_dd=30.0, g_ud=40.0, delta=0.3)
+
+
+@pytest.mark.parametrize("order,rs", VARIANTS + [("krk", "frozen")])
+@pytest.mark.parametrize("kind", ["imag", "real"])
+def test_variants_full_2x2(Solver, order, rs, kind):
+    p = _unequal_full()
+    if kind == "real":
+        p = p.replace(dt=5e-4)
+    o, s = run_pair(Solver, p, initial_state(p, "tf", seed=3), order, rs, [(kind, 300)])
+    rkr_imag = order == "rkr" and kind == "imag"
+    check(o, s, 2e-5 if rkr_imag else 1e-5, 5e-6 if rkr_imag else 1e-6)
+
+
+@pytest.mark.parametrize("order,rs", VARIANTS)
+def test_variants_converged_ground_state_energy(Solver, order, rs):
+    # run to |dE|/E < 1e-11 (oracle) and < 1e-9 (GPU), checks every 50 steps
+    p = _unequal_full(64)
+    psi0 = initial_state(p, "tf", seed=0)
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_splitting(order, rs)
+    o.set_psi(psi0)
+    eo = _relax(o, o.step_imag, 1e-11)
+    s = Solver(p).set_splitting(order, rs).set_psi(psi0)
+    eg = _relax(s, s.step_imag, 1e-9)
+    print(f"ground-state energy: GPU {eg!r}, oracle {eo!r}, rel {abs(eg - eo) / abs(eo):.2e}")
+    assert abs(eg - eo) <= 1e-6 * abs(eo)
+
+
+@pytest.mark.parametrize("order,rs", VARIANTS)
+def test_variants_diagonal_imag_then_real(Solver, order, rs):
+    p = preset("realtime_512", nx=128, ny=128, g_uu=12.0, g_dd=8.0)
+    o, s = run_pair(Solver, p, initial_state(p, "tf", seed=1), order, rs, [("imag", 200), ("real", 300)])
+    check(o, s, 1e-5)
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 256), (256, 32)])
+def test_variants_ragged(Solver, nx, ny):
+    p = Params(nx=nx, ny=ny, xmax=8.0, ymax=6.0, g_uu=3.0, g_dd=4.0, g_ud=2.0, k_l=1.3, omega=0.7, delta=0.2,
+               omega_r0=0.8, omega_rw=2.0, dt=1e-3)
+    for order, rs in VARIANTS:
+        o, s = run_pair(Solver, p, initial_state(p, "tf", seed=4), order, rs, [("imag", 100), ("real", 100)])
+        check(o, s, 1e-5)
+
+
+@pytest.mark.parametrize("order,rs", [("rkr", "frozen"), ("krk", "nln")])
+def test_variants_full_size_1024(Solver, order, rs):
+    p = preset("metric_1024")
+    o, s = run_pair(Solver, p, initial_state(p, "tf", seed=0), order, rs, [("real", 5), ("imag", 5)])
+    check(o, s, 1e-6)
+
+
+def test_rkr_call_splitting_and_switching(Solver):
+    p = _unequal_full(64)
+    psi0 = initial_state(p, "tf", seed=6)
+    a = Solver(p).set_splitting("rkr", "nln").set_psi(psi0)
+    b = Solver(p).set_splitting("rkr", "nln").set_psi(psi0)
+    a.step_imag(7)
+    b.step_imag(3)
+    b.step_imag(4)
+    assert rel_l2(b.get_psi(), a.get_psi()) <= 1e-6
+    # back to the default scheme and on: matches the oracle doing the same
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_splitting("rkr", "nln")
+    o.set_psi(psi0)
+    o.step_imag(7)
+    o.set_splitting("krk", "frozen")
+    o.step_real(50)
+    a.set_splitting("krk", "frozen")
+    a.step_real(50)
+    check(o, a, 1e-5)
+
+
+def test_variant_error_paths(Solver):
+    from paper_2010_15069_amd import SgpeError
+    from paper_2010_15069_amd._lib import lib
+    p = preset("tiny")
+    s = Solver(p).set_psi(initial_state(p, "gauss", seed=0))
+    for order, rs in ((2, 0), (0, 2), (-1, 0)):
+        st = lib().sgpe_set_splitting(s._ctx, order, rs)
+        assert st == 1, (order, rs, st)       # SGPE_EINVAL
+    s.set_splitting("rkr", "frozen")
+    with pytest.raises(SgpeError, match="SGPE_ESTATE"):
+        s.profile_steps(10)
+    with pytest.raises(SgpeError, match="SGPE_ESTATE"):
+        s.profile_kernels(10)
+    s.step_real(0)                            # zero steps: no launch, fine
+    s.set_splitting()
+    r, c = s.profile_steps(10)
+    assert r > 0 and c > 0
