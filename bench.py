@@ -218,6 +218,8 @@ def ground_2048_convergence(torch, stream, every=10, tol=1e-9, max_steps=150000)
         steps += every
         e = s.energy()
         trace.append((steps, time.perf_counter() - t0, e))
+        if steps % 50000 == 0:
+            print(f"ground_2048: {steps} steps, E = {e!r} ({trace[-1][1]:.1f} s)", file=sys.stderr, flush=True)
         if abs(e - e_prev) < tol * abs(e):
             converged = True
             break

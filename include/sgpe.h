@@ -85,6 +85,22 @@ int32_t sgpe_device_count(void);
  * runtime error), SGPE_ENOMEM. */
 sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, sgpe_ctx** out);
 
+/* Precision of a context's state and step arithmetic. */
+typedef enum {
+  SGPE_C64 = 0,   /* complex64 state, fp32 step kernels (the default) */
+  SGPE_C128 = 1   /* complex128 state, fp64 step kernels: the same kernels instantiated in double */
+} sgpe_precision;
+
+/* sgpe_create with a precision.  SGPE_C128: the state is [ny][nx] of {re_up, im_up, re_dn, im_dn}
+ * as fp64 (32*nx*ny bytes; a borrowed psi_dev must hold that many, 16-byte aligned), set_psi and
+ * get_psi copy without rounding, and the step kernels, tables and the imaginary-time norm run in
+ * fp64 (Sec. 4 uses complex128 throughout).  Its launch schedule is fixed (16 points per lane, no
+ * prefetch): sgpe_set_schedule and sgpe_set_col_tile return SGPE_EINVAL, sgpe_set_splitting accepts
+ * only the default, sgpe_profile_steps / sgpe_profile_kernels return SGPE_ESTATE.  Batches are
+ * complex64 only.  Errors: as sgpe_create, and SGPE_EINVAL for an unknown precision. */
+sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_stream, void* psi_dev,
+                           sgpe_ctx** out);
+
 /* Release the context and everything it allocated (not a borrowed state).  NULL is a no-op. */
 void sgpe_destroy(sgpe_ctx* ctx);
 

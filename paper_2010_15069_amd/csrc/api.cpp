@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -29,6 +30,11 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 
 namespace sgpe_host {
+
+inline float4 mk4(double a, double b, double c, double d, float) { return make_float4(float(a), float(b), float(c), float(d)); }
+inline double4 mk4(double a, double b, double c, double d, double) { return make_double4(a, b, c, d); }
+inline float2 mk2h(double a, double b, float) { return make_float2(float(a), float(b)); }
+inline double2 mk2h(double a, double b, double) { return make_double2(a, b); }
 
 sgpe_status dev_alloc(sgpe_ctx* c, void** ptr, size_t bytes) {
   *ptr = nullptr;
@@ -61,6 +67,12 @@ sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y) {
   const sgpe_params& p = c->p;
   sgpe_status st;
   void* ptr = nullptr;
+  if (c->prec == SGPE_C128 && !c->hbx64) {
+    if ((st = dev_alloc(c, &ptr, size_t(p.nx) * sizeof(double))) != SGPE_OK) return st;
+    c->hbx64 = static_cast<double*>(ptr);
+    if ((st = dev_alloc(c, &ptr, size_t(p.ny) * sizeof(double))) != SGPE_OK) return st;
+    c->hby64 = static_cast<double*>(ptr);
+  }
   if (!c->hbx) {
     if ((st = dev_alloc(c, &ptr, size_t(p.nx) * sizeof(float))) != SGPE_OK) return st;
     c->hbx = static_cast<float*>(ptr);
@@ -75,8 +87,16 @@ sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y) {
   if (om_x) ox.assign(om_x, om_x + p.nx);
   if (om_y) oy.assign(om_y, om_y + p.ny);
   std::vector<float> hx(p.nx), hy(p.ny);
-  for (int j = 0; j < p.nx; ++j) hx[j] = float(0.5 * p.dt * ox[j]);
-  for (int i = 0; i < p.ny; ++i) hy[i] = float(0.5 * p.dt * oy[i]);
+  std::vector<double> hx64(p.nx), hy64(p.ny);
+  for (int j = 0; j < p.nx; ++j) hx64[j] = 0.5 * p.dt * ox[j], hx[j] = float(hx64[j]);
+  for (int i = 0; i < p.ny; ++i) hy64[i] = 0.5 * p.dt * oy[i], hy[i] = float(hy64[i]);
+  if (c->prec == SGPE_C128 &&
+      (hipStreamSynchronize(c->stream) != hipSuccess ||
+       hipMemcpy(c->hbx64, hx64.data(), hx64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(c->hby64, hy64.data(), hy64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
   // the stream's queued steps may still read the old tables
   if (hipStreamSynchronize(c->stream) != hipSuccess ||
       hipMemcpy(c->hbx, hx.data(), hx.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
@@ -103,13 +123,16 @@ std::vector<double2> twiddles64(int n) {
 // 1 + eta = 1 / (cos^2 + sin^2) of the rounded pair (evaluated in fp64): the step kernels'
 // forward transform multiplies by the rounded root, their exact inverse by conj(root)(1 + eta),
 // whose low part conj(root) eta they form from cos, sin and eta.
-std::vector<float4> twiddles_plain(int n) {
-  std::vector<float4> t(n);
+// fp64 (complex128 kernels): the roots rounded to fp64 with eta = 0 -- their modulus error, ~1e-16,
+// needs no correction at that precision.
+template <class T = float>
+std::vector<sgpe::point_t<T>> twiddles_plain(int n) {
+  std::vector<sgpe::point_t<T>> t(n);
   for (int j = 0; j < n; ++j) {
     const double a = 2.0 * M_PI * double(j) / double(n);
-    const float c = float(std::cos(a)), s = float(std::sin(a));
-    const double eta = 1.0 / (double(c) * double(c) + double(s) * double(s)) - 1.0;
-    t[j] = make_float4(c, s, float(eta), 0.0f);
+    const T c = T(std::cos(a)), s = T(std::sin(a));
+    const double eta = std::is_same<T, float>::value ? 1.0 / (double(c) * double(c) + double(s) * double(s)) - 1.0 : 0.0;
+    t[j] = mk4(c, s, eta, 0.0, T());
   }
   return t;
 }
@@ -124,11 +147,12 @@ double kval(int j, int n, double d) {
 //   M'(k_x) = e^{-h kx^2/2 (i)} [ c 1 - s (b . sigma) ],  b = (omega/2, k_l k_x),
 //   P(k_y)  = e^{-h ky^2/2 (i)};
 // stored as M' - 1 (four complex entries) and P - 1, to fp32 relative accuracy.
-void k_tables(const sgpe_params& p, bool imag, double h, std::vector<float4>& kx_out,
-              std::vector<float2>& ky_out) {
+template <class T = float>
+void k_tables(const sgpe_params& p, bool imag, double h, std::vector<sgpe::point_t<T>>& kx_out,
+              std::vector<sgpe::cplx_t<T>>& ky_out) {
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
-  kx_out.assign(2 * size_t(p.nx), make_float4(0, 0, 0, 0));
-  ky_out.assign(size_t(p.ny), make_float2(0, 0));
+  kx_out.assign(2 * size_t(p.nx), mk4(0, 0, 0, 0, T()));
+  ky_out.assign(size_t(p.ny), mk2h(0, 0, T()));
   for (int j = 0; j < p.nx; ++j) {
     const double kx = kval(j, p.nx, dx);
     const double bx = 0.5 * p.omega, bz = p.k_l * kx;
@@ -152,17 +176,17 @@ void k_tables(const sgpe_params& p, bool imag, double h, std::vector<float4>& kx
       m22r = pr * (ch + sh * bz);  m22i = 0.0;
     }
     // per component: {d_own, d_other} of its row of M' - 1 (up: d11, d12; down: d22, d21)
-    kx_out[2 * size_t(j)] = make_float4(float(m11r - 1.0), float(m11i), float(m12r), float(m12i));
-    kx_out[2 * size_t(j) + 1] = make_float4(float(m22r - 1.0), float(m22i), float(m12r), float(m12i));
+    kx_out[2 * size_t(j)] = mk4(m11r - 1.0, m11i, m12r, m12i, T());
+    kx_out[2 * size_t(j) + 1] = mk4(m22r - 1.0, m22i, m12r, m12i, T());
   }
   for (int i = 0; i < p.ny; ++i) {
     const double ky = kval(i, p.ny, dy);
     const double be = 0.5 * h * ky * ky;
     if (!imag) {
       const double sh = std::sin(0.5 * be);
-      ky_out[i] = make_float2(float(-2.0 * sh * sh), float(-std::sin(be)));
+      ky_out[i] = mk2h(-2.0 * sh * sh, -std::sin(be), T());
     } else {
-      ky_out[i] = make_float2(float(std::expm1(-be)), 0.0f);
+      ky_out[i] = mk2h(std::expm1(-be), 0.0, T());
     }
   }
 }
@@ -231,15 +255,25 @@ sgpe_status status_of(hipError_t e) {
   return SGPE_EDEVICE;
 }
 
-RowArgs row_args(const sgpe_ctx* c, double h_sub) {
+template <class T>
+sgpe::RowArgsT<T> row_args_t(const sgpe_ctx* c, double h_sub) {
   const sgpe_params& p = c->p;
-  RowArgs a{};
-  a.psi = c->psi;
+  sgpe::RowArgsT<T> a{};
+  if constexpr (std::is_same<T, double>::value) {
+    a.psi = c->psi64;
+    a.tw = c->twp64_x;
+    a.hbx = c->hbx64;
+    a.hby = c->hby64;
+  } else {
+    a.psi = c->psi;
+    a.tw = c->twp_x;
+    a.hbx = c->hbx;
+    a.hby = c->hby;
+  }
   a.nx = p.nx;
   a.ny = p.ny;
   a.rows_per_block = c->rows;
-  a.tw = c->twp_x;
-  a.scale = 1.0f;
+  a.scale = T(1);
   a.partials = nullptr;
   a.n_partials = 0;
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
@@ -247,35 +281,77 @@ RowArgs row_args(const sgpe_ctx* c, double h_sub) {
   a.norm0 = p.norm0;
   a.parseval_w = dx * dy / npts;
   a.inv_npts = 1.0 / npts;
-  a.x0 = float(-p.xmax);
-  a.dx = float(dx);
-  a.y0 = float(-p.ymax);
-  a.dy = float(dy);
+  a.x0 = T(-p.xmax);
+  a.dx = T(dx);
+  a.y0 = T(-p.ymax);
+  a.dy = T(dy);
   const double h = h_sub > 0.0 ? h_sub : p.dt;
-  a.hfrac = float(h / p.dt);
-  a.hvx = float(0.5 * h * p.wx * p.wx);
-  a.hvy = float(0.5 * h * p.wy * p.wy);
-  a.hdelta2 = float(0.5 * h * p.delta);
-  a.hg_uu = float(h * p.g_uu);
-  a.hg_dd = float(h * p.g_dd);
-  a.hg_ud = float(h * p.g_ud);
-  a.hbx = c->hbx;
-  a.hby = c->hby;
+  a.hfrac = T(h / p.dt);
+  a.hvx = T(0.5 * h * p.wx * p.wx);
+  a.hvy = T(0.5 * h * p.wy * p.wy);
+  a.hdelta2 = T(0.5 * h * p.delta);
+  a.hg_uu = T(h * p.g_uu);
+  a.hg_dd = T(h * p.g_dd);
+  a.hg_ud = T(h * p.g_ud);
   return a;
 }
 
-ColArgs col_args(const sgpe_ctx* c, bool imag, bool half) {
-  ColArgs a{};
-  a.psi = c->psi;
+RowArgs row_args(const sgpe_ctx* c, double h_sub) { return row_args_t<float>(c, h_sub); }
+
+template <class T>
+sgpe::ColArgsT<T> col_args_t(const sgpe_ctx* c, bool imag, bool half) {
+  sgpe::ColArgsT<T> a{};
+  const int idx = 2 * (imag ? 1 : 0) + (half ? 1 : 0);
+  if constexpr (std::is_same<T, double>::value) {
+    a.psi = c->psi64;
+    a.tw = c->twp64_y;
+    a.kx_tab = c->kx64[idx];
+    a.ky_tab = c->ky64[idx];
+  } else {
+    a.psi = c->psi;
+    a.tw = c->twp_y;
+    a.kx_tab = c->kx_tab[idx];
+    a.ky_tab = c->ky_tab[idx];
+  }
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.cols = c->cols;
-  a.tw = c->twp_y;
-  const int idx = 2 * (imag ? 1 : 0) + (half ? 1 : 0);
-  a.kx_tab = c->kx_tab[idx];
-  a.ky_tab = c->ky_tab[idx];
   a.partials = c->partials;
   return a;
+}
+
+ColArgs col_args(const sgpe_ctx* c, bool imag, bool half) { return col_args_t<float>(c, imag, half); }
+
+// The fused schedule on a complex128 state: the same sequence of passes as run_steps, with the
+// fp64 instantiations of the kernels (16 points per lane, no prefetch).
+static sgpe_status run_steps_c128(sgpe_ctx* c, int64_t n, bool imag) {
+  const double npts = double(c->p.nx) * double(c->p.ny);
+  hipStream_t s = c->stream;
+  sgpe::RowArgsT<double> ra = row_args_t<double>(c, 0.0);
+  hipError_t e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, s);
+  if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, true), sgpe::NORM_NONE, s);
+  for (int64_t i = 1; i <= n && e == hipSuccess; ++i) {
+    sgpe::RowArgsT<double> r = ra;
+    r.scale = 1.0 / npts;
+    if (imag && i > 1) {
+      r.partials = c->partials;
+      r.n_partials = col_groups(c);
+    }
+    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, s);
+    const bool last = (i == n);
+    const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
+    if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, last), nm, s);
+  }
+  if (e == hipSuccess) {
+    sgpe::RowArgsT<double> r = ra;
+    r.scale = 1.0 / npts;
+    if (imag) {
+      r.partials = c->partials;
+      r.n_partials = col_groups(c);
+    }
+    e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, s);
+  }
+  return status_of(e);
 }
 
 // The fused schedule of n steps: K(dt/2) [R K(dt)]^(n-1) R K(dt/2), with the normalisation of
@@ -284,6 +360,10 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag);
 
 sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev) {
   if (n == 0) return SGPE_OK;
+  if (c->prec == SGPE_C128) {
+    if (ev) return SGPE_ESTATE;
+    return run_steps_c128(c, n, imag);
+  }
   if (c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
     if (ev) return SGPE_ESTATE;
     return run_steps_variant(c, n, imag);
@@ -455,9 +535,22 @@ const char* sgpe_strerror(sgpe_status s) {
   return "unknown status";
 }
 
+// Columns per column-pass tile for complex128: at most 4, 256 threads where one column allows it,
+// within the LDS (double2 slots take twice the bytes).
+static int c128_cols(int nx, int ny, size_t max_lds) {
+  int c = 4;
+  while (c > 1 && (2 * c * (ny / 16) > 256 || !sgpe::col_cols_supported(nx, ny, c, 1, 16, max_lds / 2))) c >>= 1;
+  return c;
+}
+
 sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, sgpe_ctx** out) {
+  return sgpe_create_ex(p, SGPE_C64, hip_stream, psi_dev, out);
+}
+
+sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_stream, void* psi_dev, sgpe_ctx** out) {
   if (!out) return SGPE_EINVAL;
   *out = nullptr;
+  if (precision != SGPE_C64 && precision != SGPE_C128) return SGPE_EINVAL;
   sgpe_status st = sgpe_validate_params(p);
   if (st != SGPE_OK) return st;
   int ndev = 0;
@@ -480,9 +573,18 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
   // the kernels' static LDS (reduction scratch) is < 256 bytes
   c->max_lds = prop.sharedMemPerBlock > 256 ? size_t(prop.sharedMemPerBlock) - 256 : 0;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  c->prec = precision;
   default_schedule(c);
+  const bool c128 = precision == SGPE_C128;
+  if (c128) {
+    c->rows = sgpe::row_rows_per_block(p->nx, p->ny, 16, c->max_lds / 2);
+    c->cols = c128_cols(p->nx, p->ny, c->max_lds);
+    c->row_points = c->col_points = 16;
+    c->row_iters = c->col_iters = 1;
+  }
   c->full2x2 = (p->omega_r0 != 0.0);
-  if (sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds ||
+  const size_t wb = c128 ? 2 : 1;   // LDS bytes per slot relative to complex64
+  if (wb * sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || wb * sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds ||
       !sgpe::energy_fits(p->nx, p->ny, c->max_lds)) {
     delete c;
     return SGPE_ENOMEM;
@@ -493,26 +595,40 @@ sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, s
     sgpe_destroy(c);
     return s;
   };
-  if (psi_dev) {
-    c->psi = static_cast<float4*>(psi_dev);
-  } else {
-    void* ptr = nullptr;
-    if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return fail(st);
-    c->psi = static_cast<float4*>(ptr);
+  const size_t state_bytes = npts * (c128 ? sizeof(double4) : sizeof(float4));
+  void* state = psi_dev;
+  if (!state) {
+    if ((st = dev_alloc(c, &state, state_bytes)) != SGPE_OK) return fail(st);
     c->own_psi = true;
   }
+  if (c128) c->psi64 = static_cast<double4*>(state);
+  else c->psi = static_cast<float4*>(state);
   if ((st = upload(c, &c->twd_x, twiddles64(p->nx))) != SGPE_OK) return fail(st);
   if ((st = upload(c, &c->twd_y, twiddles64(p->ny))) != SGPE_OK) return fail(st);
-  if ((st = upload(c, &c->twp_x, twiddles_plain(p->nx))) != SGPE_OK) return fail(st);
-  if ((st = upload(c, &c->twp_y, twiddles_plain(p->ny))) != SGPE_OK) return fail(st);
+  if (c128) {
+    if ((st = upload(c, &c->twp64_x, twiddles_plain<double>(p->nx))) != SGPE_OK) return fail(st);
+    if ((st = upload(c, &c->twp64_y, twiddles_plain<double>(p->ny))) != SGPE_OK) return fail(st);
+  } else {
+    if ((st = upload(c, &c->twp_x, twiddles_plain(p->nx))) != SGPE_OK) return fail(st);
+    if ((st = upload(c, &c->twp_y, twiddles_plain(p->ny))) != SGPE_OK) return fail(st);
+  }
   for (int imag = 0; imag < 2; ++imag) {
     for (int half = 0; half < 2; ++half) {
-      std::vector<float4> kx;
-      std::vector<float2> ky;
-      k_tables(*p, imag != 0, half ? 0.5 * p->dt : p->dt, kx, ky);
       const int idx = 2 * imag + half;
-      if ((st = upload(c, &c->kx_tab[idx], kx)) != SGPE_OK) return fail(st);
-      if ((st = upload(c, &c->ky_tab[idx], ky)) != SGPE_OK) return fail(st);
+      const double h = half ? 0.5 * p->dt : p->dt;
+      if (c128) {
+        std::vector<double4> kx;
+        std::vector<double2> ky;
+        k_tables<double>(*p, imag != 0, h, kx, ky);
+        if ((st = upload(c, &c->kx64[idx], kx)) != SGPE_OK) return fail(st);
+        if ((st = upload(c, &c->ky64[idx], ky)) != SGPE_OK) return fail(st);
+      } else {
+        std::vector<float4> kx;
+        std::vector<float2> ky;
+        k_tables(*p, imag != 0, h, kx, ky);
+        if ((st = upload(c, &c->kx_tab[idx], kx)) != SGPE_OK) return fail(st);
+        if ((st = upload(c, &c->ky_tab[idx], ky)) != SGPE_OK) return fail(st);
+      }
     }
   }
   if (c->full2x2) {
@@ -544,7 +660,7 @@ void sgpe_destroy(sgpe_ctx* c) {
 }
 
 sgpe_status sgpe_set_col_tile(sgpe_ctx* c, int32_t columns) {
-  if (!c) return SGPE_EINVAL;
+  if (!c || c->prec == SGPE_C128) return SGPE_EINVAL;
   if (columns == 0) {
     default_schedule(c);
     return SGPE_OK;
@@ -566,7 +682,7 @@ sgpe_status sgpe_get_schedule(sgpe_ctx* c, sgpe_schedule* out) {
 }
 
 sgpe_status sgpe_set_schedule(sgpe_ctx* c, const sgpe_schedule* s) {
-  if (!c) return SGPE_EINVAL;
+  if (!c || c->prec == SGPE_C128) return SGPE_EINVAL;
   if (!s) {
     default_schedule(c);
     return SGPE_OK;
@@ -581,13 +697,22 @@ sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {
   const size_t nx = size_t(c->p.nx), ny = size_t(c->p.ny), npts = nx * ny;
   for (size_t i = 0; i < 4 * npts; ++i)
     if (!std::isfinite(h[i])) return SGPE_ENONFINITE;
-  std::vector<float4> buf(npts);
   const double* up = h;
   const double* dn = h + 2 * npts;
-  for (size_t i = 0; i < npts; ++i)
-    buf[i] = make_float4(float(up[2 * i]), float(up[2 * i + 1]), float(dn[2 * i]), float(dn[2 * i + 1]));
-  if (hipMemcpyAsync(c->psi, buf.data(), npts * sizeof(float4), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
+  hipError_t e;
+  if (c->prec == SGPE_C128) {
+    std::vector<double4> buf(npts);
+    for (size_t i = 0; i < npts; ++i) buf[i] = make_double4(up[2 * i], up[2 * i + 1], dn[2 * i], dn[2 * i + 1]);
+    e = hipMemcpyAsync(c->psi64, buf.data(), npts * sizeof(double4), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    std::vector<float4> buf(npts);
+    for (size_t i = 0; i < npts; ++i)
+      buf[i] = make_float4(float(up[2 * i]), float(up[2 * i + 1]), float(dn[2 * i]), float(dn[2 * i + 1]));
+    e = hipMemcpyAsync(c->psi, buf.data(), npts * sizeof(float4), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return SGPE_EDEVICE;
   }
@@ -602,22 +727,34 @@ sgpe_status sgpe_get_psi(sgpe_ctx* c, double* h) {
   if (!h) return SGPE_EINVAL;
   if (!c->has_state) return SGPE_ESTATE;
   const size_t npts = size_t(c->p.nx) * size_t(c->p.ny);
-  std::vector<float4> buf(npts);
-  if (hipMemcpyAsync(buf.data(), c->psi, npts * sizeof(float4), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return SGPE_EDEVICE;
-  }
   bool ok = true;
   double* up = h;
   double* dn = h + 2 * npts;
-  for (size_t i = 0; i < npts; ++i) {
-    const float4 w = buf[i];
-    up[2 * i] = w.x;
-    up[2 * i + 1] = w.y;
-    dn[2 * i] = w.z;
-    dn[2 * i + 1] = w.w;
-    ok = ok && std::isfinite(w.x) && std::isfinite(w.y) && std::isfinite(w.z) && std::isfinite(w.w);
+  auto unpack = [&](const auto& buf) {
+    for (size_t i = 0; i < npts; ++i) {
+      const auto w = buf[i];
+      up[2 * i] = w.x;
+      up[2 * i + 1] = w.y;
+      dn[2 * i] = w.z;
+      dn[2 * i + 1] = w.w;
+      ok = ok && std::isfinite(w.x) && std::isfinite(w.y) && std::isfinite(w.z) && std::isfinite(w.w);
+    }
+  };
+  hipError_t e;
+  if (c->prec == SGPE_C128) {
+    std::vector<double4> buf(npts);
+    e = hipMemcpyAsync(buf.data(), c->psi64, npts * sizeof(double4), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) unpack(buf);
+  } else {
+    std::vector<float4> buf(npts);
+    e = hipMemcpyAsync(buf.data(), c->psi, npts * sizeof(float4), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) unpack(buf);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
   }
   if (!ok) c->latched = SGPE_ENONFINITE;
   return c->latched;
@@ -647,7 +784,8 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
   if (!c->has_state) return SGPE_ESTATE;
   const long long npts = (long long)c->p.nx * c->p.ny;
   const int nb = sgpe::norm_blocks();
-  hipError_t e = sgpe::launch_norm(c->psi, npts, c->npart, nb, c->stream);
+  hipError_t e = c->prec == SGPE_C128 ? sgpe::launch_norm(c->psi64, npts, c->npart, nb, c->stream)
+                                      : sgpe::launch_norm(c->psi, npts, c->npart, nb, c->stream);
   if (e != hipSuccess) return status_of(e);
   std::vector<double> part(nb);
   if (hipMemcpyAsync(part.data(), c->npart, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
@@ -668,6 +806,7 @@ sgpe_status sgpe_set_splitting(sgpe_ctx* c, int32_t order, int32_t real_space) {
   if ((order != SGPE_SPLIT_KRK && order != SGPE_SPLIT_RKR) ||
       (real_space != SGPE_RSPLIT_FROZEN && real_space != SGPE_RSPLIT_NLN))
     return SGPE_EINVAL;
+  if (c->prec == SGPE_C128 && (order != SGPE_SPLIT_KRK || real_space != SGPE_RSPLIT_FROZEN)) return SGPE_EINVAL;
   const int row_groups = c->p.ny / c->rows;
   if (order == SGPE_SPLIT_RKR && row_groups > kMaxPartials) return SGPE_EINVAL;
   c->split_order = order;
@@ -721,20 +860,34 @@ sgpe_status sgpe_add_noise(sgpe_ctx* c, const double* xi, double amplitude) {
   const size_t npts = size_t(c->p.nx) * size_t(c->p.ny);
   for (size_t i = 0; i < 4 * npts; ++i)
     if (!std::isfinite(xi[i])) return SGPE_ENONFINITE;
-  if (!c->scratch) {
-    void* ptr = nullptr;
-    if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return st;
-    c->scratch = static_cast<float4*>(ptr);
-  }
-  std::vector<float4> buf(npts);
   const double* up = xi;
   const double* dn = xi + 2 * npts;
-  for (size_t i = 0; i < npts; ++i)
-    buf[i] = make_float4(float(up[2 * i]), float(up[2 * i + 1]), float(dn[2 * i]), float(dn[2 * i + 1]));
-  hipError_t e = hipMemcpyAsync(c->scratch, buf.data(), npts * sizeof(float4), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = sgpe::launch_add_noise(c->psi, c->scratch, float(amplitude), (long long)npts, c->stream);
-  // buf must outlive the copy
-  if (hipStreamSynchronize(c->stream) != hipSuccess || e != hipSuccess) {
+  hipError_t e;
+  if (c->prec == SGPE_C128) {
+    if (!c->scratch_q64) {
+      void* ptr = nullptr;
+      if ((st = dev_alloc(c, &ptr, npts * sizeof(double4))) != SGPE_OK) return st;
+      c->scratch_q64 = static_cast<double4*>(ptr);
+    }
+    std::vector<double4> buf(npts);
+    for (size_t i = 0; i < npts; ++i) buf[i] = make_double4(up[2 * i], up[2 * i + 1], dn[2 * i], dn[2 * i + 1]);
+    e = hipMemcpyAsync(c->scratch_q64, buf.data(), npts * sizeof(double4), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = sgpe::launch_add_noise(c->psi64, c->scratch_q64, amplitude, (long long)npts, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) e = hipErrorUnknown;   // buf must outlive the copy
+  } else {
+    if (!c->scratch) {
+      void* ptr = nullptr;
+      if ((st = dev_alloc(c, &ptr, npts * sizeof(float4))) != SGPE_OK) return st;
+      c->scratch = static_cast<float4*>(ptr);
+    }
+    std::vector<float4> buf(npts);
+    for (size_t i = 0; i < npts; ++i)
+      buf[i] = make_float4(float(up[2 * i]), float(up[2 * i + 1]), float(dn[2 * i]), float(dn[2 * i + 1]));
+    e = hipMemcpyAsync(c->scratch, buf.data(), npts * sizeof(float4), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = sgpe::launch_add_noise(c->psi, c->scratch, float(amplitude), (long long)npts, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) e = hipErrorUnknown;   // buf must outlive the copy
+  }
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return SGPE_EDEVICE;
   }
@@ -748,7 +901,8 @@ sgpe_status sgpe_phase_separation(sgpe_ctx* c, double* out) {
   if (!c->has_state) return SGPE_ESTATE;
   const long long npts = (long long)c->p.nx * c->p.ny;
   const int nb = sgpe::norm_blocks();
-  hipError_t e = sgpe::launch_moments(c->psi, npts, c->epart, nb, c->stream);
+  hipError_t e = c->prec == SGPE_C128 ? sgpe::launch_moments(c->psi64, npts, c->epart, nb, c->stream)
+                                      : sgpe::launch_moments(c->psi, npts, c->epart, nb, c->stream);
   if (e != hipSuccess) return status_of(e);
   double m[sgpe::kMomentParts];
   if ((st = fetch_sums(c, nb, sgpe::kMomentParts, m)) != SGPE_OK) return st;
@@ -765,8 +919,10 @@ static sgpe_status disk_population(sgpe_ctx* c, double r2, double* out) {
   const sgpe_params& p = c->p;
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
   const int nb = sgpe::norm_blocks();
-  hipError_t e = sgpe::launch_disk_population(c->psi, p.nx, p.ny, -p.xmax, dx, -p.ymax, dy, r2, c->epart, nb,
-                                              c->stream);
+  hipError_t e =
+      c->prec == SGPE_C128
+          ? sgpe::launch_disk_population(c->psi64, p.nx, p.ny, -p.xmax, dx, -p.ymax, dy, r2, c->epart, nb, c->stream)
+          : sgpe::launch_disk_population(c->psi, p.nx, p.ny, -p.xmax, dx, -p.ymax, dy, r2, c->epart, nb, c->stream);
   if (e != hipSuccess) return status_of(e);
   return fetch_sums(c, nb, 1, out);
 }
@@ -807,7 +963,9 @@ sgpe_status sgpe_winding(sgpe_ctx* c, double radius, int32_t* n, double* raw) {
   const double d = std::min(2.0 * p.xmax / p.nx, 2.0 * p.ymax / p.ny);
   const double mm = std::ceil(4.0 * M_PI * radius / d);
   const int m = mm < 256.0 ? 256 : int(mm);
-  hipError_t e = sgpe::launch_winding(c->psi, p.nx, p.ny, p.xmax, p.ymax, radius, m, c->epart, c->stream);
+  hipError_t e = c->prec == SGPE_C128
+                     ? sgpe::launch_winding(c->psi64, p.nx, p.ny, p.xmax, p.ymax, radius, m, c->epart, c->stream)
+                     : sgpe::launch_winding(c->psi, p.nx, p.ny, p.xmax, p.ymax, radius, m, c->epart, c->stream);
   if (e != hipSuccess) return status_of(e);
   double w[2];
   if ((st = fetch_sums(c, 1, 2, w)) != SGPE_OK) return st;
@@ -839,6 +997,7 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
   EnergyArgs a{};
   a.psi = c->psi;
+  a.psi64 = c->psi64;
   a.scratch = c->scratch64;
   a.nx = p.nx;
   a.ny = p.ny;
@@ -895,7 +1054,9 @@ sgpe_status sgpe_profile_steps(sgpe_ctx* c, int32_t imag, int64_t n, double* row
   sgpe_status st = check_ctx(c);
   if (st != SGPE_OK) return st;
   if (n <= 0) return SGPE_EINVAL;
-  if (!c->has_state || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) return SGPE_ESTATE;
+  if (!c->has_state || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN ||
+      c->prec == SGPE_C128)
+    return SGPE_ESTATE;
   std::vector<hipEvent_t> ev(3 * size_t(n));
   for (auto& x : ev) {
     if (hipEventCreate(&x) != hipSuccess) {
@@ -926,7 +1087,9 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* c, int32_t imag, int64_t n, double* r
   sgpe_status st = check_ctx(c);
   if (st != SGPE_OK) return st;
   if (n <= 0) return SGPE_EINVAL;
-  if (!c->has_state || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) return SGPE_ESTATE;
+  if (!c->has_state || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN ||
+      c->prec == SGPE_C128)
+    return SGPE_ESTATE;
   const sgpe_params& p = c->p;
   const size_t bytes = size_t(p.nx) * size_t(p.ny) * sizeof(float4);
   if (!c->scratch) {

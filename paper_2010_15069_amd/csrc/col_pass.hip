@@ -27,9 +27,13 @@ __device__ __forceinline__ int col_group(int b, int ngroups) {
 // A workgroup handles ITERS adjacent tiles of C columns, one after the other; the next tile's
 // data is loaded into registers before the current tile is transformed.  P points per lane:
 // T = N / P lanes per transform.
-template <int N, int NORM, int ITERS, int P>
-__device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) {
-  extern __shared__ float2 lds_raw[];
+extern __shared__ __align__(16) unsigned char col_lds[];
+
+template <int N, int NORM, int ITERS, int P, class R>
+__device__ __forceinline__ void col_body(const ColArgsT<R>& a, int wg, int ngroups) {
+  using CX = cplx_t<R>;
+  CX* const lds_raw = reinterpret_cast<CX*>(col_lds);
+  constexpr uint32_t PB = sizeof(point_t<R>), CB = sizeof(CX);   // bytes per point / component
   __shared__ double red[64];
   constexpr int T = N / P;
   const int C = a.cols;
@@ -40,15 +44,15 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
   const int t = pair / C;
   const int tile0 = col_group(wg, ngroups) * ITERS;
   const int x0 = tile0 * C + cc;
-  const LdsView<float2> lds{lds_raw + 2 * cc + comp, 1 + __builtin_ctz(C)};
-  // element (row y) of this lane's component is at byte offset 16 (y nx + x) + 8 comp; 32-bit
+  const LdsView<CX> lds{lds_raw + 2 * cc + comp, 1 + __builtin_ctz(C)};
+  // element (row y) of this lane's component is at byte offset PB (y nx + x) + CB comp; 32-bit
   // offsets from a wave-uniform base, the row stride a wave-uniform value
   const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
   char* __restrict__ out = reinterpret_cast<char*>(a.psi);
-  const uint32_t rstride = 16u * static_cast<uint32_t>(a.nx);
+  const uint32_t rstride = PB * static_cast<uint32_t>(a.nx);
   const uint32_t mstride = static_cast<uint32_t>(T) * rstride;
-  const uint32_t tile_stride = 16u * static_cast<uint32_t>(C);
-  uint32_t off = static_cast<uint32_t>(t) * rstride + 16u * static_cast<uint32_t>(x0) + 8u * comp;
+  const uint32_t tile_stride = PB * static_cast<uint32_t>(C);
+  uint32_t off = static_cast<uint32_t>(t) * rstride + PB * static_cast<uint32_t>(x0) + CB * comp;
 
   // The k_y operator row is staged in LDS (loaded per point after the forward transform, its
   // latency would sit in the middle of the pass).  Its loads go out first, into registers (at
@@ -56,18 +60,18 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
   // them alone and not for the data behind them.
   constexpr int KY_MAX = P / 2;
   const int nth = blockDim.x;
-  float2 kyv[KY_MAX];
+  CX kyv[KY_MAX];
 #pragma unroll
   for (int k = 0; k < KY_MAX; ++k)
     if (k * nth < N) kyv[k] = a.ky_tab[min(tid + k * nth, N - 1)];
-  float2 v[P], nxt[P];
+  CX v[P], nxt[P];
 #pragma unroll
-  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const float2*>(base + (off + mstride * m));
+  for (int m = 0; m < P; ++m) v[m] = *reinterpret_cast<const CX*>(base + (off + mstride * m));
   // this component's row of M' - 1 at k_x: {d_own, d_other}
-  float4 d = a.kx_tab[2 * x0 + comp], dn = d;
-  TwPlain<N, P> tr;
+  point_t<R> d = a.kx_tab[2 * x0 + comp], dn = d;
+  TwPlain<N, P, R> tr;
   load_twiddles<N>(tr, t, a.tw);
-  float2* __restrict__ kyl = lds_raw + 2 * C * (N + N / 16);
+  CX* __restrict__ kyl = lds_raw + 2 * C * (N + N / 16);
 #pragma unroll
   for (int k = 0; k < KY_MAX; ++k)
     if (k * nth < N && tid + k * nth < N) kyl[tid + k * nth] = kyv[k];
@@ -78,7 +82,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m)
-        nxt[m] = *reinterpret_cast<const float2*>(base + (off + tile_stride + mstride * m));
+        nxt[m] = *reinterpret_cast<const CX*>(base + (off + tile_stride + mstride * m));
       dn = a.kx_tab[2 * (x0 + (it + 1) * C) + comp];
     }
     fwd_pass<N>(v, lds, t, tr);
@@ -86,18 +90,18 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
 
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-      const float2 w = v[m];
-      const float2 o = pair_swap(w);
-      const float2 q = kyl[t + T * m];
-      const float c1r = fmaf(-d.w, o.y, fmaf(d.z, o.x, fmaf(-d.y, w.y, d.x * w.x)));
-      const float c1i = fmaf(d.w, o.x, fmaf(d.z, o.y, fmaf(d.y, w.x, d.x * w.y)));
-      const float cr = fmaf(-q.y, w.y, fmaf(q.x, w.x, fmaf(-q.y, c1i, fmaf(q.x, c1r, c1r))));
-      const float ci = fmaf(q.y, w.x, fmaf(q.x, w.y, fmaf(q.y, c1r, fmaf(q.x, c1i, c1i))));
-      const float2 res = make_float2(w.x + cr, w.y + ci);
+      const CX w = v[m];
+      const CX o = pair_swap(w);
+      const CX q = kyl[t + T * m];
+      const R c1r = fma_(-d.w, o.y, fma_(d.z, o.x, fma_(-d.y, w.y, d.x * w.x)));
+      const R c1i = fma_(d.w, o.x, fma_(d.z, o.y, fma_(d.y, w.x, d.x * w.y)));
+      const R cr = fma_(-q.y, w.y, fma_(q.x, w.x, fma_(-q.y, c1i, fma_(q.x, c1r, c1r))));
+      const R ci = fma_(q.y, w.x, fma_(q.x, w.y, fma_(q.y, c1r, fma_(q.x, c1i, c1i))));
+      const CX res = mk2(w.x + cr, w.y + ci);
       if constexpr (NORM == NORM_DOT) {
-        acc += static_cast<double>(fmaf(w.x, res.x, w.y * res.y));
+        acc += static_cast<double>(fma_(w.x, res.x, w.y * res.y));
       } else if constexpr (NORM == NORM_SQ) {
-        acc += static_cast<double>(fmaf(res.x, res.x, res.y * res.y));
+        acc += static_cast<double>(fma_(res.x, res.x, res.y * res.y));
       }
       v[m] = res;
     }
@@ -105,7 +109,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int wg, int ngroups) 
     inv_pass<N>(v, lds, t, tr);
 
 #pragma unroll
-    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + (off + mstride * m)) = v[m];
+    for (int m = 0; m < P; ++m) *reinterpret_cast<CX*>(out + (off + mstride * m)) = v[m];
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = nxt[m];
@@ -129,6 +133,13 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) 
 template <int N, int NORM, int P>
 __global__ void __launch_bounds__(512) col_kernel_batch(const ColArgs* __restrict__ tab) {
   col_body<N, NORM, 1, P>(tab[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+// complex128: 16 points per lane, one tile per workgroup; the host keeps tiles at 256 threads
+// except where one column alone needs more (N = 4096)
+template <int N, int NORM>
+__global__ void __launch_bounds__(2 * N / 16 > 256 ? 512 : 256) col_kernel_c128(ColArgsT<double> a) {
+  col_body<N, NORM, 1, 16>(a, blockIdx.x, gridDim.x);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -182,6 +193,42 @@ static hipError_t col_dispatch(const ColArgs& a, const ColArgs* tab, int count, 
     case 1024: return col_launch_n<1024>(a, tab, count, norm, iters, points, s);
     case 2048: return col_launch_n<2048>(a, tab, count, norm, iters, points, s);
     case 4096: return col_launch_n<4096>(a, tab, count, norm, iters, points, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int NORM>
+static hipError_t col_launch_c128(const ColArgsT<double>& a, hipStream_t s) {
+  const dim3 block(2 * a.cols * (N / 16));
+  const dim3 grid(a.nx / a.cols);
+  if (block.x > (2 * N / 16 > 256 ? 512u : 256u)) return hipErrorInvalidValue;
+  const size_t lds = 2 * col_lds_bytes(N, a.cols);   // double2 slots and k_y row
+  hipLaunchKernelGGL((col_kernel_c128<N, NORM>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t col_launch_c128_n(const ColArgsT<double>& a, int norm_mode, hipStream_t s) {
+  switch (norm_mode) {
+    case NORM_NONE: return col_launch_c128<N, NORM_NONE>(a, s);
+    case NORM_DOT: return col_launch_c128<N, NORM_DOT>(a, s);
+    case NORM_SQ: return col_launch_c128<N, NORM_SQ>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col(const ColArgsT<double>& a, int norm_mode, hipStream_t s) {
+  if (!schedule_supported(a.ny, a.cols, 1, 16) || a.cols > a.nx || a.nx % a.cols != 0) return hipErrorInvalidValue;
+  switch (a.ny) {
+    case 16: return col_launch_c128_n<16>(a, norm_mode, s);
+    case 32: return col_launch_c128_n<32>(a, norm_mode, s);
+    case 64: return col_launch_c128_n<64>(a, norm_mode, s);
+    case 128: return col_launch_c128_n<128>(a, norm_mode, s);
+    case 256: return col_launch_c128_n<256>(a, norm_mode, s);
+    case 512: return col_launch_c128_n<512>(a, norm_mode, s);
+    case 1024: return col_launch_c128_n<1024>(a, norm_mode, s);
+    case 2048: return col_launch_c128_n<2048>(a, norm_mode, s);
+    case 4096: return col_launch_c128_n<4096>(a, norm_mode, s);
     default: return hipErrorInvalidValue;
   }
 }

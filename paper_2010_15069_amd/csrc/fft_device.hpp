@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "sgpe_internal.hpp"
+
 namespace sgpe {
 
 // ---------------------------------------------------------------------------------------------
@@ -34,6 +36,26 @@ __device__ __forceinline__ float4 vneg(float4 a) { return make_float4(-a.x, -a.y
 __device__ __forceinline__ float4 vscale(float4 a, float s) {
   return make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
 }
+__device__ __forceinline__ double2 vadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 vsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 vneg(double2 a) { return make_double2(-a.x, -a.y); }
+__device__ __forceinline__ double2 vscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// The real type of a complex type (the complex types of a precision are in sgpe_internal.hpp).
+template <class C> struct RealOf;
+template <> struct RealOf<float2> { using T = float; };
+template <> struct RealOf<double2> { using T = double; };
+__device__ __forceinline__ float2 mk2(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ double2 mk2(double x, double y) { return make_double2(x, y); }
+// fp32 intrinsics for float (the complex64 code is unchanged by the templating), fp64 for double
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float exp_(float x) { return expf(x); }
+__device__ __forceinline__ double exp_(double x) { return exp(x); }
+__device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float fabs_(float x) { return fabsf(x); }
+__device__ __forceinline__ double fabs_(double x) { return fabs(x); }
 
 // ---------------------------------------------------------------------------------------------
 // LDS addressing: a transform's N positions occupy N + N/16 slots (one pad slot per 16
@@ -64,54 +86,79 @@ struct LdsView {
 // commutators with the step's operators, O(dt eps) per step.  The forward costs 4 instructions
 // per complex product instead of 8 for a compensated one; the inverse costs 8.
 // ---------------------------------------------------------------------------------------------
-#define SGPE_P_R2 0.70710676908493042f       // fp32(1/sqrt(2))
-#define SGPE_P_R2_LO 2.42032350e-08f         // r2 (1/(2 r2^2) - 1) for the fp32 r2
-#define SGPE_P_C8 0.92387950420379639f       // fp32(cos(pi/8))
-#define SGPE_P_S8 0.38268342614173889f       // fp32(sin(pi/8))
-#define SGPE_P_C8_LO 5.27244843e-08f         // c8 eta8, eta8 = 1/(c8^2 + s8^2) - 1 for the pair
-#define SGPE_P_S8_LO 2.18391971e-08f         // s8 eta8
+// Butterfly constants.  fp32: the rounded 1/sqrt(2), cos(pi/8), sin(pi/8) and the low parts that
+// make the inverse exact.  fp64: the rounded constants; their modulus error (~1e-16) is left in
+// place -- applied every step it drifts by ~1e-10 over 10^6 steps -- so the low parts are zero.
+template <class T> struct Roots;
+template <> struct Roots<float> {
+  static constexpr float R2 = 0.70710676908493042f;      // fp32(1/sqrt(2))
+  static constexpr float R2_LO = 2.42032350e-08f;        // r2 (1/(2 r2^2) - 1) for the fp32 r2
+  static constexpr float C8 = 0.92387950420379639f;      // fp32(cos(pi/8))
+  static constexpr float S8 = 0.38268342614173889f;      // fp32(sin(pi/8))
+  static constexpr float C8_LO = 5.27244843e-08f;        // c8 eta8, eta8 = 1/(c8^2 + s8^2) - 1
+  static constexpr float S8_LO = 2.18391971e-08f;        // s8 eta8
+};
+template <> struct Roots<double> {
+  static constexpr double R2 = 0.70710678118654752440;
+  static constexpr double R2_LO = 0.0;
+  static constexpr double C8 = 0.92387953251128675613;
+  static constexpr double S8 = 0.38268343236508977173;
+  static constexpr double C8_LO = 0.0;
+  static constexpr double S8_LO = 0.0;
+};
 
-__device__ __forceinline__ float2 pf_rot90(float2 a) { return make_float2(a.y, -a.x); }   // * (-i)
-__device__ __forceinline__ float2 pi_rot90(float2 a) { return make_float2(-a.y, a.x); }   // * (+i)
+template <class C>
+__device__ __forceinline__ C pf_rot90(C a) { return mk2(a.y, -a.x); }   // * (-i)
+template <class C>
+__device__ __forceinline__ C pi_rot90(C a) { return mk2(-a.y, a.x); }   // * (+i)
 // * r2 (1 - i) and its exact inverse * (1 + i) / (2 r2)
-__device__ __forceinline__ float2 pf_rot45(float2 a) {
-  return make_float2(SGPE_P_R2 * (a.x + a.y), SGPE_P_R2 * (a.y - a.x));
+template <class C>
+__device__ __forceinline__ C pf_rot45(C a) {
+  using K = Roots<typename RealOf<C>::T>;
+  return mk2(K::R2 * (a.x + a.y), K::R2 * (a.y - a.x));
 }
-__device__ __forceinline__ float2 pi_rot45(float2 a) {
-  const float d = a.x - a.y, e = a.x + a.y;
-  return make_float2(fmaf(d, SGPE_P_R2, d * SGPE_P_R2_LO), fmaf(e, SGPE_P_R2, e * SGPE_P_R2_LO));
+template <class C>
+__device__ __forceinline__ C pi_rot45(C a) {
+  using K = Roots<typename RealOf<C>::T>;
+  const auto d = a.x - a.y, e = a.x + a.y;
+  return mk2(fma_(d, K::R2, d * K::R2_LO), fma_(e, K::R2, e * K::R2_LO));
 }
 // * (c - i s) and its exact inverse * ((c + lx) + i (s + ly)), (lx, ly) = (c, s) eta
-__device__ __forceinline__ float2 pf_cmul(float2 a, float c, float s) {
-  return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -a.x * s));
+template <class C, class T = typename RealOf<C>::T>
+__device__ __forceinline__ C pf_cmul(C a, T c, T s) {
+  return mk2(fma_(a.x, c, a.y * s), fma_(a.y, c, -a.x * s));
 }
-__device__ __forceinline__ float2 pi_cmul(float2 a, float c, float s, float lx, float ly) {
-  return make_float2(fmaf(a.x, c, fmaf(-a.y, s, fmaf(a.x, lx, -a.y * ly))),
-                     fmaf(a.y, c, fmaf(a.x, s, fmaf(a.y, lx, a.x * ly))));
+template <class C, class T = typename RealOf<C>::T>
+__device__ __forceinline__ C pi_cmul(C a, T c, T s, T lx, T ly) {
+  return mk2(fma_(a.x, c, fma_(-a.y, s, fma_(a.x, lx, -a.y * ly))),
+             fma_(a.y, c, fma_(a.x, s, fma_(a.y, lx, a.x * ly))));
 }
 
 // forward small DFTs (sign -1)
-__device__ __forceinline__ void pf_dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
-  const float2 t0 = vadd(a0, a2), t1 = vsub(a0, a2);
-  const float2 t2 = vadd(a1, a3), t3 = pf_rot90(vsub(a1, a3));
+template <class C>
+__device__ __forceinline__ void pf_dft4(C& a0, C& a1, C& a2, C& a3) {
+  const C t0 = vadd(a0, a2), t1 = vsub(a0, a2);
+  const C t2 = vadd(a1, a3), t3 = pf_rot90(vsub(a1, a3));
   a0 = vadd(t0, t2);
   a2 = vsub(t0, t2);
   a1 = vadd(t1, t3);
   a3 = vsub(t1, t3);
 }
 // its exact inverse times 4 (conjugate structure; the constants are exact)
-__device__ __forceinline__ void pi_dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
-  const float2 t0 = vadd(a0, a2), t1 = vsub(a0, a2);
-  const float2 t2 = vadd(a1, a3), t3 = pi_rot90(vsub(a1, a3));
+template <class C>
+__device__ __forceinline__ void pi_dft4(C& a0, C& a1, C& a2, C& a3) {
+  const C t0 = vadd(a0, a2), t1 = vsub(a0, a2);
+  const C t2 = vadd(a1, a3), t3 = pi_rot90(vsub(a1, a3));
   a0 = vadd(t0, t2);
   a2 = vsub(t0, t2);
   a1 = vadd(t1, t3);
   a3 = vsub(t1, t3);
 }
 
-__device__ __forceinline__ void pf_dft8(float2 (&a)[8]) {
-  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
-  float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+template <class C>
+__device__ __forceinline__ void pf_dft8(C (&a)[8]) {
+  C e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  C o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
   pf_dft4(e0, e1, e2, e3);
   pf_dft4(o0, o1, o2, o3);
   o1 = pf_rot45(o1);
@@ -123,11 +170,12 @@ __device__ __forceinline__ void pf_dft8(float2 (&a)[8]) {
   a[3] = vadd(e3, o3); a[7] = vsub(e3, o3);
 }
 // exact inverse of pf_dft8, times 8
-__device__ __forceinline__ void pi_dft8(float2 (&a)[8]) {
-  float2 e0 = vadd(a[0], a[4]), o0 = vsub(a[0], a[4]);
-  float2 e1 = vadd(a[1], a[5]), o1 = vsub(a[1], a[5]);
-  float2 e2 = vadd(a[2], a[6]), o2 = vsub(a[2], a[6]);
-  float2 e3 = vadd(a[3], a[7]), o3 = vsub(a[3], a[7]);
+template <class C>
+__device__ __forceinline__ void pi_dft8(C (&a)[8]) {
+  C e0 = vadd(a[0], a[4]), o0 = vsub(a[0], a[4]);
+  C e1 = vadd(a[1], a[5]), o1 = vsub(a[1], a[5]);
+  C e2 = vadd(a[2], a[6]), o2 = vsub(a[2], a[6]);
+  C e3 = vadd(a[3], a[7]), o3 = vsub(a[3], a[7]);
   o1 = pi_rot45(o1);
   o2 = pi_rot90(o2);
   o3 = pi_rot45(pi_rot90(o3));
@@ -138,21 +186,23 @@ __device__ __forceinline__ void pi_dft8(float2 (&a)[8]) {
 }
 
 // forward 16-point DFT (4x4; input r = r1 + 4 r2, output k = k2 + 4 k1)
-__device__ __forceinline__ void pf_dft16(float2 (&a)[16]) {
+template <class C>
+__device__ __forceinline__ void pf_dft16(C (&a)[16]) {
+  using K = Roots<typename RealOf<C>::T>;
 #pragma unroll
   for (int r1 = 0; r1 < 4; ++r1) pf_dft4(a[r1], a[r1 + 4], a[r1 + 8], a[r1 + 12]);
-  a[5] = pf_cmul(a[5], SGPE_P_C8, SGPE_P_S8);             // W16^1
+  a[5] = pf_cmul(a[5], K::C8, K::S8);                    // W16^1
   a[9] = pf_rot45(a[9]);                                 // W16^2
-  a[13] = pf_cmul(a[13], SGPE_P_S8, SGPE_P_C8);           // W16^3
+  a[13] = pf_cmul(a[13], K::S8, K::C8);                  // W16^3
   a[6] = pf_rot45(a[6]);                                 // W16^2
   a[10] = pf_rot90(a[10]);                               // W16^4
   a[14] = pf_rot90(pf_rot45(a[14]));                     // W16^6
-  a[7] = pf_cmul(a[7], SGPE_P_S8, SGPE_P_C8);             // W16^3
+  a[7] = pf_cmul(a[7], K::S8, K::C8);                    // W16^3
   a[11] = pf_rot90(pf_rot45(a[11]));                     // W16^6
-  a[15] = vneg(pf_cmul(a[15], SGPE_P_C8, SGPE_P_S8));     // W16^9 = -W16^1
+  a[15] = vneg(pf_cmul(a[15], K::C8, K::S8));            // W16^9 = -W16^1
 #pragma unroll
   for (int k2 = 0; k2 < 4; ++k2) pf_dft4(a[4 * k2], a[4 * k2 + 1], a[4 * k2 + 2], a[4 * k2 + 3]);
-  float2 t[16];
+  C t[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) t[i] = a[i];
 #pragma unroll
@@ -161,33 +211,35 @@ __device__ __forceinline__ void pf_dft16(float2 (&a)[16]) {
     for (int k2 = 0; k2 < 4; ++k2) a[k2 + 4 * k1] = t[k1 + 4 * k2];
 }
 // exact inverse of pf_dft16, times 16: the same steps undone in reverse order
-__device__ __forceinline__ void pi_dft16(float2 (&a)[16]) {
-  float2 t[16];
+template <class C>
+__device__ __forceinline__ void pi_dft16(C (&a)[16]) {
+  using K = Roots<typename RealOf<C>::T>;
+  C t[16];
 #pragma unroll
   for (int k1 = 0; k1 < 4; ++k1)
 #pragma unroll
     for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = a[k2 + 4 * k1];
 #pragma unroll
   for (int k2 = 0; k2 < 4; ++k2) pi_dft4(t[4 * k2], t[4 * k2 + 1], t[4 * k2 + 2], t[4 * k2 + 3]);
-  t[5] = pi_cmul(t[5], SGPE_P_C8, SGPE_P_S8, SGPE_P_C8_LO, SGPE_P_S8_LO);
+  t[5] = pi_cmul(t[5], K::C8, K::S8, K::C8_LO, K::S8_LO);
   t[9] = pi_rot45(t[9]);
-  t[13] = pi_cmul(t[13], SGPE_P_S8, SGPE_P_C8, SGPE_P_S8_LO, SGPE_P_C8_LO);
+  t[13] = pi_cmul(t[13], K::S8, K::C8, K::S8_LO, K::C8_LO);
   t[6] = pi_rot45(t[6]);
   t[10] = pi_rot90(t[10]);
   t[14] = pi_rot45(pi_rot90(t[14]));
-  t[7] = pi_cmul(t[7], SGPE_P_S8, SGPE_P_C8, SGPE_P_S8_LO, SGPE_P_C8_LO);
+  t[7] = pi_cmul(t[7], K::S8, K::C8, K::S8_LO, K::C8_LO);
   t[11] = pi_rot45(pi_rot90(t[11]));
-  t[15] = vneg(pi_cmul(t[15], SGPE_P_C8, SGPE_P_S8, SGPE_P_C8_LO, SGPE_P_S8_LO));
+  t[15] = vneg(pi_cmul(t[15], K::C8, K::S8, K::C8_LO, K::S8_LO));
 #pragma unroll
   for (int r1 = 0; r1 < 4; ++r1) pi_dft4(t[r1], t[r1 + 4], t[r1 + 8], t[r1 + 12]);
 #pragma unroll
   for (int i = 0; i < 16; ++i) a[i] = t[i];
 }
 
-template <int R>
-__device__ __forceinline__ void pf_dft(float2 (&a)[R]) {
+template <int R, class C>
+__device__ __forceinline__ void pf_dft(C (&a)[R]) {
   if constexpr (R == 2) {
-    const float2 t = a[0];
+    const C t = a[0];
     a[0] = vadd(t, a[1]);
     a[1] = vsub(t, a[1]);
   } else if constexpr (R == 4) {
@@ -199,10 +251,10 @@ __device__ __forceinline__ void pf_dft(float2 (&a)[R]) {
     pf_dft16(a);
   }
 }
-template <int R>
-__device__ __forceinline__ void pi_dft(float2 (&a)[R]) {
+template <int R, class C>
+__device__ __forceinline__ void pi_dft(C (&a)[R]) {
   if constexpr (R == 2) {
-    const float2 t = a[0];
+    const C t = a[0];
     a[0] = vadd(t, a[1]);
     a[1] = vsub(t, a[1]);
   } else if constexpr (R == 4) {
@@ -243,15 +295,16 @@ constexpr int last_radix() {
 // products at use (its rounding, ~1e-15, lies far below the fp32 rounding it feeds).  Table
 // entries are float4 {cos, sin, eta, 0} of exp(-2 pi i j / N).  Loaded once per kernel (they
 // depend only on the thread index); three registers per root.
-template <int N, int P = 16>
+template <int N, int P = 16, class T = float>
 struct TwPlain {
   static constexpr int COUNT = tw_count_p<N, P>() > 0 ? tw_count_p<N, P>() : 1;
-  float2 cs[COUNT];
-  float eta[COUNT];
+  cplx_t<T> cs[COUNT];
+  T eta[COUNT];
 };
 
-template <int N, int P, int L = 1, int BASE = 0>
-__device__ __forceinline__ void load_twiddles(TwPlain<N, P>& tr, int t, const float4* __restrict__ tw) {
+template <int N, int P, int L = 1, int BASE = 0, class TR>
+__device__ __forceinline__ void load_twiddles(TwPlain<N, P, TR>& tr, int t, const typename Cplx<TR>::Q* __restrict__ tw) {
+  using Q = typename Cplx<TR>::Q;
   constexpr int T = N / P;
   constexpr int REM = N / L;
   constexpr int R = REM >= P ? P : REM;
@@ -261,11 +314,11 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N, P>& tr, int t, const fl
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       // byte offset of root s r TW_STRIDE, 32-bit from the uniform table base
-      const uint32_t o = static_cast<uint32_t>((t + T * u) & (L - 1)) * (16u * TW_STRIDE);
+      const uint32_t o = static_cast<uint32_t>((t + T * u) & (L - 1)) * (uint32_t(sizeof(Q)) * TW_STRIDE);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float4 w = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(tw) + o * r);
-        tr.cs[BASE + u * (R - 1) + (r - 1)] = make_float2(w.x, w.y);
+        const Q w = *reinterpret_cast<const Q*>(reinterpret_cast<const char*>(tw) + o * r);
+        tr.cs[BASE + u * (R - 1) + (r - 1)] = mk2(w.x, w.y);
         tr.eta[BASE + u * (R - 1) + (r - 1)] = w.z;
       }
     }
@@ -277,13 +330,13 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N, P>& tr, int t, const fl
 }
 
 // forward stage (plain roots)
-template <int N, int P, int R, int L, bool LAST, int BASE>
-__device__ __forceinline__ void pf_stage(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
+template <int N, int P, int R, int L, bool LAST, int BASE, class C, class TR>
+__device__ __forceinline__ void pf_stage(C (&v)[P], const LdsView<C>& lds, int t, const TwPlain<N, P, TR>& tr) {
   constexpr int T = N / P;
   constexpr int U = P / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    float2 a[R];
+    C a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + U * r];
     const int b = t + T * u;
@@ -291,7 +344,7 @@ __device__ __forceinline__ void pf_stage(float2 (&v)[P], const LdsView<float2>& 
     if constexpr (L > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float2 w = tr.cs[BASE + u * (R - 1) + (r - 1)];
+        const C w = tr.cs[BASE + u * (R - 1) + (r - 1)];
         a[r] = pf_cmul(a[r], w.x, w.y);
       }
     }
@@ -308,8 +361,8 @@ __device__ __forceinline__ void pf_stage(float2 (&v)[P], const LdsView<float2>& 
 }
 
 // Forward length-N transform (positions t + T*m in and out), plain roots.
-template <int N, int L = 1, int BASE = 0, int P>
-__device__ __forceinline__ void fwd_pass(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
+template <int N, int L = 1, int BASE = 0, int P, class C, class TR>
+__device__ __forceinline__ void fwd_pass(C (&v)[P], const LdsView<C>& lds, int t, const TwPlain<N, P, TR>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= P ? P : REM;
   constexpr bool LAST = (R == REM);
@@ -327,13 +380,13 @@ __device__ __forceinline__ void fwd_pass(float2 (&v)[P], const LdsView<float2>& 
 
 // Inverse stage: the forward stage's outputs (from LDS, or the registers for the last stage)
 // through the exact inverse butterfly and inverse roots, into registers {u + U r}.
-template <int N, int P, int R, int L, bool LAST, int BASE>
-__device__ __forceinline__ void pi_stage(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
+template <int N, int P, int R, int L, bool LAST, int BASE, class C, class TR>
+__device__ __forceinline__ void pi_stage(C (&v)[P], const LdsView<C>& lds, int t, const TwPlain<N, P, TR>& tr) {
   constexpr int T = N / P;
   constexpr int U = P / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    float2 a[R];
+    C a[R];
     const int b = t + T * u;
     const int s = b & (L - 1);
     if constexpr (LAST) {
@@ -348,8 +401,8 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[P], const LdsView<float2>& 
     if constexpr (L > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const float2 w = tr.cs[BASE + u * (R - 1) + (r - 1)];
-        const float eta = tr.eta[BASE + u * (R - 1) + (r - 1)];
+        const C w = tr.cs[BASE + u * (R - 1) + (r - 1)];
+        const TR eta = tr.eta[BASE + u * (R - 1) + (r - 1)];
         a[r] = pi_cmul(a[r], w.x, w.y, w.x * eta, w.y * eta);
       }
     }
@@ -360,8 +413,8 @@ __device__ __forceinline__ void pi_stage(float2 (&v)[P], const LdsView<float2>& 
 
 // Exact inverse of fwd_pass, times N: the stages undone in reverse order.  All threads of the
 // workgroup call it; on return every LDS read is complete.
-template <int N, int L = 1, int BASE = 0, int P>
-__device__ __forceinline__ void inv_pass(float2 (&v)[P], const LdsView<float2>& lds, int t, const TwPlain<N, P>& tr) {
+template <int N, int L = 1, int BASE = 0, int P, class C, class TR>
+__device__ __forceinline__ void inv_pass(C (&v)[P], const LdsView<C>& lds, int t, const TwPlain<N, P, TR>& tr) {
   constexpr int REM = N / L;
   constexpr int R = REM >= P ? P : REM;
   constexpr bool LAST = (R == REM);
@@ -388,6 +441,12 @@ __device__ __forceinline__ float pair_swap(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float2 pair_swap(float2 x) { return make_float2(pair_swap(x.x), pair_swap(x.y)); }
+__device__ __forceinline__ double pair_swap(double x) {
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0xB1, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double2 pair_swap(double2 x) { return make_double2(pair_swap(x.x), pair_swap(x.y)); }
 
 // ---------------------------------------------------------------------------------------------
 // (cos(phi) - 1, sin(phi)) with relative accuracy on both parts for small |phi|, and
@@ -451,6 +510,21 @@ __device__ __forceinline__ SinCosM1 sincos_m1_t(float phi) {
   else return sincos_m1_reduced(phi);
 }
 constexpr float kSmallPhase = 0.785398163f;   // pi/4
+
+// fp64: (cos(phi) - 1, sin(phi), sin(phi)/phi) from the fp64 library, cos - 1 as -2 sin^2(phi/2)
+// (relative accuracy for small phi); one routine for every phi, so SMALL makes no difference.
+struct SinCosM1d {
+  double cm1, s, sinc;
+};
+template <bool SMALL>
+__device__ __forceinline__ SinCosM1d sincos_m1_t(double phi) {
+  SinCosM1d out;
+  const double h = sin(0.5 * phi);
+  out.s = sin(phi);
+  out.cm1 = -2.0 * h * h;
+  out.sinc = phi != 0.0 ? out.s / phi : 1.0;
+  return out;
+}
 
 // True in every lane iff p holds in every active lane of the wave (a wave-uniform value).
 __device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }

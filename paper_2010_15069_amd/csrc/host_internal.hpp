@@ -42,6 +42,17 @@ struct sgpe_ctx {
   int row_points = 16;      // points per lane of the x transforms
   int col_points = 16;      // points per lane of the y transforms
   int n_cu = 1;             // compute units of the device
+  // complex128 contexts (prec == SGPE_C128): the state and the step tables in fp64; psi, the fp32
+  // tables and the schedule fields above are then unused (16 points per lane, no prefetch)
+  int prec = 0;             // sgpe_precision
+  double4* psi64 = nullptr;
+  double4* twp64_x = nullptr;
+  double4* twp64_y = nullptr;
+  double4* kx64[4] = {nullptr, nullptr, nullptr, nullptr};
+  double2* ky64[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* hbx64 = nullptr;  // dt * Omega_x(x_j) / 2
+  double* hby64 = nullptr;  // dt * Omega_y(y_i) / 2
+  double4* scratch_q64 = nullptr;  // staging of complex128 inputs (annealing noise)
   bool full2x2 = false;
   int split_order = 0;      // sgpe_split_order
   int split_rs = 0;         // sgpe_real_space_split

@@ -94,15 +94,20 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   __shared__ double red[64];
   const int n = a.nx, log2n = __builtin_ctz(a.nx);
   const int row = blockIdx.x;
-  const float4* __restrict__ p = a.psi + size_t(row) * n;
   const double y = a.ymin + a.dy * row;
   const double om_row = a.om_y ? a.om_y[row] : 0.0;
   double er = 0.0, ei = 0.0, nr = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const float4 v = p[j];
+    double ur, ui, dr, di;
+    if (a.psi64) {
+      const double4 v = a.psi64[size_t(row) * n + j];
+      ur = v.x, ui = v.y, dr = v.z, di = v.w;
+    } else {
+      const float4 v = a.psi[size_t(row) * n + j];
+      ur = v.x, ui = v.y, dr = v.z, di = v.w;
+    }
     const double x = a.xmin + a.dx * j;
     const double V = a.wx2h * x * x + a.wy2h * y * y;
-    const double ur = v.x, ui = v.y, dr = v.z, di = v.w;
     const double nu = ur * ur + ui * ui, nd = dr * dr + di * di;
     const double om = a.om_x ? a.om_x[j] + om_row : 0.0;
     er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (ur * dr + ui * di);
@@ -161,12 +166,13 @@ __global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
 // -------------------------------------------------------------------------------------------
 // Norm: sum |psi|^2 with a fixed grid (deterministic), fp64.
 // -------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) norm_kernel(const float4* __restrict__ psi, long long n,
+template <class Q>
+__global__ void __launch_bounds__(256) norm_kernel(const Q* __restrict__ psi, long long n,
                                                    double* __restrict__ partials) {
   __shared__ double red[64];
   double acc = 0.0;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
-    const float4 w = psi[i];
+    const Q w = psi[i];
     const double ur = w.x, ui = w.y, dr = w.z, di = w.w;
     acc += ur * ur + ui * ui + dr * dr + di * di;
   }
@@ -185,7 +191,12 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(norm_kernel, dim3(nblocks), dim3(256), 0, s, psi, npts, partials);
+  hipLaunchKernelGGL(norm_kernel<float4>, dim3(nblocks), dim3(256), 0, s, psi, npts, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(norm_kernel<double4>, dim3(nblocks), dim3(256), 0, s, psi, npts, partials);
   return hipGetLastError();
 }
 

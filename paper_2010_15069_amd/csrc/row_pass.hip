@@ -36,7 +36,8 @@ namespace sgpe {
 // -------------------------------------------------------------------------------------------
 constexpr int kPrefetchPartials = 256;
 
-__device__ __forceinline__ void prefetch_partials(const RowArgs& a, double (&pv)[4]) {
+template <class A>
+__device__ __forceinline__ void prefetch_partials(const A& a, double (&pv)[4]) {
   const int lane = threadIdx.x & 63;
   // a uniform branch around unconditional loads (indices clamped into range; the surplus
   // masked out at the sum), so no lane-dependent control flow waits on a load
@@ -49,7 +50,8 @@ __device__ __forceinline__ void prefetch_partials(const RowArgs& a, double (&pv)
   }
 }
 
-__device__ __forceinline__ float row_scale(const RowArgs& a, const double (&pv)[4]) {
+template <class A>
+__device__ __forceinline__ decltype(A::scale) row_scale(const A& a, const double (&pv)[4]) {
   if (a.partials == nullptr) return a.scale;
   double s = 0.0;
   if (blockDim.x >= 64) {
@@ -66,7 +68,7 @@ __device__ __forceinline__ float row_scale(const RowArgs& a, const double (&pv)[
     for (int i = 0; i < a.n_partials; ++i) s += a.partials[i];
   }
   const double norm = a.parseval_w * s;
-  return static_cast<float>(sqrt(a.norm0 / norm) * a.inv_npts);
+  return static_cast<decltype(A::scale)>(sqrt(a.norm0 / norm) * a.inv_npts);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -74,68 +76,74 @@ __device__ __forceinline__ float row_scale(const RowArgs& a, const double (&pv)[
 // component's row of the 2x2 exponential to its value w; o is the partner lane's value at the
 // same point.  hv = h V(x, y); hbx = h Omega(x, y) / 2 with Omega(x, y) = Omega_x(x) + Omega_y(y).
 // -------------------------------------------------------------------------------------------
+template <class T>
 struct RCoef {
-  float hd_own;      // +- h delta / 2 for this component
-  float hg_own;      // h g_{ss} of this component
-  float hg_ud;       // h g_{up dn}
-  float sgn;         // +1 up, -1 down
-  float hg_uu, hg_dd, hdelta2;
+  T hd_own;          // +- h delta / 2 for this component
+  T hg_own;          // h g_{ss} of this component
+  T hg_ud;           // h g_{up dn}
+  T sgn;             // +1 up, -1 down
+  T hg_uu, hg_dd, hdelta2;
 };
 
 // Diagonal R (no spatial Raman coupling): w exp(-ph) in imaginary time, w exp(-i ph) in real
 // time, with ph = h (V + g_own n_own + g_ud n_other +- delta/2).  The real-time form is
 // w + w (cm1 - i s), the small correction formed first.
-template <bool IMAG, bool SMALL>
-__device__ __forceinline__ float2 apply_r_diag(float2 w, float ph) {
+template <bool IMAG, bool SMALL, class C, class T>
+__device__ __forceinline__ C apply_r_diag(C w, T ph) {
   if constexpr (!IMAG) {
-    const SinCosM1 sc = sincos_m1_t<SMALL>(ph);
-    return make_float2(w.x + fmaf(w.x, sc.cm1, w.y * sc.s), w.y + fmaf(w.y, sc.cm1, -w.x * sc.s));
+    const auto sc = sincos_m1_t<SMALL>(ph);
+    return mk2(w.x + fma_(w.x, sc.cm1, w.y * sc.s), w.y + fma_(w.y, sc.cm1, -w.x * sc.s));
   } else {
-    return vscale(w, expf(-ph));
+    return vscale(w, exp_(-ph));
   }
 }
 
 // Full 2x2 R: H_R = A 1 + Bx sigma_x + Bz sigma_z (all times h).  The angles (A, |B|) of this
 // point, for the wave's choice of routine.
+template <class T>
 struct RFull {
-  float ha, hbz, th;
+  T ha, hbz, th;
 };
-__device__ __forceinline__ RFull r_full_angles(float n_own, float n_oth, float hv, const RCoef& c, float hbx) {
-  const float nu = c.sgn > 0.0f ? n_own : n_oth;
-  const float nd = c.sgn > 0.0f ? n_oth : n_own;
-  const float gu = fmaf(c.hg_uu, nu, c.hg_ud * nd);
-  const float gd = fmaf(c.hg_dd, nd, c.hg_ud * nu);
-  RFull f;
-  f.ha = fmaf(0.5f, gu + gd, hv);
-  f.hbz = fmaf(0.5f, gu - gd, c.hdelta2);
-  f.th = sqrtf(fmaf(hbx, hbx, f.hbz * f.hbz));
+template <class T>
+__device__ __forceinline__ RFull<T> r_full_angles(T n_own, T n_oth, T hv, const RCoef<T>& c, T hbx) {
+  const T nu = c.sgn > T(0) ? n_own : n_oth;
+  const T nd = c.sgn > T(0) ? n_oth : n_own;
+  const T gu = fma_(c.hg_uu, nu, c.hg_ud * nd);
+  const T gd = fma_(c.hg_dd, nd, c.hg_ud * nu);
+  RFull<T> f;
+  f.ha = fma_(T(0.5), gu + gd, hv);
+  f.hbz = fma_(T(0.5), gu - gd, c.hdelta2);
+  f.th = sqrt_(fma_(hbx, hbx, f.hbz * f.hbz));
   return f;
 }
 // Whether the SMALL routines are valid for this point.
-template <bool IMAG>
-__device__ __forceinline__ bool r_full_small(const RFull& f) {
-  if constexpr (!IMAG) return fabsf(f.ha) <= kSmallPhase && f.th <= kSmallPhase;
-  else return f.th < 0.25f;
+template <bool IMAG, class T>
+__device__ __forceinline__ bool r_full_small(const RFull<T>& f) {
+  if constexpr (!IMAG) return fabs_(f.ha) <= T(kSmallPhase) && f.th <= T(kSmallPhase);
+  else return f.th < T(0.25);
 }
 
-template <bool IMAG, bool SMALL>
-__device__ __forceinline__ float2 apply_r_full(float2 w, float2 o, const RFull& f, float hbx, float sgn) {
+template <bool IMAG, bool SMALL, class C, class T>
+__device__ __forceinline__ C apply_r_full(C w, C o, const RFull<T>& f, T hbx, T sgn) {
   if constexpr (!IMAG) {
     // M = cos(th) 1 - i sin(th)/th (hB . sigma): this component's row of (M - 1) psi is
     // cm1 w - i X with X = +-pz w + px o.
-    const SinCosM1 sb = sincos_m1_t<SMALL>(f.th);
-    const float px = sb.sinc * hbx, pz = sgn * sb.sinc * f.hbz;
-    const float xr = fmaf(pz, w.x, px * o.x), xi = fmaf(pz, w.y, px * o.y);
-    const float mr = fmaf(sb.cm1, w.x, xi), mi = fmaf(sb.cm1, w.y, -xr);
+    const auto sb = sincos_m1_t<SMALL>(f.th);
+    const T px = sb.sinc * hbx, pz = sgn * sb.sinc * f.hbz;
+    const T xr = fma_(pz, w.x, px * o.x), xi = fma_(pz, w.y, px * o.y);
+    const T mr = fma_(sb.cm1, w.x, xi), mi = fma_(sb.cm1, w.y, -xr);
     // E M psi - psi = c_M + (E - 1)(w + c_M), E - 1 = cm1_A - i s_A; added to w once.
-    const SinCosM1 se = sincos_m1_t<SMALL>(f.ha);
-    const float cr = fmaf(se.s, w.y, fmaf(se.cm1, w.x, fmaf(se.s, mi, fmaf(se.cm1, mr, mr))));
-    const float ci = fmaf(-se.s, w.x, fmaf(se.cm1, w.y, fmaf(-se.s, mr, fmaf(se.cm1, mi, mi))));
-    return make_float2(w.x + cr, w.y + ci);
+    const auto se = sincos_m1_t<SMALL>(f.ha);
+    const T cr = fma_(se.s, w.y, fma_(se.cm1, w.x, fma_(se.s, mi, fma_(se.cm1, mr, mr))));
+    const T ci = fma_(-se.s, w.x, fma_(se.cm1, w.y, fma_(-se.s, mr, fma_(se.cm1, mi, mi))));
+    return mk2(w.x + cr, w.y + ci);
   } else {
-    const float ea = expf(-f.ha);
-    float ch, shc;  // cosh(th), sinh(th)/th
-    if constexpr (SMALL) {
+    const T ea = exp_(-f.ha);
+    T ch, shc;  // cosh(th), sinh(th)/th
+    if constexpr (sizeof(T) == 8) {
+      ch = cosh(f.th);
+      shc = f.th > 1e-4 ? sinh(f.th) / f.th : fma(f.th * f.th, 1.0 / 6.0, 1.0);   // next term th^4/120
+    } else if constexpr (SMALL) {
       const float t2 = f.th * f.th;
       ch = fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.48015873e-5f, 1.38888889e-3f), 4.16666667e-2f), 0.5f), 1.0f);
       shc = fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.75573192e-6f, 1.98412698e-4f), 8.33333333e-3f),
@@ -153,9 +161,9 @@ __device__ __forceinline__ float2 apply_r_full(float2 w, float2 o, const RFull& 
         shc = 0.5f * (ep - em) / f.th;
       }
     }
-    const float m_own = ea * fmaf(-sgn * shc, f.hbz, ch);
-    const float m_x = -ea * shc * hbx;
-    return make_float2(fmaf(m_own, w.x, m_x * o.x), fmaf(m_own, w.y, m_x * o.y));
+    const T m_own = ea * fma_(-sgn * shc, f.hbz, ch);
+    const T m_x = -ea * shc * hbx;
+    return mk2(fma_(m_own, w.x, m_x * o.x), fma_(m_own, w.y, m_x * o.y));
   }
 }
 
@@ -167,36 +175,36 @@ __device__ __forceinline__ float2 apply_r_full(float2 w, float2 o, const RFull& 
 // branch, so a wave never runs both.
 // hbx_r: this lane's h Omega_x / 2 at its P positions, hb_row: h Omega_y / 2 of the row (full
 // 2x2 variant only; loaded by the caller ahead of the transforms).
-template <int N, bool IMAG, bool FULL, int P>
-__device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, int row, int t, bool up,
-                                            const float (&hbx_r)[P], float hb_row) {
+template <int N, bool IMAG, bool FULL, int P, class C, class R>
+__device__ __forceinline__ void row_apply_r(C (&v)[P], const RowArgsT<R>& a, int row, int t, bool up,
+                                            const R (&hbx_r)[P], R hb_row) {
   constexpr int T = N / P;
-  RCoef c;
-  c.sgn = up ? 1.0f : -1.0f;
+  RCoef<R> c;
+  c.sgn = up ? R(1) : R(-1);
   c.hd_own = up ? a.hdelta2 : -a.hdelta2;
   c.hg_own = up ? a.hg_uu : a.hg_dd;
   c.hg_ud = a.hg_ud;
   c.hg_uu = a.hg_uu;
   c.hg_dd = a.hg_dd;
   c.hdelta2 = a.hdelta2;
-  const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
-  const float hvy = a.hvy * y * y;
+  const R y = fma_(static_cast<R>(row), a.dy, a.y0);
+  const R hvy = a.hvy * y * y;
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     const int j = t + T * m;
-    const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
-    const float hv = fmaf(a.hvx * x, x, hvy);
-    const float n_own = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+    const R x = fma_(static_cast<R>(j), a.dx, a.x0);
+    const R hv = fma_(a.hvx * x, x, hvy);
+    const R n_own = fma_(v[m].x, v[m].x, v[m].y * v[m].y);
     if constexpr (!FULL) {
-      const float n_oth = pair_swap(n_own);
-      const float ph = fmaf(c.hg_own, n_own, fmaf(c.hg_ud, n_oth, hv + c.hd_own));
-      if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) v[m] = apply_r_diag<IMAG, true>(v[m], ph);
+      const R n_oth = pair_swap(n_own);
+      const R ph = fma_(c.hg_own, n_own, fma_(c.hg_ud, n_oth, hv + c.hd_own));
+      if (IMAG || wave_all(fabs_(ph) <= R(kSmallPhase))) v[m] = apply_r_diag<IMAG, true>(v[m], ph);
       else v[m] = apply_r_diag<IMAG, false>(v[m], ph);
     } else {
-      const float hbx = hbx_r[m] + hb_row;
-      const float2 o = pair_swap(v[m]);
-      const float n_oth = fmaf(o.x, o.x, o.y * o.y);
-      const RFull f = r_full_angles(n_own, n_oth, hv, c, hbx);
+      const R hbx = hbx_r[m] + hb_row;
+      const C o = pair_swap(v[m]);
+      const R n_oth = fma_(o.x, o.x, o.y * o.y);
+      const RFull<R> f = r_full_angles(n_own, n_oth, hv, c, hbx);
       if (wave_all(r_full_small<IMAG>(f))) v[m] = apply_r_full<IMAG, true>(v[m], o, f, hbx, c.sgn);
       else v[m] = apply_r_full<IMAG, false>(v[m], o, f, hbx, c.sgn);
     }
@@ -206,44 +214,44 @@ __device__ __forceinline__ void row_apply_r(float2 (&v)[P], const RowArgs& a, in
 // R(h) split to second order as N(h/2) L(h) N(h/2): the mean-field phase with the densities of
 // its input, the exponential of the linear real-space terms (trap, detuning, spatial coupling),
 // the mean-field phase again with the updated densities.  Coefficients as in row_apply_r.
-template <int N, bool IMAG, bool FULL, int P>
-__device__ __forceinline__ void row_apply_r_nln(float2 (&v)[P], const RowArgs& a, int row, int t, bool up,
-                                                const float (&hbx_r)[P], float hb_row) {
+template <int N, bool IMAG, bool FULL, int P, class C, class R>
+__device__ __forceinline__ void row_apply_r_nln(C (&v)[P], const RowArgsT<R>& a, int row, int t, bool up,
+                                                const R (&hbx_r)[P], R hb_row) {
   constexpr int T = N / P;
-  RCoef c;
-  c.sgn = up ? 1.0f : -1.0f;
+  RCoef<R> c;
+  c.sgn = up ? R(1) : R(-1);
   c.hd_own = up ? a.hdelta2 : -a.hdelta2;
   c.hg_own = up ? a.hg_uu : a.hg_dd;
   c.hg_ud = a.hg_ud;
   c.hg_uu = a.hg_uu;
   c.hg_dd = a.hg_dd;
   c.hdelta2 = a.hdelta2;
-  const float y = fmaf(static_cast<float>(row), a.dy, a.y0);
-  const float hvy = a.hvy * y * y;
-  auto half_n = [&](float2 w) {
-    const float n_own = fmaf(w.x, w.x, w.y * w.y);
-    const float n_oth = pair_swap(n_own);
-    const float ph = 0.5f * fmaf(c.hg_own, n_own, c.hg_ud * n_oth);
-    if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) return apply_r_diag<IMAG, true>(w, ph);
+  const R y = fma_(static_cast<R>(row), a.dy, a.y0);
+  const R hvy = a.hvy * y * y;
+  auto half_n = [&](C w) {
+    const R n_own = fma_(w.x, w.x, w.y * w.y);
+    const R n_oth = pair_swap(n_own);
+    const R ph = R(0.5) * fma_(c.hg_own, n_own, c.hg_ud * n_oth);
+    if (IMAG || wave_all(fabs_(ph) <= R(kSmallPhase))) return apply_r_diag<IMAG, true>(w, ph);
     return apply_r_diag<IMAG, false>(w, ph);
   };
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     const int j = t + T * m;
-    const float x = fmaf(static_cast<float>(j), a.dx, a.x0);
-    const float hv = fmaf(a.hvx * x, x, hvy);
-    float2 w = half_n(v[m]);
+    const R x = fma_(static_cast<R>(j), a.dx, a.x0);
+    const R hv = fma_(a.hvx * x, x, hvy);
+    C w = half_n(v[m]);
     if constexpr (!FULL) {
-      const float ph = hv + c.hd_own;
-      if (IMAG || wave_all(fabsf(ph) <= kSmallPhase)) w = apply_r_diag<IMAG, true>(w, ph);
+      const R ph = hv + c.hd_own;
+      if (IMAG || wave_all(fabs_(ph) <= R(kSmallPhase))) w = apply_r_diag<IMAG, true>(w, ph);
       else w = apply_r_diag<IMAG, false>(w, ph);
     } else {
-      const float hbx = hbx_r[m] + hb_row;
-      const float2 o = pair_swap(w);
-      RFull f;
+      const R hbx = hbx_r[m] + hb_row;
+      const C o = pair_swap(w);
+      RFull<R> f;
       f.ha = hv;
       f.hbz = c.hdelta2;
-      f.th = sqrtf(fmaf(hbx, hbx, f.hbz * f.hbz));
+      f.th = sqrt_(fma_(hbx, hbx, f.hbz * f.hbz));
       if (wave_all(r_full_small<IMAG>(f))) w = apply_r_full<IMAG, true>(w, o, f, hbx, c.sgn);
       else w = apply_r_full<IMAG, false>(w, o, f, hbx, c.sgn);
     }
@@ -254,29 +262,34 @@ __device__ __forceinline__ void row_apply_r_nln(float2 (&v)[P], const RowArgs& a
 // A workgroup handles ITERS groups of rows_per_block rows, one after the other; the next group's
 // data is loaded into registers before the current group is transformed, so its memory latency
 // hides behind this group's arithmetic.  P points per lane: T = N / P lanes per transform.
-template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
-__device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
-  extern __shared__ float2 lds_raw[];
+// The kernels' dynamic LDS, typed per precision where it is used.
+extern __shared__ __align__(16) unsigned char row_lds[];
+
+template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P, class R>
+__device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
+  using C = cplx_t<R>;
+  C* const lds_raw = reinterpret_cast<C*>(row_lds);
   constexpr int T = N / P;
   constexpr int SLOTS = N + N / 16;
+  constexpr uint32_t PB = sizeof(point_t<R>), CB = sizeof(C);   // bytes per point / component
   const int tid = threadIdx.x;
   const int comp = tid & 1;
   const int pair = tid >> 1;
   const int rloc = pair / T;
   const int t = pair - rloc * T;
   const int row0 = wg * ITERS * a.rows_per_block + rloc;
-  const LdsView<float2> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
-  // element `pos` of this lane's component is at byte offset 16 pos from the row start; 32-bit
+  const LdsView<C> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
+  // element `pos` of this lane's component is at byte offset PB pos from the row start; 32-bit
   // offsets from a wave-uniform base
   const char* __restrict__ base = reinterpret_cast<const char*>(a.psi);
   char* __restrict__ out = reinterpret_cast<char*>(a.psi);
-  const uint32_t lane_off = static_cast<uint32_t>(t) * 16u + 8u * comp;
-  const uint32_t group_stride = static_cast<uint32_t>(a.rows_per_block) * (16u * N);
+  const uint32_t lane_off = static_cast<uint32_t>(t) * PB + CB * comp;
+  const uint32_t group_stride = static_cast<uint32_t>(a.rows_per_block) * (PB * N);
 
   double pv[4];
   if constexpr (MODE != ROW_FWD) prefetch_partials(a, pv);
-  float2 v[P], nxt[P];
-  uint32_t off = static_cast<uint32_t>(row0) * (16u * N) + lane_off;
+  C v[P], nxt[P];
+  uint32_t off = static_cast<uint32_t>(row0) * (PB * N) + lane_off;
   // Load order: the inverse transform starts with the last forward stage, whose butterfly u
   // takes positions u + U k; issuing those loads together lets it start before the rest land.
   constexpr int RL = MODE == ROW_FWD ? P : last_radix<N, P>();
@@ -284,19 +297,19 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int m = i / RL + UL * (i % RL);
-    v[m] = *reinterpret_cast<const float2*>(base + (off + 16u * T * m));
+    v[m] = *reinterpret_cast<const C*>(base + (off + PB * T * m));
   }
-  TwPlain<N, P> tr;
+  TwPlain<N, P, R> tr;
   load_twiddles<N>(tr, t, a.tw);
   // spatial Raman tables: the x part is the same for every row of the workgroup
-  float hbx_r[P], hby_r[ITERS];
+  R hbx_r[P], hby_r[ITERS];
   if constexpr (FULL && MODE == ROW_STEP) {
 #pragma unroll
     for (int m = 0; m < P; ++m) hbx_r[m] = a.hbx[t + T * m];
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) hby_r[it] = a.hby[row0 + it * a.rows_per_block];
   }
-  float s = 1.0f;
+  R s = R(1);
 
 #pragma unroll
   for (int it = 0; it < ITERS; ++it) {
@@ -304,7 +317,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const int m = i / RL + UL * (i % RL);
-        nxt[m] = *reinterpret_cast<const float2*>(base + (off + group_stride + 16u * T * m));
+        nxt[m] = *reinterpret_cast<const C*>(base + (off + group_stride + PB * T * m));
       }
     }
     if constexpr (MODE == ROW_FWD) {
@@ -316,12 +329,12 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
       for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
       if constexpr (MODE == ROW_STEP) {
         row_apply_r<N, IMAG, FULL>(v, a, row0 + it * a.rows_per_block, t, comp == 0, hbx_r,
-                                   FULL ? hby_r[it] : 0.0f);
+                                   FULL ? hby_r[it] : R(0));
         fwd_pass<N>(v, lds, t, tr);
       }
     }
 #pragma unroll
-    for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + (off + 16u * T * m)) = v[m];
+    for (int m = 0; m < P; ++m) *reinterpret_cast<C*>(out + (off + PB * T * m)) = v[m];
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = nxt[m];
@@ -333,7 +346,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int wg) {
 // The general row pass of the splitting variants (one row group per workgroup); see RowVarFlags.
 template <int N, bool IMAG, bool FULL, int P>
 __device__ __forceinline__ void row_var_body(const RowArgs& a, int wg) {
-  extern __shared__ float2 lds_raw[];
+  float2* const lds_raw = reinterpret_cast<float2*>(row_lds);
   __shared__ double red[64];
   constexpr int T = N / P;
   constexpr int SLOTS = N + N / 16;
@@ -397,6 +410,13 @@ __global__ void __launch_bounds__(2 * N / P > 256 ? 512 : 256) row_var_kernel(Ro
 template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
 __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) {
   row_body<N, MODE, IMAG, FULL, ITERS, P>(a, blockIdx.x);
+}
+
+// complex128: 16 points per lane, one row group per workgroup; row groups are sized for 256
+// threads except at N = 4096 (512)
+template <int N, int MODE, bool IMAG, bool FULL>
+__global__ void __launch_bounds__(2 * N / 16 > 256 ? 512 : 256) row_kernel_c128(RowArgsT<double> a) {
+  row_body<N, MODE, IMAG, FULL, 1, 16>(a, blockIdx.x);
 }
 
 template <int N, int MODE, bool IMAG, bool FULL, int P>
@@ -473,6 +493,45 @@ static hipError_t row_dispatch(const RowArgs& a, const RowArgs* tab, int count, 
     case 1024: return row_launch_n<1024>(a, tab, count, mode, imag, full, iters, points, s);
     case 2048: return row_launch_n<2048>(a, tab, count, mode, imag, full, iters, points, s);
     case 4096: return row_launch_n<4096>(a, tab, count, mode, imag, full, iters, points, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int MODE, bool IMAG, bool FULL>
+static hipError_t row_launch_c128(const RowArgsT<double>& a, hipStream_t s) {
+  const dim3 block(2 * a.rows_per_block * (N / 16));
+  const dim3 grid(a.ny / a.rows_per_block);
+  if (block.x > (2 * N / 16 > 256 ? 512u : 256u)) return hipErrorInvalidValue;
+  const size_t lds = 2 * row_lds_bytes(N, a.rows_per_block);   // double2 slots
+  hipLaunchKernelGGL((row_kernel_c128<N, MODE, IMAG, FULL>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t row_launch_c128_n(const RowArgsT<double>& a, int mode, bool imag, bool full, hipStream_t s) {
+  switch (mode) {
+    case ROW_FWD: return row_launch_c128<N, ROW_FWD, false, false>(a, s);
+    case ROW_INV: return row_launch_c128<N, ROW_INV, false, false>(a, s);
+    case ROW_STEP:
+      if (imag) return full ? row_launch_c128<N, ROW_STEP, true, true>(a, s) : row_launch_c128<N, ROW_STEP, true, false>(a, s);
+      return full ? row_launch_c128<N, ROW_STEP, false, true>(a, s) : row_launch_c128<N, ROW_STEP, false, false>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_row(const RowArgsT<double>& a, int mode, bool imag, bool full, hipStream_t s) {
+  if (!schedule_supported(a.nx, a.rows_per_block, 1, 16)) return hipErrorInvalidValue;
+  if (a.ny % a.rows_per_block != 0) return hipErrorInvalidValue;
+  switch (a.nx) {
+    case 16: return row_launch_c128_n<16>(a, mode, imag, full, s);
+    case 32: return row_launch_c128_n<32>(a, mode, imag, full, s);
+    case 64: return row_launch_c128_n<64>(a, mode, imag, full, s);
+    case 128: return row_launch_c128_n<128>(a, mode, imag, full, s);
+    case 256: return row_launch_c128_n<256>(a, mode, imag, full, s);
+    case 512: return row_launch_c128_n<512>(a, mode, imag, full, s);
+    case 1024: return row_launch_c128_n<1024>(a, mode, imag, full, s);
+    case 2048: return row_launch_c128_n<2048>(a, mode, imag, full, s);
+    case 4096: return row_launch_c128_n<4096>(a, mode, imag, full, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -6,6 +6,15 @@
 
 namespace sgpe {
 
+// Precision of the step kernels: T = float (complex64 state) or double (complex128).  C is the
+// complex type of one spinor component, Q that of a grid point (both components, the state's
+// element type).
+template <class T> struct Cplx;
+template <> struct Cplx<float> { using C = float2; using Q = float4; };
+template <> struct Cplx<double> { using C = double2; using Q = double4; };
+template <class T> using cplx_t = typename Cplx<T>::C;
+template <class T> using point_t = typename Cplx<T>::Q;
+
 // Row (x) pass modes.
 enum RowMode : int {
   ROW_FWD = 0,   // forward x-FFT only (enter the mixed (k_x, y) representation)
@@ -31,47 +40,52 @@ enum ColNorm : int {
   NORM_SQ = 2,   // |U psik|^2
 };
 
-struct RowArgs {
-  float4* psi;           // [ny][nx] state, in place
+template <class T>
+struct RowArgsT {
+  point_t<T>* psi;       // [ny][nx] state, in place
   int nx, ny;
   int rows_per_block;
-  const float4* tw;      // roots exp(-2 pi i j / nx) as {cos, sin, eta, 0} (fp32-rounded, see fwd_pass)
+  const point_t<T>* tw;  // roots exp(-2 pi i j / nx) as {cos, sin, eta, 0} (rounded to T, see fwd_pass)
   // scale applied after the inverse transform: either `scale`, or computed from partials
-  float scale;
+  T scale;
   const double* partials;  // NULL => use `scale`
   int n_partials;
   double norm0, parseval_w;  // norm = parseval_w * sum(partials)
   double inv_npts;           // 1/(nx*ny)
   // real-space exponential (all pre-multiplied by the sub-step h)
-  float x0, dx, y0, dy;      // x_j = x0 + j dx, y_i = y0 + i dy
-  float hvx, hvy;            // h * wx^2 / 2, h * wy^2 / 2
-  float hdelta2;             // h * delta / 2
-  float hg_uu, hg_dd, hg_ud;
-  const float* hbx;          // h * Omega_x(x_j) / 2, length nx (full 2x2 variant only)
-  const float* hby;          // h * Omega_y(y_i) / 2, length ny (full 2x2 variant only);
+  T x0, dx, y0, dy;          // x_j = x0 + j dx, y_i = y0 + i dy
+  T hvx, hvy;                // h * wx^2 / 2, h * wy^2 / 2
+  T hdelta2;                 // h * delta / 2
+  T hg_uu, hg_dd, hg_ud;
+  const T* hbx;              // h * Omega_x(x_j) / 2, length nx (full 2x2 variant only)
+  const T* hby;              // h * Omega_y(y_i) / 2, length ny (full 2x2 variant only);
                              //   the spatial coupling is Omega_x(x) + Omega_y(y)
   // general row pass (ROW_VAR) only:
   int var_flags;             // RowVarFlags
   int var_r;                 // real-space sub-steps R(h) applied in turn (0, 1 or 2)
   int var_nln;               // 1: each R(h) as N(h/2) L(h) N(h/2)
-  float hfrac;               // h / dt: scales the hbx / hby tables (built for h = dt)
+  T hfrac;                   // h / dt: scales the hbx / hby tables (built for h = dt)
   double* partials_out;      // VAR_NORM_OUT: one double per workgroup
 };
+using RowArgs = RowArgsT<float>;
 
-struct ColArgs {
-  float4* psi;
+template <class T>
+struct ColArgsT {
+  point_t<T>* psi;
   int nx, ny;
   int cols;                  // columns per workgroup
-  const float4* tw;          // roots exp(-2 pi i j / ny) as {cos, sin, eta, 0}
-  const float4* kx_tab;      // per k_x: {d11, d12} {d21, d22} as complex (M'(k_x) - 1)
-  const float2* ky_tab;      // per k_y: P(k_y) - 1
+  const point_t<T>* tw;      // roots exp(-2 pi i j / ny) as {cos, sin, eta, 0}
+  const point_t<T>* kx_tab;  // per k_x: {d11, d12} {d21, d22} as complex (M'(k_x) - 1)
+  const cplx_t<T>* ky_tab;   // per k_y: P(k_y) - 1
   double* partials;          // one double per workgroup (norm modes)
 };
+using ColArgs = ColArgsT<float>;
 
 constexpr int kEnergyRowParts = 3;
 
 struct EnergyArgs {
-  const float4* psi;
+  const float4* psi;         // the complex64 state, or
+  const double4* psi64;      //   the complex128 one (exactly one is set)
   double4* scratch;          // [ny][nx] x-transformed state in fp64 {re_up, im_up, re_dn, im_dn}
   int nx, ny;
   int cols;                  // columns per column-kernel workgroup
@@ -106,6 +120,9 @@ inline bool schedule_supported(int n, int groups, int iters, int points) {
 
 hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full2x2, int iters, int points, hipStream_t s);
 hipError_t launch_col(const ColArgs& a, int norm_mode, int iters, int points, hipStream_t s);
+// complex128: 16 points per lane, one row group / column tile per workgroup, the step modes only
+hipError_t launch_row(const RowArgsT<double>& a, int mode, bool imag, bool full2x2, hipStream_t s);
+hipError_t launch_col(const ColArgsT<double>& a, int norm_mode, hipStream_t s);
 // Batches of instances of one grid shape: `shape` gives the geometry (every table entry must
 // share nx, ny, rows_per_block / cols); instance i's arguments are tab[i] (device memory), and
 // it is blockIdx.y = i of one launch.  One row group / column tile per workgroup.
@@ -115,20 +132,27 @@ hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count,
                             hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+hipError_t launch_norm(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 
 // Observables and state updates (observables.hip).  Grid-stride reductions write one partial (or
 // `kMomentParts` partials) per block, summed on the host in block order.
 constexpr int kMomentParts = 3;
 // psi += amp * xi, both components (xi in the state's layout).
 hipError_t launch_add_noise(float4* psi, const float4* xi, float amp, long long npts, hipStream_t s);
+hipError_t launch_add_noise(double4* psi, const double4* xi, double amp, long long npts, hipStream_t s);
 // per block: sum n_u n_d, sum n_u^2, sum n_d^2
 hipError_t launch_moments(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+hipError_t launch_moments(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 // per block: sum of n_u + n_d over the points with x^2 + y^2 <= r2
 hipError_t launch_disk_population(const float4* psi, int nx, int ny, double x0, double dx, double y0, double dy,
+                                  double r2, double* partials, int nblocks, hipStream_t s);
+hipError_t launch_disk_population(const double4* psi, int nx, int ny, double x0, double dx, double y0, double dy,
                                   double r2, double* partials, int nblocks, hipStream_t s);
 // Phase increments of both components along the closed lattice path of `m` samples of the circle
 // of this radius about the origin; out[c] = (sum of increments) / (2 pi).  One workgroup.
 hipError_t launch_winding(const float4* psi, int nx, int ny, double xmax, double ymax, double radius, int m,
+                          double* out, hipStream_t s);
+hipError_t launch_winding(const double4* psi, int nx, int ny, double xmax, double ymax, double radius, int m,
                           double* out, hipStream_t s);
 
 // Workgroup geometry helpers (shared with the host so that partial counts match).

@@ -15,19 +15,26 @@ class Solver:
     ``params``: any object (or dict) with the fields of ``workloads.Params`` / ``sgpe_params``.
     ``stream``: a raw hipStream_t handle (int) or None for the null stream; e.g.
     ``torch.cuda.current_stream().cuda_stream``.
-    ``psi_dev``: optional device pointer (int) of >= 16*nx*ny bytes that the context borrows,
-    e.g. ``t.data_ptr()`` of a torch float32 tensor of shape (ny, nx, 4).
+    ``psi_dev``: optional device pointer (int) of >= 16*nx*ny bytes (32*nx*ny for complex128) that
+    the context borrows, e.g. ``t.data_ptr()`` of a torch float32 tensor of shape (ny, nx, 4).
+    ``precision``: "c64" (complex64 state, fp32 kernels) or "c128" (complex128, fp64 kernels).
     """
 
-    def __init__(self, params, stream=None, psi_dev=None):
+    PRECISIONS = {"c64": 0, "c128": 1}
+
+    def __init__(self, params, stream=None, psi_dev=None, precision="c64"):
         self._lib = lib()
         self.params = params
         self._cp = SgpeParams.from_obj(params)
         self.nx, self.ny = int(self._cp.nx), int(self._cp.ny)
+        if precision not in self.PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(self.PRECISIONS)}")
+        self.precision = precision
         self._ctx = ctypes.c_void_p()
-        check(self._lib.sgpe_create(ctypes.byref(self._cp), ctypes.c_void_p(stream or 0),
-                                    ctypes.c_void_p(psi_dev or 0), ctypes.byref(self._ctx)),
-              "sgpe_create")
+        check(self._lib.sgpe_create_ex(ctypes.byref(self._cp), self.PRECISIONS[precision],
+                                       ctypes.c_void_p(stream or 0), ctypes.c_void_p(psi_dev or 0),
+                                       ctypes.byref(self._ctx)),
+              "sgpe_create_ex")
 
     # -- lifetime --------------------------------------------------------------------------
     def close(self):

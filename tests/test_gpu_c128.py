@@ -1,0 +1,158 @@
+"""GPU parity of the complex128 instantiation of the step kernels (precision as a template
+parameter of the same kernels) against the FP64 oracle, through the C ABI.
+
+Both sides compute in fp64, so the bar is rounding: psi relative L2 <= 1e-12 and energies within
+1e-11 (the two FFT algorithms round differently; measured after hundreds of steps: 2e-14 to 7e-14).  Cases: the tiny workload as written (64^2, complex128, imaginary then real time), the
+512^2 real-time physics, the spatial Raman full 2x2 exponential, ragged and extreme shapes, the
+full 1024^2 grid, unitarity, observables, and the error paths of the fixed complex128 schedule."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleGPE
+from workloads import Params, complex_noise, initial_state, preset, spin_hall_params, spin_hall_profile, vortex_state
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    from paper_2010_15069_amd import Solver, device_count
+    if device_count() <= 0:
+        pytest.skip("no HIP device")
+    return Solver
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def pair(Solver, p, psi0):
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_psi(psi0)
+    s = Solver(p, precision="c128")
+    s.set_psi(psi0)
+    return o, s
+
+
+def check(o, s, tol=1e-12, e_tol=1e-11):
+    err = rel_l2(s.get_psi(), o.psi)
+    assert err <= tol, f"psi rel L2 {err:.3e} > {tol:.0e}"
+    eo, eg = o.energy(), s.energy()
+    assert abs(eg - eo) <= e_tol * abs(eo), (eg, eo)
+    no, ng = o.norm(), s.norm()
+    assert abs(ng - no) <= 1e-12 * no, (ng, no)
+    print(f"psi rel L2 {err:.2e}")
+
+
+def test_tiny_as_written_complex128(Solver):
+    p = preset("tiny")
+    psi0 = initial_state(p, "gauss", seed=0)
+    o, s = pair(Solver, p, psi0)
+    o.step_imag(200)
+    s.step_imag(200)
+    check(o, s)
+    o.step_real(200)
+    s.step_real(200)
+    check(o, s)
+
+
+def test_state_round_trip_is_exact(Solver):
+    p = preset("tiny")
+    psi0 = initial_state(p, "gauss", seed=1) * (1 + 1e-9j)   # values not representable in complex64
+    s = Solver(p, precision="c128").set_psi(psi0)
+    assert np.array_equal(s.get_psi(), psi0)
+
+
+def test_realtime_512(Solver):
+    p = preset("realtime_512")
+    o, s = pair(Solver, p, initial_state(p, "tf", seed=0))
+    o.step_real(200)
+    s.step_real(200)
+    check(o, s)
+
+
+@pytest.mark.parametrize("kind", ["imag", "real"])
+def test_spatial_raman_full_2x2(Solver, kind):
+    p = preset("ground_2048", nx=128, ny=128)
+    o, s = pair(Solver, p, initial_state(p, "tf", seed=2))
+    getattr(o, f"step_{kind}")(300)
+    getattr(s, f"step_{kind}")(300)
+    check(o, s)
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 256), (256, 32), (2048, 16), (16, 2048), (4096, 16), (128, 512)])
+def test_ragged_shapes(Solver, nx, ny):
+    p = Params(nx=nx, ny=ny, xmax=8.0, ymax=6.0, g_uu=3.0, g_dd=4.0, g_ud=2.0, k_l=1.3, omega=0.7, delta=0.2,
+               dt=1e-3)
+    o, s = pair(Solver, p, initial_state(p, "tf", seed=3))
+    o.step_imag(50)
+    s.step_imag(50)
+    o.step_real(50)
+    s.step_real(50)
+    check(o, s)
+
+
+def test_full_size_1024(Solver):
+    p = preset("metric_1024")
+    o, s = pair(Solver, p, initial_state(p, "tf", seed=0))
+    o.step_real(5)
+    s.step_real(5)
+    check(o, s)
+    o.step_imag(5)
+    s.step_imag(5)
+    check(o, s)
+
+
+def test_unitarity_1000_real_steps(Solver):
+    p = preset("tiny")
+    s = Solver(p, precision="c128").set_psi(initial_state(p, "gauss", seed=0))
+    n0 = s.norm()
+    s.step_real(1000)
+    assert abs(s.norm() - n0) <= 1e-12 * n0
+
+
+def test_observables_and_annealing(Solver):
+    p = spin_hall_params(n=128, ratio=0.3)
+    psi0 = vortex_state(p, n_vortices=5, seed=2)
+    o = OracleGPE(p, workers=WORKERS)
+    o.set_raman_profile(None, spin_hall_profile(p))
+    o.set_psi(psi0)
+    s = Solver(p, precision="c128").set_raman_profile(omega_y=spin_hall_profile(p)).set_psi(psi0)
+    xi = complex_noise(p, seed=[2, 0])
+    o.add_noise(xi, 1e-3)
+    s.add_noise(xi, 1e-3)
+    o.step_imag(100)
+    s.step_imag(100)
+    check(o, s)
+    psi = s.get_psi()
+    assert abs(s.phase_separation() - oracle.phase_separation(psi)) <= 1e-12
+    r = s.population_radius(0.99)
+    assert abs(r - oracle.population_radius(psi, p.xmax, p.ymax, 0.99)) <= 1e-9 * r
+    (nu, nd), _ = oracle.winding(psi, p.xmax, p.ymax, r)
+    assert s.winding(r)[:2] == (nu, nd)
+
+
+def test_fixed_schedule_and_limits(Solver):
+    from paper_2010_15069_amd import SgpeError
+    from paper_2010_15069_amd._lib import lib
+    p = preset("tiny")
+    s = Solver(p, precision="c128").set_psi(initial_state(p, "gauss", seed=0))
+    assert s.get_schedule()["row_points"] == 16 and s.get_schedule()["row_iters"] == 1
+    with pytest.raises(SgpeError, match="SGPE_EINVAL"):
+        s.set_schedule(col_tile=1)
+    with pytest.raises(SgpeError, match="SGPE_EINVAL"):
+        s.set_col_tile(2)
+    with pytest.raises(SgpeError, match="SGPE_EINVAL"):
+        s.set_splitting("rkr", "frozen")
+    with pytest.raises(SgpeError, match="SGPE_ESTATE"):
+        s.profile_steps(5)
+    with pytest.raises(ValueError):
+        Solver(p, precision="c256")
+    # complex128 columns of 4096 points do not fit the LDS: reported, not attempted
+    with pytest.raises(SgpeError, match="SGPE_ENOMEM"):
+        Solver(Params(nx=16, ny=4096), precision="c128")
