@@ -35,6 +35,14 @@ BYTES_PER_POINT_STEP = 64      # two passes per step
 IMAG_DT = 1e-3                 # imaginary-time step of the throughput workload
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg} ({time.perf_counter() - _T0:.0f} s)", file=sys.stderr, flush=True)
+
+
 def median_mad(xs):
     import numpy as np
     a = np.asarray(xs, dtype=float)
@@ -325,6 +333,22 @@ def splitting_variants(torch, stream, timed, p, p_imag, psi0, steps=600, warmup=
     return out
 
 
+def complex128_rates(torch, stream, timed, p, p_imag, psi0, steps=300, warmup=20):
+    """Throughput of the complex128 instantiation on the headline workload (1024^2)."""
+    from paper_2010_15069_amd import Solver
+    res = {}
+    for kind, pp in (("imag", p_imag), ("real", p)):
+        s = Solver(pp, stream=stream.cuda_stream, precision="c128").set_psi(psi0)
+        step = s.step_imag if kind == "imag" else s.step_real
+        step(warmup)
+        total_ms, _ = timed(step, steps, 100)
+        res[f"split_steps_per_s_{kind}"] = steps / (total_ms * 1e-3)
+        s.close()
+    res["hbm_roofline_frac_imag"] = 128 * p.nx * p.ny * res["split_steps_per_s_imag"] / (HBM_PEAK_GBS * 1e9)
+    res["note"] = "complex128 state: 32 B per point per sweep, 128 B per point per step"
+    return res
+
+
 def spin_hall_trial(torch):
     """One spin-Hall trial (Sec. 6) at 1024^2: vortex-seeded start, 60000 annealed and 60000
     plain imaginary-time steps with the Raman profile Omega(y), then the observables."""
@@ -411,6 +435,7 @@ def main():
     value = args.steps / (total_ms * 1e-3)
     e_final = s.energy()
 
+    progress("imaginary-time 1024^2 timed")
     # real time, same workload
     s_real.set_psi(psi0)
     s_real.step_real(args.warmup)
@@ -470,11 +495,15 @@ def main():
                      "launch_ms": dom_ms},
     }
     s.close()
+    progress("real-time 1024^2 and per-pass timing")
     if not args.no_other_grids:
         out["other_grids"] = other_grids(torch, stream, timed, p)
         out["splitting_variants"] = splitting_variants(torch, stream, timed, p, p_imag, psi0)
+        out["complex128"] = complex128_rates(torch, stream, timed, p, p_imag, psi0)
+        progress("other grids, splitting variants, complex128")
     if not args.no_ground:
         out["ground_state"] = ground_state_time(torch, stream)
+        progress("ground state 256^2")
         if args.ground_2048:
             out["ground_2048"] = ground_2048_convergence(torch, stream, max_steps=args.ground_2048)
         model = _load_surrogate(torch)
@@ -483,12 +512,16 @@ def main():
             if not args.no_batch:
                 out["learned_start_sweep"] = learned_start_sweep(torch, stream, model)
             del model
+            progress("learned start")
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(torch, stream)
+        progress("batched sweep")
     if not args.no_spin_hall:
         out["spin_hall_trial"] = spin_hall_trial(torch)
+        progress("spin-Hall trial")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, psi0, args.cpu_seconds, args.cpu_single_seconds)
+        progress("oracle CPU baseline")
     print(json.dumps(out), flush=True)
 
 
