@@ -50,16 +50,18 @@ def median_mad(xs):
     return med, float(np.median(np.abs(a - med)))
 
 
-def _traffic_record(kernel_name, workload):
+def _traffic_record(kernel_name, workload, schedule):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source (matched by source hash); else None."""
+    current step kernels (matched by the kernel-source hash) with the same launch schedule; else
+    None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        from paper_2010_15069_amd.build import source_hash
-        if rec.get("source_hash") != source_hash() or rec.get("workload") != workload:
+        from paper_2010_15069_amd.build import kernel_hash
+        if (rec.get("kernel_hash") != kernel_hash() or rec.get("workload") != workload
+                or rec.get("schedule") != schedule):
             return None
         return rec.get("kernels", {}).get(kernel_name)
     except Exception:
@@ -456,7 +458,7 @@ def main():
     dom_name, dom_ms = ("col_pass", col_ms) if col_ms >= row_ms else ("row_pass", row_ms)
     alg_bytes = BYTES_PER_POINT_PASS * npts
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = _traffic_record(dom_name, args.workload)
+    traffic = _traffic_record(dom_name, args.workload, s.get_schedule())
 
     out = {
         "metric": "split-steps/s at 1024^2x2 c64 (%HBM roofline); ground-state time-to-1e-6 E",

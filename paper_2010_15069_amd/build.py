@@ -48,6 +48,21 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# The sources the step kernels compile from (with the device compile flags): a record measured on
+# these kernels stays valid while this hash is unchanged, whatever happens to the host library.
+KERNEL_SOURCES = ("row_pass.hip", "col_pass.hip", "fft_device.hpp", "sgpe_internal.hpp")
+
+
+def kernel_hash() -> str:
+    """Short hash of the step kernels' sources and device compile flags."""
+    h = hashlib.sha256(" ".join(HIP_FLAGS).encode())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _torch_lib_dir():
     spec = importlib.util.find_spec("torch")
     if spec is None or not spec.submodule_search_locations:
@@ -79,7 +94,7 @@ def build(verbose: bool = False) -> str:
         for src in ("row_pass.hip", "col_pass.hip", "reductions.hip", "observables.hip"):
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             jobs.append(([hipcc, "-c"] + HIP_FLAGS + incs + [os.path.join(CSRC, src), "-o", obj], obj))
-        for src in ("api.cpp", "batch.cpp"):
+        for src in ("api.cpp", "batch.cpp", "observables_api.cpp"):
             obj = os.path.join(tmp, src.replace(".cpp", ".o"))
             jobs.append(([hipcc, "-c", "-x", "c++"] + HOST_FLAGS + incs +
                          [os.path.join(CSRC, src), "-o", obj], obj))

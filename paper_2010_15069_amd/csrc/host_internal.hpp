@@ -76,6 +76,9 @@ sgpe_schedule get_schedule(const sgpe_ctx* c);
 sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
+// Spatial Raman coupling tables Omega_x(x_j) + Omega_y(y_i) (NULL = zero profile), allocated on first
+// use; waits for the stream's queued work before overwriting them.
+sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y);
 sgpe_status sync_and_latch(sgpe_ctx* c);
 
 }  // namespace sgpe_host

@@ -7,7 +7,6 @@
 
 namespace sgpe {
 
-// psi <- psi + amp xi at every point, both components.
 // The kernels below take either state type: float4 (complex64) or double4 (complex128).
 __device__ __forceinline__ float4 fma4(float a, float4 z, float4 w) {
   return make_float4(fmaf(a, z.x, w.x), fmaf(a, z.y, w.y), fmaf(a, z.z, w.z), fmaf(a, z.w, w.w));
@@ -16,6 +15,7 @@ __device__ __forceinline__ double4 fma4(double a, double4 z, double4 w) {
   return make_double4(fma(a, z.x, w.x), fma(a, z.y, w.y), fma(a, z.z, w.z), fma(a, z.w, w.w));
 }
 
+// psi <- psi + amp xi at every point, both components.
 template <class Q, class T>
 __global__ void __launch_bounds__(256) add_noise_kernel(Q* __restrict__ psi, const Q* __restrict__ xi, T amp,
                                                         long long n) {
