@@ -163,3 +163,29 @@ def test_sweep_instances_are_seeded_and_in_range():
         assert 0.0 <= p.omega <= 3.0 and -0.5 <= p.delta <= 0.5
         assert p.k_l == 2.0 and p.dt == 1e-3 and p.omega_r0 == 0.0
     assert len({p.g_uu for p in a}) == 96
+
+
+def test_new_entry_points_reject_null_and_invalid_arguments(lib):
+    # all of these fail before any device call
+    from paper_2010_15069_amd import SgpeParams
+    d = ctypes.c_double()
+    n = (ctypes.c_int32 * 2)()
+    assert lib.sgpe_set_splitting(None, 0, 0) == 1
+    assert lib.sgpe_set_raman_profile(None, None, None) == 1
+    assert lib.sgpe_add_noise(None, None, 1.0) == 1
+    assert lib.sgpe_phase_separation(None, ctypes.byref(d)) == 1
+    assert lib.sgpe_population_radius(None, 0.99, ctypes.byref(d)) == 1
+    assert lib.sgpe_winding(None, 1.0, n, None) == 1
+    out = ctypes.c_void_p(1234)
+    p = SgpeParams.from_obj(Params())
+    for prec in (-1, 2, 7):
+        assert lib.sgpe_create_ex(ctypes.byref(p), prec, None, None, ctypes.byref(out)) == 1
+        assert out.value is None
+    assert lib.sgpe_create_ex(ctypes.byref(p), 1, None, None, None) == 1
+
+
+def test_header_documents_precision_and_splitting_enums():
+    h = open(HEADER).read()
+    for name in ("SGPE_C64 = 0", "SGPE_C128 = 1", "SGPE_SPLIT_KRK = 0", "SGPE_SPLIT_RKR = 1",
+                 "SGPE_RSPLIT_FROZEN = 0", "SGPE_RSPLIT_NLN = 1"):
+        assert name in h, name
