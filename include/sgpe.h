@@ -224,6 +224,8 @@ sgpe_status sgpe_set_col_tile(sgpe_ctx* ctx, int32_t columns);
  *   col_iters   the same for column tiles
  *   row_points  points per lane of the x transforms: 16, or 8 / 4 when nx <= 1024
  *   col_points  the same for the y transforms and ny
+ *   row_tile    rows per row-pass workgroup (power of two); 0 in sgpe_set_schedule: the default
+ *               for row_points (256-thread workgroups)
  * A workgroup has 2 * lines * (n / points) threads, at most 512 (256 when prefetching), and its
  * LDS must fit the device. */
 typedef struct {
@@ -232,6 +234,7 @@ typedef struct {
   int32_t col_iters;
   int32_t row_points;
   int32_t col_points;
+  int32_t row_tile;
 } sgpe_schedule;
 
 /* The schedule in use.  SGPE_EINVAL if either pointer is NULL. */

@@ -39,7 +39,7 @@ class Schedule(ctypes.Structure):
     """sgpe_schedule: launch schedule of the two passes (see include/sgpe.h)."""
     _fields_ = [("col_tile", ctypes.c_int32), ("row_iters", ctypes.c_int32),
                 ("col_iters", ctypes.c_int32), ("row_points", ctypes.c_int32),
-                ("col_points", ctypes.c_int32)]
+                ("col_points", ctypes.c_int32), ("row_tile", ctypes.c_int32)]
 
 
 class SgpeError(RuntimeError):

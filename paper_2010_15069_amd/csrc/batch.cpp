@@ -192,7 +192,7 @@ sgpe_status set_class_schedule(sgpe_batch* b, BatchClass& k, const sgpe_schedule
 // Default for a class: the single-instance rule applied to the class's total point count.
 sgpe_schedule class_default(const sgpe_ctx* c0, size_t members) {
   const size_t total = members * size_t(c0->p.nx) * size_t(c0->p.ny);
-  sgpe_schedule s;
+  sgpe_schedule s{};   // row_tile 0: the default for the points per lane
   s.row_points = default_points(c0->p.nx, total);
   s.col_points = default_points(c0->p.ny, total);
   s.row_iters = 1;
@@ -392,7 +392,7 @@ sgpe_status sgpe_batch_autotune(sgpe_batch* b, int32_t steps, double* best_ms) {
       for (int cp : pts)
         for (int ct : tiles) {
           if (st != SGPE_OK) break;
-          sgpe_schedule s;
+          sgpe_schedule s{};
           s.col_tile = ct;
           s.row_iters = 1;
           s.col_iters = 1;

@@ -172,8 +172,10 @@ class Solver:
             check(self._lib.sgpe_set_schedule(self._ctx, None), "sgpe_set_schedule")
             return self
         cur = self.get_schedule()
-        cur.update(schedule or {})
-        cur.update(fields)
+        changes = dict(schedule or {}, **fields)
+        if "row_points" in changes and "row_tile" not in changes:
+            cur["row_tile"] = 0          # the default tile for the new points per lane
+        cur.update(changes)
         sc = Schedule(**{k: int(v) for k, v in cur.items()})
         check(self._lib.sgpe_set_schedule(self._ctx, ctypes.byref(sc)), "sgpe_set_schedule")
         return self
@@ -277,8 +279,10 @@ class Batch:
             check(self._lib.sgpe_batch_set_schedule(self._b, int(k), None), "sgpe_batch_set_schedule")
             return self
         cur = self.get_schedule(k)
-        cur.update(schedule or {})
-        cur.update(fields)
+        changes = dict(schedule or {}, **fields)
+        if "row_points" in changes and "row_tile" not in changes:
+            cur["row_tile"] = 0          # the default tile for the new points per lane
+        cur.update(changes)
         sc = Schedule(**{key: int(v) for key, v in cur.items()})
         check(self._lib.sgpe_batch_set_schedule(self._b, int(k), ctypes.byref(sc)), "sgpe_batch_set_schedule")
         return self

@@ -220,6 +220,34 @@ def test_pipeline_depth_variants(Solver, name, nx, ny):
     assert done >= 2
 
 
+@pytest.mark.parametrize("n", [256, 1024])
+def test_row_tile_variants(Solver, n):
+    # rows per row-pass workgroup (1..4, with and without prefetch) only regroup the work:
+    # real-time results bit-identical, imaginary time up to the grouping of the norm partials
+    p = preset("metric_1024", nx=n, ny=n)
+    psi0 = initial_state(p, "tf", seed=6)
+    ref_real = ref_imag = None
+    tried = 0
+    for tile in (1, 2, 4):
+        for it in (1, 2):
+            s = Solver(p)
+            try:
+                s.set_schedule(row_tile=tile, row_iters=it)
+            except Exception:
+                continue
+            tried += 1
+            s.set_psi(psi0).step_real(10)
+            r = s.get_psi()
+            s.step_imag(10)
+            i = s.get_psi()
+            if ref_real is None:
+                ref_real, ref_imag = r, i
+            else:
+                assert np.array_equal(r, ref_real), (tile, it)
+                assert rel_l2(i, ref_imag) < 1e-6, (tile, it)
+    assert tried >= 3
+
+
 def test_energy_and_norm_of_arbitrary_states(Solver):
     for (nx, ny, seed) in [(64, 64, 1), (256, 128, 2), (512, 1024, 3)]:
         p = Params(nx=nx, ny=ny, xmax=7.0, ymax=9.0, g_uu=5.0, g_dd=2.0, g_ud=3.0, k_l=1.1,
