@@ -214,6 +214,13 @@ void default_schedule(sgpe_ctx* c) {
   c->cols = sgpe::col_default_cols(nx, ny, c->col_points, c->max_lds);
   c->row_iters = 1;
   c->col_iters = 1;
+  // Column tiles: as many workgroups as compute units, up to one per CU, where that tile is
+  // supported (measured: 1 column at 128^2 and 256^2, -9 % and -4 % per step; 512^2-1024^2 already
+  // have one per CU; at 2048^2 it would take 2048 threads).
+  {
+    const int cc = std::max(1, nx / c->n_cu);
+    if ((cc & (cc - 1)) == 0 && sgpe::col_cols_supported(nx, ny, cc, 1, c->col_points, c->max_lds)) c->cols = cc;
+  }
   // One row-pass workgroup per compute unit (up to 512 threads) where the rows divide evenly:
   // measured fastest at 256^2, 512^2 and 1024^2 (at 1024^2, 4-row workgroups beat 2-row ones
   // with prefetch by 6 %; at 2048^2 it would take 2048 threads).
