@@ -194,11 +194,9 @@ void k_tables(const sgpe_params& p, bool imag, double h, std::vector<sgpe::point
 // Default schedule (from measured sweeps on MI355X).  Points per lane: 16 where the grid alone
 // fills the device; on small grids fewer points per lane (more lanes, a shorter instruction
 // stream per lane) cut each pass's latency.  Row prefetching (two row groups per workgroup) pays
-// only when the one-group grid is a single round of resident workgroups (two per compute unit):
-// then nothing else would overlap the first loads and last stores.  With more rounds, later
-// workgroups' loads already overlap earlier ones' arithmetic and halving the resident waves
-// loses.  Column prefetching needs the narrower tile and measured slower everywhere; it stays
-// off by default.
+// only for small rows whose one-group grid is a single round of resident workgroups (two per
+// compute unit): then nothing else would overlap the first loads and last stores.  Column
+// prefetching needs the narrower tile and measured slower everywhere; it stays off by default.
 int default_points(int n, size_t npts) {
   if (n > sgpe::kMaxNSmallP) return 16;
   if (npts >= (size_t(1) << 19)) return 16;
@@ -221,16 +219,13 @@ void default_schedule(sgpe_ctx* c) {
     const int cc = std::max(1, nx / c->n_cu);
     if ((cc & (cc - 1)) == 0 && sgpe::col_cols_supported(nx, ny, cc, 1, c->col_points, c->max_lds)) c->cols = cc;
   }
-  // One row-pass workgroup per compute unit (up to 512 threads) where the rows divide evenly:
-  // measured fastest at 256^2, 512^2 and 1024^2 (at 1024^2, 4-row workgroups beat 2-row ones
-  // with prefetch by 6 %; at 2048^2 it would take 2048 threads).
-  if (ny % c->n_cu == 0) {
-    const int rows_cu = ny / c->n_cu;
-    if ((rows_cu & (rows_cu - 1)) == 0 && sgpe::schedule_supported(nx, rows_cu, 1, c->row_points) &&
-        sgpe::row_lds_bytes(nx, rows_cu) <= c->max_lds) {
-      c->rows = rows_cu;
-      return;
-    }
+  // One row per workgroup where a row takes at least two waves (measured at 256^2-2048^2: fastest,
+  // or within 1 % at 512^2; one 4-row workgroup per CU was 8 % slower per step at 1024^2 and row
+  // prefetch slower everywhere).  Smaller rows keep the derived tile.
+  if (nx / c->row_points >= 64 && sgpe::schedule_supported(nx, 1, 1, c->row_points) &&
+      sgpe::row_lds_bytes(nx, 1) <= c->max_lds) {
+    c->rows = 1;
+    return;
   }
   const int groups = ny / c->rows;
   if (c->row_points == 16 && groups == 2 * c->n_cu && sgpe::schedule_supported(nx, c->rows, 2, 16))

@@ -29,7 +29,7 @@ __device__ __forceinline__ int col_group(int b, int ngroups) {
 // T = N / P lanes per transform.
 extern __shared__ __align__(16) unsigned char col_lds[];
 
-template <int N, int NORM, int ITERS, int P, class R>
+template <int N, int NORM, int ITERS, int P, bool WT, class R>
 __device__ __forceinline__ void col_body(const ColArgsT<R>& a, int wg, int ngroups) {
   using CX = cplx_t<R>;
   CX* const lds_raw = reinterpret_cast<CX*>(col_lds);
@@ -109,7 +109,7 @@ __device__ __forceinline__ void col_body(const ColArgsT<R>& a, int wg, int ngrou
     inv_pass<N>(v, lds, t, tr);
 
 #pragma unroll
-    for (int m = 0; m < P; ++m) *reinterpret_cast<CX*>(out + (off + mstride * m)) = v[m];
+    for (int m = 0; m < P; ++m) store_state<WT>(reinterpret_cast<CX*>(out + (off + mstride * m)), v[m]);
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = nxt[m];
@@ -127,19 +127,19 @@ __device__ __forceinline__ void col_body(const ColArgsT<R>& a, int wg, int ngrou
 // instance blockIdx.y, its arguments from a device table.
 template <int N, int NORM, int ITERS, int P>
 __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) {
-  col_body<N, NORM, ITERS, P>(a, blockIdx.x, gridDim.x);
+  col_body<N, NORM, ITERS, P, true>(a, blockIdx.x, gridDim.x);
 }
 
 template <int N, int NORM, int P>
 __global__ void __launch_bounds__(512) col_kernel_batch(const ColArgs* __restrict__ tab) {
-  col_body<N, NORM, 1, P>(tab[blockIdx.y], blockIdx.x, gridDim.x);
+  col_body<N, NORM, 1, P, false>(tab[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // complex128: 16 points per lane, one tile per workgroup; the host keeps tiles at 256 threads
 // except where one column alone needs more (N = 4096)
 template <int N, int NORM>
 __global__ void __launch_bounds__(2 * N / 16 > 256 ? 512 : 256) col_kernel_c128(ColArgsT<double> a) {
-  col_body<N, NORM, 1, 16>(a, blockIdx.x, gridDim.x);
+  col_body<N, NORM, 1, 16, false>(a, blockIdx.x, gridDim.x);
 }
 
 // -------------------------------------------------------------------------------------------

@@ -58,6 +58,33 @@ __device__ __forceinline__ float fabs_(float x) { return fabsf(x); }
 __device__ __forceinline__ double fabs_(double x) { return fabs(x); }
 
 // ---------------------------------------------------------------------------------------------
+// State stores of the step kernels.  Consecutive passes split the grid between workgroups by
+// rows, then by columns, so almost every point a pass writes is next read on another XCD, whose
+// L2 it must leave first.  A plain store parks the line dirty in the writer's L2, and the end of
+// the kernel writes back every XCD's dirty lines in one burst that the next kernel then waits
+// for.  A device-scope store goes through the L2 to the memory side as it is issued, so that
+// traffic overlaps the rest of the pass.  Relaxed order: the scope is the only property wanted
+// (every point has a single writer in a pass, and kernel boundaries order the passes).
+// Measured per launch kind: write-through wins for single-instance complex64 passes (one round
+// of workgroups, nothing behind the last stores); batched launches, whose later workgroups
+// already overlap the write-back, and complex128 points (two 8-byte device-scope stores per
+// 16-byte component) are faster with plain stores.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void store_through(float2* p, float2 v) {
+  unsigned long long b;
+  __builtin_memcpy(&b, &v, sizeof b);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool WT, class C>
+__device__ __forceinline__ void store_state(C* p, C v) {
+  if constexpr (WT && sizeof(C) == sizeof(float2)) {
+    store_through(p, v);
+  } else {
+    *p = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // LDS addressing: a transform's N positions occupy N + N/16 slots (one pad slot per 16
 // positions) and `stride` transforms are interleaved slot by slot, so that lanes which own
 // neighbouring transforms touch neighbouring slots.

@@ -265,7 +265,7 @@ __device__ __forceinline__ void row_apply_r_nln(C (&v)[P], const RowArgsT<R>& a,
 // The kernels' dynamic LDS, typed per precision where it is used.
 extern __shared__ __align__(16) unsigned char row_lds[];
 
-template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P, class R>
+template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P, bool WT, class R>
 __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
   using C = cplx_t<R>;
   C* const lds_raw = reinterpret_cast<C*>(row_lds);
@@ -334,7 +334,7 @@ __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
       }
     }
 #pragma unroll
-    for (int m = 0; m < P; ++m) *reinterpret_cast<C*>(out + (off + PB * T * m)) = v[m];
+    for (int m = 0; m < P; ++m) store_state<WT>(reinterpret_cast<C*>(out + (off + PB * T * m)), v[m]);
     if (it + 1 < ITERS) {
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = nxt[m];
@@ -394,7 +394,7 @@ __device__ __forceinline__ void row_var_body(const RowArgs& a, int wg) {
   }
   if (flags & VAR_FWD) fwd_pass<N>(v, lds, t, tr);
 #pragma unroll
-  for (int m = 0; m < P; ++m) *reinterpret_cast<float2*>(out + (off + 16u * T * m)) = v[m];
+  for (int m = 0; m < P; ++m) store_state<true>(reinterpret_cast<float2*>(out + (off + 16u * T * m)), v[m]);
 }
 
 // Row groups are sized for 256 threads (row_rows_per_block); only a 4096-point row at 16 points
@@ -409,19 +409,19 @@ __global__ void __launch_bounds__(2 * N / P > 256 ? 512 : 256) row_var_kernel(Ro
 // instance blockIdx.y, its arguments from a device table.
 template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
 __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) {
-  row_body<N, MODE, IMAG, FULL, ITERS, P>(a, blockIdx.x);
+  row_body<N, MODE, IMAG, FULL, ITERS, P, true>(a, blockIdx.x);
 }
 
 // complex128: 16 points per lane, one row group per workgroup; row groups are sized for 256
 // threads except at N = 4096 (512)
 template <int N, int MODE, bool IMAG, bool FULL>
 __global__ void __launch_bounds__(2 * N / 16 > 256 ? 512 : 256) row_kernel_c128(RowArgsT<double> a) {
-  row_body<N, MODE, IMAG, FULL, 1, 16>(a, blockIdx.x);
+  row_body<N, MODE, IMAG, FULL, 1, 16, false>(a, blockIdx.x);
 }
 
 template <int N, int MODE, bool IMAG, bool FULL, int P>
 __global__ void __launch_bounds__(512) row_kernel_batch(const RowArgs* __restrict__ tab) {
-  row_body<N, MODE, IMAG, FULL, 1, P>(tab[blockIdx.y], blockIdx.x);
+  row_body<N, MODE, IMAG, FULL, 1, P, false>(tab[blockIdx.y], blockIdx.x);
 }
 
 // -------------------------------------------------------------------------------------------
