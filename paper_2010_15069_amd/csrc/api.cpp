@@ -511,6 +511,31 @@ sgpe_status sync_and_latch(sgpe_ctx* c) {
   return c->latched;
 }
 
+const double* fetch_partials(sgpe_ctx* c, const double* dev, size_t n) {
+  if (n > c->host_part_n) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (c->host_part) (void)hipHostFree(c->host_part);
+    c->host_part = nullptr;
+    c->host_part_n = 0;
+    void* ptr = nullptr;
+    if (hipHostMalloc(&ptr, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    c->host_part = static_cast<double*>(ptr);
+    c->host_part_n = n;
+  }
+  if (hipMemcpyAsync(c->host_part, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return c->host_part;
+}
+
 }  // namespace sgpe_host
 
 using namespace sgpe_host;
@@ -674,6 +699,7 @@ void sgpe_destroy(sgpe_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (void* ptr : c->allocations) (void)hipFree(ptr);
+  if (c->host_part) (void)hipHostFree(c->host_part);
   (void)hipGetLastError();
   delete c;
 }
@@ -806,14 +832,10 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
   hipError_t e = c->prec == SGPE_C128 ? sgpe::launch_norm(c->psi64, npts, c->npart, nb, c->stream)
                                       : sgpe::launch_norm(c->psi, npts, c->npart, nb, c->stream);
   if (e != hipSuccess) return status_of(e);
-  std::vector<double> part(nb);
-  if (hipMemcpyAsync(part.data(), c->npart, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return SGPE_EDEVICE;
-  }
+  const double* part = fetch_partials(c, c->npart, size_t(nb));
+  if (!part) return SGPE_EDEVICE;
   double s = 0.0;
-  for (double v : part) s += v;
+  for (int b = 0; b < nb; ++b) s += part[b];
   const double dx = 2.0 * c->p.xmax / c->p.nx, dy = 2.0 * c->p.ymax / c->p.ny;
   *out = dx * dy * s;
   if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
@@ -879,13 +901,8 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   a.col_partials = c->epart + RP * nrb;
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e != hipSuccess) return status_of(e);
-  std::vector<double> part(RP * size_t(nrb) + ncb);
-  if (hipMemcpyAsync(part.data(), c->epart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return SGPE_EDEVICE;
-  }
+  const double* part = fetch_partials(c, c->epart, RP * size_t(nrb) + ncb);
+  if (!part) return SGPE_EDEVICE;
   double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
   for (int b = 0; b < nrb; ++b) {
     er += part[RP * b];

@@ -59,6 +59,8 @@ struct sgpe_ctx {
   bool has_state = false;
   sgpe_status latched = SGPE_OK;
   std::vector<void*> allocations;
+  double* host_part = nullptr;   // pinned host copy of reduction partials, grown on demand
+  size_t host_part_n = 0;
 };
 
 namespace sgpe_host {
@@ -76,6 +78,10 @@ sgpe_schedule get_schedule(const sgpe_ctx* c);
 sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
+// Copies n doubles of reduction partials from the device into the context's pinned host buffer
+// (queued on the context's stream, which is then synchronised) and returns that buffer; NULL on a
+// device or allocation error.  A pinned destination avoids the staging copy of pageable memory.
+const double* fetch_partials(sgpe_ctx* c, const double* dev, size_t n);
 // Spatial Raman coupling tables Omega_x(x_j) + Omega_y(y_i) (NULL = zero profile), allocated on first
 // use; waits for the stream's queued work before overwriting them.
 sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y);

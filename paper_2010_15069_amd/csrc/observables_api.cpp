@@ -41,13 +41,8 @@ sgpe_status sgpe_set_raman_profile(sgpe_ctx* c, const double* omega_x, const dou
 
 // Copies nblocks * per_block partials from c->epart to the host and sums each slot in block order.
 static sgpe_status fetch_sums(sgpe_ctx* c, int nblocks, int per_block, double* sums) {
-  std::vector<double> part(size_t(nblocks) * per_block);
-  if (hipMemcpyAsync(part.data(), c->epart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return SGPE_EDEVICE;
-  }
+  const double* part = fetch_partials(c, c->epart, size_t(nblocks) * per_block);
+  if (!part) return SGPE_EDEVICE;
   for (int k = 0; k < per_block; ++k) sums[k] = 0.0;
   for (int b = 0; b < nblocks; ++b)
     for (int k = 0; k < per_block; ++k) sums[k] += part[size_t(b) * per_block + k];
