@@ -43,7 +43,8 @@ extern "C" {
 typedef enum {
   SGPE_OK = 0,
   SGPE_EINVAL = 1,      /* invalid argument or parameter (reported before any device work) */
-  SGPE_ENOMEM = 2,      /* device allocation failed, or the grid exceeds the supported size */
+  SGPE_ENOMEM = 2,      /* device or pinned host allocation failed, or the grid exceeds the
+                           supported size */
   SGPE_EDEVICE = 3,     /* no usable gfx950 device, or a HIP runtime error */
   SGPE_ENONFINITE = 4,  /* NaN/Inf in an input state, or a non-finite norm during stepping */
   SGPE_ESTATE = 5       /* call not valid in the current state (e.g. stepping before set_psi) */
@@ -123,11 +124,13 @@ sgpe_status sgpe_step_imag(sgpe_ctx* ctx, int64_t n);
 
 /* Energy per particle of the current state rescaled to norm0 (Gross-Pitaevskii functional, Eqs.
  * (H1)-(H4) with 1/2 on the interaction terms; quadratic terms over the norm N, interaction terms
- * over N^2 / norm0).  Accumulated in fp64.  Synchronises. */
+ * over N^2 / norm0).  Accumulated in fp64.  Synchronises.  The partial sums come back through a
+ * pinned host buffer owned by the context, allocated on the first reduction (energy, norm or an
+ * observable) and grown on demand; SGPE_ENOMEM if that allocation fails. */
 sgpe_status sgpe_energy(sgpe_ctx* ctx, double* e_per_particle);
 
 /* Norm dx dy sum |psi|^2 of the current state (both components), accumulated in fp64.
- * Synchronises. */
+ * Synchronises.  Partials as sgpe_energy. */
 sgpe_status sgpe_norm(sgpe_ctx* ctx, double* norm);
 
 /* Wait for all work enqueued by the context; reports a latched error. */

@@ -511,11 +511,13 @@ sgpe_status sync_and_latch(sgpe_ctx* c) {
   return c->latched;
 }
 
-const double* fetch_partials(sgpe_ctx* c, const double* dev, size_t n) {
+sgpe_status fetch_partials(sgpe_ctx* c, const double* dev, size_t n, const double** host) {
+  *host = nullptr;
   if (n > c->host_part_n) {
+    // the old buffer may still be the destination of a queued copy
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
       (void)hipGetLastError();
-      return nullptr;
+      return SGPE_EDEVICE;
     }
     if (c->host_part) (void)hipHostFree(c->host_part);
     c->host_part = nullptr;
@@ -523,7 +525,7 @@ const double* fetch_partials(sgpe_ctx* c, const double* dev, size_t n) {
     void* ptr = nullptr;
     if (hipHostMalloc(&ptr, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
-      return nullptr;
+      return SGPE_ENOMEM;
     }
     c->host_part = static_cast<double*>(ptr);
     c->host_part_n = n;
@@ -531,9 +533,10 @@ const double* fetch_partials(sgpe_ctx* c, const double* dev, size_t n) {
   if (hipMemcpyAsync(c->host_part, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipGetLastError();
-    return nullptr;
+    return SGPE_EDEVICE;
   }
-  return c->host_part;
+  *host = c->host_part;
+  return SGPE_OK;
 }
 
 }  // namespace sgpe_host
@@ -832,8 +835,8 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
   hipError_t e = c->prec == SGPE_C128 ? sgpe::launch_norm(c->psi64, npts, c->npart, nb, c->stream)
                                       : sgpe::launch_norm(c->psi, npts, c->npart, nb, c->stream);
   if (e != hipSuccess) return status_of(e);
-  const double* part = fetch_partials(c, c->npart, size_t(nb));
-  if (!part) return SGPE_EDEVICE;
+  const double* part = nullptr;
+  if ((st = fetch_partials(c, c->npart, size_t(nb), &part)) != SGPE_OK) return st;
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += part[b];
   const double dx = 2.0 * c->p.xmax / c->p.nx, dy = 2.0 * c->p.ymax / c->p.ny;
@@ -901,8 +904,8 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   a.col_partials = c->epart + RP * nrb;
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e != hipSuccess) return status_of(e);
-  const double* part = fetch_partials(c, c->epart, RP * size_t(nrb) + ncb);
-  if (!part) return SGPE_EDEVICE;
+  const double* part = nullptr;
+  if ((st = fetch_partials(c, c->epart, RP * size_t(nrb) + ncb, &part)) != SGPE_OK) return st;
   double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
   for (int b = 0; b < nrb; ++b) {
     er += part[RP * b];

@@ -79,9 +79,10 @@ sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
 // Copies n doubles of reduction partials from the device into the context's pinned host buffer
-// (queued on the context's stream, which is then synchronised) and returns that buffer; NULL on a
-// device or allocation error.  A pinned destination avoids the staging copy of pageable memory.
-const double* fetch_partials(sgpe_ctx* c, const double* dev, size_t n);
+// (queued on the context's stream, which is then synchronised) and points *host at it.  Returns
+// SGPE_ENOMEM if the buffer cannot grow, SGPE_EDEVICE on a device error.  A pinned destination
+// avoids the staging copy of pageable memory.
+sgpe_status fetch_partials(sgpe_ctx* c, const double* dev, size_t n, const double** host);
 // Spatial Raman coupling tables Omega_x(x_j) + Omega_y(y_i) (NULL = zero profile), allocated on first
 // use; waits for the stream's queued work before overwriting them.
 sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y);

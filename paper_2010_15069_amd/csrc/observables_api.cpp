@@ -41,8 +41,9 @@ sgpe_status sgpe_set_raman_profile(sgpe_ctx* c, const double* omega_x, const dou
 
 // Copies nblocks * per_block partials from c->epart to the host and sums each slot in block order.
 static sgpe_status fetch_sums(sgpe_ctx* c, int nblocks, int per_block, double* sums) {
-  const double* part = fetch_partials(c, c->epart, size_t(nblocks) * per_block);
-  if (!part) return SGPE_EDEVICE;
+  const double* part = nullptr;
+  const sgpe_status st = fetch_partials(c, c->epart, size_t(nblocks) * per_block, &part);
+  if (st != SGPE_OK) return st;
   for (int k = 0; k < per_block; ++k) sums[k] = 0.0;
   for (int b = 0; b < nblocks; ++b)
     for (int k = 0; k < per_block; ++k) sums[k] += part[size_t(b) * per_block + k];
