@@ -538,16 +538,18 @@ __device__ __forceinline__ SinCosM1 sincos_m1_t(float phi) {
 }
 constexpr float kSmallPhase = 0.785398163f;   // pi/4
 
-// fp64: (cos(phi) - 1, sin(phi), sin(phi)/phi) from the fp64 library, cos - 1 as -2 sin^2(phi/2)
-// (relative accuracy for small phi); one routine for every phi, so SMALL makes no difference.
+// fp64: (cos(phi) - 1, sin(phi), sin(phi)/phi) from one fp64 library sincos of phi/2, by the
+// half-angle identities cos(phi) - 1 = -2 sin^2(phi/2) (relative accuracy for small phi) and
+// sin(phi) = 2 sin(phi/2) cos(phi/2); one routine for every phi, so SMALL makes no difference.
 struct SinCosM1d {
   double cm1, s, sinc;
 };
 template <bool SMALL>
 __device__ __forceinline__ SinCosM1d sincos_m1_t(double phi) {
   SinCosM1d out;
-  const double h = sin(0.5 * phi);
-  out.s = sin(phi);
+  double h, c;
+  sincos(0.5 * phi, &h, &c);
+  out.s = 2.0 * h * c;
   out.cm1 = -2.0 * h * h;
   out.sinc = phi != 0.0 ? out.s / phi : 1.0;
   return out;
