@@ -263,6 +263,21 @@ def test_energy_and_norm_of_arbitrary_states(Solver):
         assert abs(s.energy() - o.energy()) <= 1e-6 * abs(o.energy())
 
 
+def test_reductions_repeat_in_any_order(Solver):
+    """Energy, norm and the observables share one host buffer for their partials, grown on
+    demand: repeated and interleaved calls (small reduction first, then larger ones) return the
+    same bits as the first call on a fresh context."""
+    p = preset("realtime_512", nx=512, ny=256)
+    psi = round_to_c64(initial_state(p, "tf", seed=4))
+    fresh = Solver(p).set_psi(psi)
+    e_ref, n_ref, s_ref = fresh.energy(), Solver(p).set_psi(psi).norm(), Solver(p).set_psi(psi).phase_separation()
+    s = Solver(p).set_psi(psi)
+    seq = [s.norm(), s.energy(), s.phase_separation(), s.norm(), s.energy(), s.energy()]
+    assert seq[0] == n_ref and seq[3] == n_ref
+    assert seq[1] == e_ref and seq[4] == e_ref and seq[5] == e_ref
+    assert seq[2] == s_ref
+
+
 def test_nonfinite_input_rejected(Solver):
     from paper_2010_15069_amd import SgpeError
     p = preset("tiny")
