@@ -624,7 +624,9 @@ sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_st
   default_schedule(c);
   const bool c128 = precision == SGPE_C128;
   if (c128) {
-    c->rows = sgpe::row_rows_per_block(p->nx, p->ny, 16, c->max_lds / 2);
+    // one row per workgroup where a row takes at least one wave (measured: 29.1 -> 27.5 us per
+    // imaginary step at 512^2, 64.3 -> 63.8 at 1024^2, unchanged at 2048^2), else the derived tile
+    c->rows = p->nx / 16 >= 32 ? 1 : sgpe::row_rows_per_block(p->nx, p->ny, 16, c->max_lds / 2);
     c->cols = c128_cols(p->nx, p->ny, c->max_lds);
     c->row_points = c->col_points = 16;
     c->row_iters = c->col_iters = 1;
