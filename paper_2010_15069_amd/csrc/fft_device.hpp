@@ -484,7 +484,7 @@ struct SinCosM1 {
   float cm1, s, sinc;
 };
 
-__device__ __forceinline__ SinCosM1 sincos_m1_reduced(float phi) {
+__host__ __device__ __forceinline__ SinCosM1 sincos_m1_reduced(float phi) {
   const float k = rintf(phi * 0.636619772367581343f);
   float r = fmaf(-k, 1.57079637050628662f, phi);   // pi/2 hi
   r = fmaf(-k, -4.37113900018624283e-8f, r);        // pi/2 lo
@@ -497,9 +497,11 @@ __device__ __forceinline__ SinCosM1 sincos_m1_reduced(float phi) {
   const int q = static_cast<int>(k) & 3;
   SinCosM1 out;
   if (q == 0) {
+    // cos and sin have period 2 pi, so the reduced values serve for every k = 0 mod 4; sin(phi)/phi
+    // does not: (1 + ps) = sin(r)/r equals it only for k = 0
     out.cm1 = cr_m1;
     out.s = sr;
-    out.sinc = 1.0f + ps;
+    out.sinc = k == 0.0f ? 1.0f + ps : sr / phi;
   } else {
     const float cr = cr_m1 + 1.0f;
     const float c = q == 1 ? -sr : (q == 2 ? -cr : sr);
@@ -511,7 +513,7 @@ __device__ __forceinline__ SinCosM1 sincos_m1_reduced(float phi) {
 }
 
 // |phi| <= pi/4 needs no reduction; the polynomials alone are accurate there.
-__device__ __forceinline__ SinCosM1 sincos_m1_small(float phi) {
+__host__ __device__ __forceinline__ SinCosM1 sincos_m1_small(float phi) {
   const float r2 = phi * phi;
   const float ps = r2 * fmaf(r2, fmaf(r2, fmaf(r2, 2.75573192e-6f, -1.98412698e-4f), 8.33333333e-3f),
                              -1.66666667e-1f);
