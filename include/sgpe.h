@@ -28,8 +28,14 @@
  * Threading: a context is not thread-safe; distinct contexts are independent.
  * Errors: every call returns a status; nothing aborts and no C++ exception crosses the ABI.
  * Validation errors are returned before any device work.  A non-finite norm found during
- * imaginary-time stepping is latched in the context and reported by the next synchronising call
- * (sgpe_get_psi, sgpe_norm, sgpe_energy, sgpe_synchronize) as SGPE_ENONFINITE.
+ * imaginary-time stepping (the renormalisation of Sec. 3.2 divides by it) is latched in the
+ * context: the pass that would rescale by a norm that is zero, infinite or NaN sets a status word
+ * in pinned host memory, and the next synchronising call (sgpe_synchronize, sgpe_get_psi,
+ * sgpe_norm, sgpe_energy, the observables) returns SGPE_ENONFINITE.  Non-finite values found in
+ * the state by get_psi, norm or energy latch the same way.  sgpe_set_psi clears the latch.
+ *
+ * Field names: sgpe_params names the spin-momentum coefficient k_l (k_L of Eq. H1) and the uniform
+ * Raman coupling omega (Omega of Eq. H4), after the paper's symbols.
  */
 #ifndef SGPE_H
 #define SGPE_H
@@ -74,7 +80,9 @@ sgpe_status sgpe_validate_params(const sgpe_params* p);
  * Host-side query; never fails with an exception. */
 int32_t sgpe_device_count(void);
 
-/* Create a solver context on the current HIP device.
+/* Create a solver context on the current HIP device for the two-component model of Sec. 3.1
+ * (Eq. GPEcomponent, Hamiltonian Eqs. H1-H4) on the periodic grid of Sec. 3.2 (x_j = -xmax + j dx,
+ * k-space spacing pi / xmax).  Builds the operator and root tables of Eq. (TEOp) for dt and dt/2.
  *   hip_stream: a hipStream_t to enqueue all work on, or NULL for the null stream.  Borrowed.
  *   psi_dev:    NULL to let the context allocate the state (16*nx*ny bytes), or a device pointer
  *               of at least 16*nx*ny bytes, 16-byte aligned, which the context borrows and which
@@ -105,12 +113,18 @@ sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_st
 /* Release the context and everything it allocated (not a borrowed state).  NULL is a no-op. */
 void sgpe_destroy(sgpe_ctx* ctx);
 
-/* Copy a host state in: psi_host is complex128, shape (2, ny, nx), C order, re/im interleaved
- * (component 0 = up).  It is rounded once to complex64.  Synchronous.
- * Errors: SGPE_EINVAL (NULL), SGPE_ENONFINITE (NaN/Inf in the input; the state is unchanged). */
+/* Set the pseudospinor order parameter (Psi_up, Psi_down) of Sec. 3.1 on the grid points of
+ * Sec. 3.2 -- the initial state of a real- or imaginary-time propagation.  psi_host is complex128,
+ * shape (2, ny, nx), C order, re/im interleaved (component 0 = up); the caller keeps ownership.
+ * It is rounded once to complex64 (copied as is for SGPE_C128).  Synchronous.  Clears a latched
+ * status.  Errors: SGPE_EINVAL (NULL), SGPE_ENONFINITE (NaN/Inf in the input; the state is
+ * unchanged). */
 sgpe_status sgpe_set_psi(sgpe_ctx* ctx, const double* psi_host);
 
-/* Copy the state out in the same complex128 layout.  Synchronises the stream. */
+/* Copy the order parameter (Sec. 3.1) out in the layout of sgpe_set_psi, into the caller's
+ * array of 4 * nx * ny doubles.  Synchronises the stream.  Errors: SGPE_EINVAL (NULL), SGPE_ESTATE
+ * (no state), SGPE_ENONFINITE (a non-finite value in the state, or a latched status; the values
+ * are still copied). */
 sgpe_status sgpe_get_psi(sgpe_ctx* ctx, double* psi_host);
 
 /* Advance n >= 0 real-time steps (Sec. 3.2).  Asynchronous on the context's stream.  The
@@ -129,11 +143,14 @@ sgpe_status sgpe_step_imag(sgpe_ctx* ctx, int64_t n);
  * observable) and grown on demand; SGPE_ENOMEM if that allocation fails. */
 sgpe_status sgpe_energy(sgpe_ctx* ctx, double* e_per_particle);
 
-/* Norm dx dy sum |psi|^2 of the current state (both components), accumulated in fp64.
- * Synchronises.  Partials as sgpe_energy. */
+/* Norm dx dy sum |psi|^2 of the current state (both components), accumulated in fp64: the atom
+ * number that imaginary time restores after every step (Sec. 3.2).  Synchronises.  Partials as
+ * sgpe_energy.  Errors: SGPE_EINVAL (NULL), SGPE_ESTATE (no state), SGPE_ENONFINITE. */
 sgpe_status sgpe_norm(sgpe_ctx* ctx, double* norm);
 
-/* Wait for all work enqueued by the context; reports a latched error. */
+/* Wait for all work enqueued by the context; reports a latched error (SGPE_ENONFINITE after an
+ * imaginary-time step met a norm that is zero, infinite or NaN, so that the renormalisation of
+ * Sec. 3.2 could not be applied). */
 sgpe_status sgpe_synchronize(sgpe_ctx* ctx);
 
 /* Measurement helper: run n real-time (imag = 0) or imaginary-time (imag = 1) steady-state
@@ -157,8 +174,11 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* ctx, int32_t imag, int64_t n,
  * default), or SGPE_SPLIT_RKR, one step = R(dt/2) K(dt) R(dt/2).  real_space: SGPE_RSPLIT_FROZEN,
  * R(h) = one closed-form 2x2 exponential of H_R with the densities of its input (the default), or
  * SGPE_RSPLIT_NLN, R(h) = N(h/2) L(h) N(h/2) with N the mean-field phase (Eq. H3) with the densities
- * of its input and L the exponential of the linear real-space terms (Eqs. H2, H4) -- second order
- * also when g_uu != g_dd and a spatial Raman coupling is present.  Imaginary time normalises after
+ * of its input and L the exponential of the linear real-space terms (Eqs. H2, H4).  The frozen
+ * form is the exact real-space sub-flow when there is no spatial Raman coupling, or when
+ * g_uu = g_dd = g_ud (the mean field is then a multiple of the total density, which the coupling
+ * conserves); otherwise it is first order in the mean-field coupling, and N L N keeps the step
+ * second order.  Imaginary time normalises after
  * every step in every variant.  Cost per step: two sweeps, except R-K-R in imaginary time (three:
  * the norm is needed between the two R halves of consecutive steps).  The variants run the
  * general row pass without prefetching; sgpe_profile_steps and sgpe_profile_kernels measure the
@@ -209,6 +229,24 @@ sgpe_status sgpe_population_radius(sgpe_ctx* ctx, double fraction, double* radiu
  * n: int32[2] (up, down); raw: double[2] or NULL.  Synchronises.
  * Errors: SGPE_EINVAL (NULL n, radius not in (0, min(xmax, ymax))), SGPE_ESTATE (no state). */
 sgpe_status sgpe_winding(sgpe_ctx* ctx, double radius, int32_t* n, double* raw);
+
+/* Measurement helper: the memory floor of a step's data movement (no arithmetic).  The row pass
+ * and the column pass of a step (the two sweeps of the fused schedule of Sec. 3.2's split step)
+ * partition the grid among workgroups by rows, then by columns.  This probe copies an nx x ny grid
+ * of 16-byte points between two buffers of its own, alternating the two partitions: each point
+ * stays at its address, and what alternates is which workgroup (and so which XCD) reads and writes
+ * it.  Each lane moves the 16 eight-byte values its transform would own.
+ *   layout_rows L (1, 2, 4, 8): point (x, y) at index ((y / L) nx + x) L + y % L (L = 1: the
+ *                 state's [ny][nx] layout; larger L makes L rows of a column contiguous);
+ *   row_tile:     rows per row-partition workgroup; col_tile: columns per column-partition
+ *                 workgroup (2 row_tile nx / 16 and 2 col_tile ny / 16 threads, at most 1024);
+ *   write_through: device-scope stores, as the single-instance step kernels use.
+ * One untimed round, then reps rounds; row_ms / col_ms (either may be NULL) receive the mean
+ * HIP-event duration of one launch of each partition.  Allocates and frees its buffers on the
+ * current device, synchronises.  Errors: SGPE_EINVAL (sizes not powers of two, out of range, or a
+ * workgroup above 1024 threads), SGPE_ENOMEM, SGPE_EDEVICE. */
+sgpe_status sgpe_probe_exchange(int32_t nx, int32_t ny, int32_t layout_rows, int32_t row_tile, int32_t col_tile,
+                                int32_t write_through, int32_t reps, double* row_ms, double* col_ms);
 
 /* Static description of a status code.  Never NULL. */
 const char* sgpe_strerror(sgpe_status s);

@@ -309,6 +309,7 @@ sgpe::RowArgsT<T> row_args_t(const sgpe_ctx* c, double h_sub) {
   a.hg_uu = T(h * p.g_uu);
   a.hg_dd = T(h * p.g_dd);
   a.hg_ud = T(h * p.g_ud);
+  a.nonfinite = c->status_dev;
   return a;
 }
 
@@ -427,7 +428,12 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
 //   R-K-R, real time:       row (R(dt/2), fwd-x); n x [col K(dt); row (inv-x, R(dt/2), R(dt/2), fwd-x)],
 //                           the last row pass (inv-x, R(dt/2)) only;
 //   R-K-R, imaginary time:  the norm falls between the two R halves, so each step's row work takes
-//                           two passes: (inv-x, R(dt/2), norm partials) and (scale, R(dt/2), fwd-x).
+//                           two passes: (inv-x, R(dt/2), norm partials) that stores nothing, then
+//                           (inv-x, R(dt/2), scale, R(dt/2), fwd-x).  The second recomputes the
+//                           first's R(dt/2) from the same input with the same code, so the partials
+//                           belong to exactly the state it rescales, and no intermediate state is
+//                           stored (one complex64 rounding fewer per step, and 48 instead of 64 bytes
+//                           per point of row traffic).
 static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag) {
   if (n == 0) return SGPE_OK;
   const sgpe_params& p = c->p;
@@ -445,7 +451,7 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag) {
     r.var_flags = flags;
     r.var_r = nr;
     r.var_nln = rs;
-    r.scale = (flags & sgpe::VAR_INV) ? inv_n : 1.0f;
+    r.scale = (flags & sgpe::VAR_INV) ? inv_n : 1.0f;   // with VAR_MID_SCALE: the inverse's 1/N only
     r.partials = parts;
     r.n_partials = nparts;
     if (real_space_parts) {
@@ -486,11 +492,44 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag) {
     if (!imag) {
       row(h, last ? sgpe::VAR_INV : (sgpe::VAR_INV | sgpe::VAR_FWD), last ? 1 : 2, nullptr, 0, false);
     } else {
-      row(h, sgpe::VAR_INV | sgpe::VAR_NORM_OUT, 1, nullptr, 0, false);
-      row(h, last ? sgpe::VAR_SCALE : (sgpe::VAR_SCALE | sgpe::VAR_FWD), last ? 0 : 1, c->partials, row_groups, true);
+      row(h, sgpe::VAR_INV | sgpe::VAR_NORM_OUT | sgpe::VAR_NO_STORE, 1, nullptr, 0, false);
+      row(h, sgpe::VAR_INV | sgpe::VAR_MID_SCALE | (last ? 0 : sgpe::VAR_FWD), last ? 1 : 2, c->partials, row_groups,
+          true);
     }
   }
   return status_of(e);
+}
+
+EnergyArgs energy_args(const sgpe_ctx* c, double4* scratch, double* row_partials, double* col_partials) {
+  const sgpe_params& p = c->p;
+  EnergyArgs a{};
+  a.psi = c->psi;
+  a.psi64 = c->psi64;
+  a.scratch = scratch;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
+  a.twx = c->twd_x;
+  a.twy = c->twd_y;
+  a.xmin = -p.xmax;
+  a.dx = 2.0 * p.xmax / p.nx;
+  a.ymin = -p.ymax;
+  a.dy = 2.0 * p.ymax / p.ny;
+  a.wx2h = 0.5 * p.wx * p.wx;
+  a.wy2h = 0.5 * p.wy * p.wy;
+  a.delta = p.delta;
+  a.g_uu = p.g_uu;
+  a.g_dd = p.g_dd;
+  a.g_ud = p.g_ud;
+  a.k_l = p.k_l;
+  a.omega = p.omega;
+  a.om_x = c->full2x2 ? c->omx : nullptr;
+  a.om_y = c->full2x2 ? c->omy : nullptr;
+  a.dkx = M_PI / p.xmax;
+  a.dky = M_PI / p.ymax;
+  a.row_partials = row_partials;
+  a.col_partials = col_partials;
+  return a;
 }
 
 sgpe_status check_ctx(sgpe_ctx* c) {
@@ -502,13 +541,18 @@ sgpe_status check_ctx(sgpe_ctx* c) {
   return SGPE_OK;
 }
 
+sgpe_status latched_status(sgpe_ctx* c) {
+  if (c->status_host && __atomic_load_n(c->status_host, __ATOMIC_ACQUIRE) != 0u) c->latched = SGPE_ENONFINITE;
+  return c->latched;
+}
+
 sgpe_status sync_and_latch(sgpe_ctx* c) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return SGPE_EDEVICE;
   }
-  return c->latched;
+  return latched_status(c);
 }
 
 sgpe_status fetch_partials(sgpe_ctx* c, const double* dev, size_t n, const double** host) {
@@ -695,6 +739,21 @@ sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_st
   c->epart = static_cast<double*>(ptr);
   if ((st = dev_alloc(c, &ptr, sgpe::norm_blocks() * sizeof(double))) != SGPE_OK) return fail(st);
   c->npart = static_cast<double*>(ptr);
+  {
+    void* hptr = nullptr;
+    void* dptr = nullptr;
+    if (hipHostMalloc(&hptr, sizeof(unsigned int), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SGPE_ENOMEM);
+    }
+    c->status_host = static_cast<unsigned int*>(hptr);
+    *c->status_host = 0u;
+    if (hipHostGetDevicePointer(&dptr, hptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SGPE_EDEVICE);
+    }
+    c->status_dev = static_cast<unsigned int*>(dptr);
+  }
   *out = c;
   return SGPE_OK;
 }
@@ -705,6 +764,7 @@ void sgpe_destroy(sgpe_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (void* ptr : c->allocations) (void)hipFree(ptr);
   if (c->host_part) (void)hipHostFree(c->host_part);
+  if (c->status_host) (void)hipHostFree(c->status_host);
   (void)hipGetLastError();
   delete c;
 }
@@ -768,6 +828,7 @@ sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {
   }
   c->has_state = true;
   c->latched = SGPE_OK;
+  if (c->status_host) __atomic_store_n(c->status_host, 0u, __ATOMIC_RELEASE);   // the stream is idle
   return SGPE_OK;
 }
 
@@ -807,7 +868,7 @@ sgpe_status sgpe_get_psi(sgpe_ctx* c, double* h) {
     return SGPE_EDEVICE;
   }
   if (!ok) c->latched = SGPE_ENONFINITE;
-  return c->latched;
+  return latched_status(c);
 }
 
 static sgpe_status step_common(sgpe_ctx* c, int64_t n, bool imag) {
@@ -844,7 +905,7 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
   const double dx = 2.0 * c->p.xmax / c->p.nx, dy = 2.0 * c->p.ymax / c->p.ny;
   *out = dx * dy * s;
   if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
-  return c->latched;
+  return latched_status(c);
 }
 
 sgpe_status sgpe_set_splitting(sgpe_ctx* c, int32_t order, int32_t real_space) {
@@ -874,36 +935,10 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
     c->scratch64 = static_cast<double4*>(ptr);
   }
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
-  EnergyArgs a{};
-  a.psi = c->psi;
-  a.psi64 = c->psi64;
-  a.scratch = c->scratch64;
-  a.nx = p.nx;
-  a.ny = p.ny;
-  a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
-  a.twx = c->twd_x;
-  a.twy = c->twd_y;
-  a.xmin = -p.xmax;
-  a.dx = dx;
-  a.ymin = -p.ymax;
-  a.dy = dy;
-  a.wx2h = 0.5 * p.wx * p.wx;
-  a.wy2h = 0.5 * p.wy * p.wy;
-  a.delta = p.delta;
-  a.g_uu = p.g_uu;
-  a.g_dd = p.g_dd;
-  a.g_ud = p.g_ud;
-  a.k_l = p.k_l;
-  a.omega = p.omega;
-  a.om_x = c->full2x2 ? c->omx : nullptr;
-  a.om_y = c->full2x2 ? c->omy : nullptr;
-  a.dkx = M_PI / p.xmax;
-  a.dky = M_PI / p.ymax;
   const int nrb = p.ny;  // one row per row-kernel workgroup
-  const int ncb = p.nx / a.cols;
   constexpr int RP = sgpe::kEnergyRowParts;
-  a.row_partials = c->epart;
-  a.col_partials = c->epart + RP * nrb;
+  EnergyArgs a = energy_args(c, c->scratch64, c->epart, c->epart + RP * nrb);
+  const int ncb = p.nx / a.cols;
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e != hipSuccess) return status_of(e);
   const double* part = nullptr;
@@ -921,7 +956,7 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   const double nrm = w * nr;
   *out = (w / double(npts) * ek + w * er) / nrm + w * ei * p.norm0 / (nrm * nrm);
   if (!std::isfinite(*out)) c->latched = SGPE_ENONFINITE;
-  return c->latched;
+  return latched_status(c);
 }
 
 sgpe_status sgpe_profile_steps(sgpe_ctx* c, int32_t imag, int64_t n, double* row_ms, double* col_ms) {
@@ -1009,7 +1044,7 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* c, int32_t imag, int64_t n, double* r
   }
   if (row_ms) *row_ms = double(a) / double(n);
   if (col_ms) *col_ms = double(b) / double(n);
-  return c->latched;
+  return latched_status(c);
 }
 
 }  // extern "C"

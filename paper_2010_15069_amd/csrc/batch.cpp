@@ -338,7 +338,13 @@ sgpe_status sgpe_batch_norm(sgpe_batch* b, int32_t index, double* n) {
 sgpe_status sgpe_batch_synchronize(sgpe_batch* b) {
   if (!b) return SGPE_EINVAL;
   if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
-  return hip_status(hipStreamSynchronize(b->stream));
+  const sgpe_status st = hip_status(hipStreamSynchronize(b->stream));
+  if (st != SGPE_OK) return st;
+  // an instance whose imaginary-time norm went non-finite is reported (and stays latched in it)
+  sgpe_status out = SGPE_OK;
+  for (sgpe_ctx* c : b->inst)
+    if (latched_status(c) != SGPE_OK && out == SGPE_OK) out = c->latched;
+  return out;
 }
 
 sgpe_status sgpe_batch_use_graph(sgpe_batch* b, int32_t on) {

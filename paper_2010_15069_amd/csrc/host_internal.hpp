@@ -58,6 +58,10 @@ struct sgpe_ctx {
   int split_rs = 0;         // sgpe_real_space_split
   bool has_state = false;
   sgpe_status latched = SGPE_OK;
+  // status word the step kernels set when an imaginary-time norm is not finite and positive:
+  // fine-grained pinned host memory, mapped into the device's address space
+  unsigned int* status_host = nullptr;
+  unsigned int* status_dev = nullptr;
   std::vector<void*> allocations;
   double* host_part = nullptr;   // pinned host copy of reduction partials, grown on demand
   size_t host_part_n = 0;
@@ -78,6 +82,9 @@ sgpe_schedule get_schedule(const sgpe_ctx* c);
 sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
+// Arguments of the energy kernels for the context's state, with the given fp64 scratch (nx*ny
+// points) and partial buffers (kEnergyRowParts per row, then one per column block).
+sgpe::EnergyArgs energy_args(const sgpe_ctx* c, double4* scratch, double* row_partials, double* col_partials);
 // Copies n doubles of reduction partials from the device into the context's pinned host buffer
 // (queued on the context's stream, which is then synchronised) and points *host at it.  Returns
 // SGPE_ENOMEM if the buffer cannot grow, SGPE_EDEVICE on a device error.  A pinned destination
@@ -87,5 +94,8 @@ sgpe_status fetch_partials(sgpe_ctx* c, const double* dev, size_t n, const doubl
 // use; waits for the stream's queued work before overwriting them.
 sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y);
 sgpe_status sync_and_latch(sgpe_ctx* c);
+// The context's latched status after the stream has been synchronised: folds in the status word
+// the step kernels set on a non-finite norm.
+sgpe_status latched_status(sgpe_ctx* c);
 
 }  // namespace sgpe_host

@@ -89,7 +89,7 @@ sgpe_status sgpe_add_noise(sgpe_ctx* c, const double* xi, double amplitude) {
     (void)hipGetLastError();
     return SGPE_EDEVICE;
   }
-  return c->latched;
+  return latched_status(c);
 }
 
 sgpe_status sgpe_phase_separation(sgpe_ctx* c, double* out) {
@@ -106,11 +106,11 @@ sgpe_status sgpe_phase_separation(sgpe_ctx* c, double* out) {
   if ((st = fetch_sums(c, nb, sgpe::kMomentParts, m)) != SGPE_OK) return st;
   if (!std::isfinite(m[0] + m[1] + m[2])) {
     c->latched = SGPE_ENONFINITE;
-    return c->latched;
+    return latched_status(c);
   }
   if (!(m[1] > 0.0) || !(m[2] > 0.0)) return SGPE_ESTATE;
   *out = 1.0 - m[0] / std::sqrt(m[1] * m[2]);
-  return c->latched;
+  return latched_status(c);
 }
 
 static sgpe_status disk_population(sgpe_ctx* c, double r2, double* out) {
@@ -135,7 +135,7 @@ sgpe_status sgpe_population_radius(sgpe_ctx* c, double fraction, double* radius)
   if ((st = disk_population(c, HUGE_VAL, &total)) != SGPE_OK) return st;
   if (!std::isfinite(total)) {
     c->latched = SGPE_ENONFINITE;
-    return c->latched;
+    return latched_status(c);
   }
   if (!(total > 0.0)) return SGPE_ESTATE;
   const double target = fraction * total;
@@ -149,7 +149,7 @@ sgpe_status sgpe_population_radius(sgpe_ctx* c, double fraction, double* radius)
     else lo = mid;
   }
   *radius = hi;
-  return c->latched;
+  return latched_status(c);
 }
 
 sgpe_status sgpe_winding(sgpe_ctx* c, double radius, int32_t* n, double* raw) {
@@ -169,7 +169,7 @@ sgpe_status sgpe_winding(sgpe_ctx* c, double radius, int32_t* n, double* raw) {
   if ((st = fetch_sums(c, 1, 2, w)) != SGPE_OK) return st;
   if (!std::isfinite(w[0]) || !std::isfinite(w[1])) {
     c->latched = SGPE_ENONFINITE;
-    return c->latched;
+    return latched_status(c);
   }
   n[0] = int32_t(std::lround(w[0]));
   n[1] = int32_t(std::lround(w[1]));
@@ -177,7 +177,7 @@ sgpe_status sgpe_winding(sgpe_ctx* c, double radius, int32_t* n, double* raw) {
     raw[0] = w[0];
     raw[1] = w[1];
   }
-  return c->latched;
+  return latched_status(c);
 }
 
 }  // extern "C"

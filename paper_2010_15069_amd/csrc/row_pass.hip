@@ -71,6 +71,16 @@ __device__ __forceinline__ decltype(A::scale) row_scale(const A& a, const double
   return static_cast<decltype(A::scale)>(sqrt(a.norm0 / norm) * a.inv_npts);
 }
 
+// A norm-derived scale that is not finite and positive means that the norm the partials gave was
+// zero, infinite or NaN (a diverging or overflowing imaginary-time run).  Workgroup 0 records it in
+// the context's status word; the host reports it at the next synchronising call.
+template <class A, class R>
+__device__ __forceinline__ void check_scale(const A& a, R s, int wg) {
+  if (a.partials != nullptr && a.nonfinite != nullptr && wg == 0 && threadIdx.x == 0 &&
+      !(s > R(0) && __builtin_isfinite(s)))
+    __hip_atomic_store(a.nonfinite, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // -------------------------------------------------------------------------------------------
 // Real-space exponential R(h) (Eqs. (H2)-(H4), densities of the input).  Each lane applies its
 // component's row of the 2x2 exponential to its value w; o is the partner lane's value at the
@@ -324,7 +334,10 @@ __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
       fwd_pass<N>(v, lds, t, tr);
     } else {
       inv_pass<N>(v, lds, t, tr);
-      if (it == 0) s = row_scale(a, pv);
+      if (it == 0) {
+        s = row_scale(a, pv);
+        check_scale(a, s, wg);
+      }
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
       if constexpr (MODE == ROW_STEP) {
@@ -375,15 +388,23 @@ __device__ __forceinline__ void row_var_body(const RowArgs& a, int wg) {
     for (int m = 0; m < P; ++m) hbx_r[m] = a.hbx[t + T * m] * a.hfrac;
     hb_row = a.hby[row] * a.hfrac;
   }
+  const bool mid = (flags & VAR_MID_SCALE) != 0;
   if (flags & (VAR_INV | VAR_SCALE)) {
     if (flags & VAR_INV) inv_pass<N>(v, lds, t, tr);
-    const float s = row_scale(a, pv);
+    const float s = mid ? a.scale : row_scale(a, pv);
+    if (!mid) check_scale(a, s, wg);
 #pragma unroll
     for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
   }
   for (int r = 0; r < a.var_r; ++r) {
     if (a.var_nln) row_apply_r_nln<N, IMAG, FULL>(v, a, row, t, comp == 0, hbx_r, hb_row);
     else row_apply_r<N, IMAG, FULL>(v, a, row, t, comp == 0, hbx_r, hb_row);
+    if (mid && r == 0) {
+      const float c = row_scale(a, pv);
+      check_scale(a, c, wg);
+#pragma unroll
+      for (int m = 0; m < P; ++m) v[m] = vscale(v[m], c);
+    }
   }
   if (flags & VAR_NORM_OUT) {
     double acc = 0.0;
@@ -393,8 +414,10 @@ __device__ __forceinline__ void row_var_body(const RowArgs& a, int wg) {
     if (tid == 0) a.partials_out[wg] = acc;
   }
   if (flags & VAR_FWD) fwd_pass<N>(v, lds, t, tr);
+  if (!(flags & VAR_NO_STORE)) {
 #pragma unroll
-  for (int m = 0; m < P; ++m) store_state<true>(reinterpret_cast<float2*>(out + (off + 16u * T * m)), v[m]);
+    for (int m = 0; m < P; ++m) store_state<true>(reinterpret_cast<float2*>(out + (off + 16u * T * m)), v[m]);
+  }
 }
 
 // Row groups are sized for 256 threads (row_rows_per_block); only a 4096-point row at 16 points

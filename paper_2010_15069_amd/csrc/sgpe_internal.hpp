@@ -27,10 +27,13 @@ enum RowMode : int {
 // x-FFT and scale, or only the scale; var_r real-space sub-steps R(h) in turn (each in closed form
 // with frozen densities, or as N(h/2) L(h) N(h/2) when var_nln); the norm partial; forward x-FFT.
 enum RowVarFlags : int {
-  VAR_INV = 1,       // inverse x-FFT, then the scale (`scale`, or from the partials)
-  VAR_SCALE = 2,     // scale only, from the partials (the state is in real space on entry)
-  VAR_NORM_OUT = 4,  // one fp64 partial of sum |psi|^2 per workgroup into partials_out
-  VAR_FWD = 8,       // forward x-FFT
+  VAR_INV = 1,        // inverse x-FFT, then the scale (`scale`, or from the partials)
+  VAR_SCALE = 2,      // scale only, from the partials (the state is in real space on entry)
+  VAR_NORM_OUT = 4,   // one fp64 partial of sum |psi|^2 per workgroup into partials_out
+  VAR_FWD = 8,        // forward x-FFT
+  VAR_MID_SCALE = 16, // the scale after the inverse x-FFT is `scale`; the scale from the partials
+                      //   is applied after the first real-space sub-step instead
+  VAR_NO_STORE = 32,  // the state is not written back (a pass that only produces partials)
 };
 
 // Column (y) pass norm accumulation.
@@ -66,6 +69,10 @@ struct RowArgsT {
   int var_nln;               // 1: each R(h) as N(h/2) L(h) N(h/2)
   T hfrac;                   // h / dt: scales the hbx / hby tables (built for h = dt)
   double* partials_out;      // VAR_NORM_OUT: one double per workgroup
+  // Status word of the context (host-visible, fine-grained memory) or NULL: workgroup 0 of a
+  // pass that rescales by a norm from `partials` stores 1 there when that scale is not finite and
+  // positive (the norm was zero, infinite or NaN).  Read by the host at synchronising calls.
+  unsigned int* nonfinite;
 };
 using RowArgs = RowArgsT<float>;
 
@@ -154,6 +161,13 @@ hipError_t launch_winding(const float4* psi, int nx, int ny, double xmax, double
                           double* out, hipStream_t s);
 hipError_t launch_winding(const double4* psi, int nx, int ny, double xmax, double ymax, double radius, int m,
                           double* out, hipStream_t s);
+
+// Measurement probes (probes.hip): the data movement of the row and column partitions with no
+// arithmetic, on a layout with `layout_rows` interleaved rows (1 = the state's layout).
+hipError_t launch_probe_rows(const float4* src, float4* dst, int nx, int ny, int layout_rows, int row_tile,
+                             bool write_through, hipStream_t s);
+hipError_t launch_probe_cols(const float4* src, float4* dst, int nx, int ny, int layout_rows, int col_tile,
+                             bool write_through, hipStream_t s);
 
 // Workgroup geometry helpers (shared with the host so that partial counts match).
 // max_lds: the device's LDS bytes per workgroup (minus the kernels' static LDS).

@@ -189,3 +189,29 @@ def test_header_documents_precision_and_splitting_enums():
     for name in ("SGPE_C64 = 0", "SGPE_C128 = 1", "SGPE_SPLIT_KRK = 0", "SGPE_SPLIT_RKR = 1",
                  "SGPE_RSPLIT_FROZEN = 0", "SGPE_RSPLIT_NLN = 1"):
         assert name in h, name
+
+
+def _comment_before(decl_name):
+    """The comment block that ends right before the declaration of decl_name."""
+    text = open(HEADER).read()
+    m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*(?:typedef[^;]*;\s*)*(?:sgpe_status|void|int32_t|const char\*)\s+"
+                  + decl_name + r"\s*\(", text, flags=re.S)
+    assert m, decl_name
+    return m.group(1)
+
+
+@pytest.mark.parametrize("name", ["sgpe_create", "sgpe_create_ex", "sgpe_set_psi", "sgpe_get_psi",
+                                  "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
+                                  "sgpe_synchronize", "sgpe_set_splitting", "sgpe_set_raman_profile",
+                                  "sgpe_add_noise", "sgpe_phase_separation", "sgpe_winding"])
+def test_boundary_calls_cite_the_paper(name):
+    # every call of the solver boundary names the passage that defines what it computes
+    doc = _comment_before(name)
+    assert re.search(r"\b(Sec\.|Eq\.|Eqs\.)", doc), f"{name}: no citation in {doc!r}"
+
+
+def test_header_documents_the_nonfinite_latch():
+    h = open(HEADER).read()
+    assert "SGPE_ENONFINITE" in _comment_before("sgpe_synchronize")
+    assert "clears" in _comment_before("sgpe_set_psi").lower()
+    assert "status word" in h

@@ -156,12 +156,15 @@ def test_trial_protocol_matches_the_oracle(Solver):
     n, seed, ratio = 128, 7, 0.3
     res = run_trial(ratio=ratio, seed=seed, n=n, segments=(600, 300), anneal_every=200, n_vortices=8,
                     return_psi=True)
+    # unequal couplings with a spatial Raman profile: the driver takes the N L N real-space split
+    assert res["real_space"] == "nln"
     # the same protocol on the oracle: anneal after 200 and 400 steps with amplitudes
     # amp0 (1 - 1/3) and amp0 (1 - 2/3) (the third anneal has amplitude zero), 300 plain steps
     p = spin_hall_params(n=n, ratio=ratio)
     psi0 = vortex_state(p, n_vortices=8, seed=seed)
     amp0 = 0.05 * float(np.abs(psi0).max())
     o = OracleGPE(p, workers=WORKERS)
+    o.set_splitting("krk", "nln")
     o.set_raman_profile(None, spin_hall_profile(p))
     o.set_psi(psi0)
     for k, amp in enumerate((amp0 * 2 / 3, amp0 / 3)):
