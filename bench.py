@@ -34,6 +34,23 @@ BYTES_PER_POINT_PASS = 32      # one pass reads and writes both complex64 compon
 BYTES_PER_POINT_STEP = 64      # two passes per step
 IMAG_DT = 1e-3                 # imaginary-time step of the throughput workload
 
+# The paper's own timings for this path (Sec. 5, Fig. 2 and Fig. 3; hardware of Table 1; Sec. 6),
+# quoted as context: complex128 PyTorch/cuFFT on 2015-2018 NVIDIA GPUs, not a target.
+PAPER_CONTEXT = {
+    "precision": "complex128 (PyTorch tensors, cuFFT)",
+    "step_time_fit": "GPU step time ~ theta N + offset with theta = 9.7(1)e-8 s per grid point "
+                     "(Fig. 2); about 0.10 s per step at N = 1024^2",
+    "cpu_exponent": "CPU step time ~ N^kappa, kappa = 1.03(3) (Fig. 2)",
+    "max_speedup_gpu_vs_cpu": [6.3, 36, 85],
+    "break_even": "GPU and CPU step times equal near N = 2^12 grid points",
+    "spin_hall_trial": "about 45 minutes per trial (1024^2 x 2, 2 x 60000 imaginary-time steps) on the "
+                       "Titan V, about a day estimated on the i9-9900K (Sec. 6)",
+    "hardware": {"GeForce MX150": "384 cores, 2 GB, 48.06 GB/s",
+                 "GeForce GTX 980 Ti": "2816 cores, 6 GB, 336.6 GB/s",
+                 "Titan V": "5120 cores, 12 GB, 651.3 GB/s",
+                 "CPUs": "i5-7200U, FX-6300, i9-9900K"},
+}
+
 
 _T0 = time.perf_counter()
 
@@ -366,6 +383,30 @@ def spin_hall_trial(torch):
     return res
 
 
+def exchange_floor():
+    """The arithmetic-free copy with the two passes' data movement, per layout and tile: mean
+    microseconds per launch of each partition, and the bandwidth of a row + column pair on the
+    algorithmic bytes (32 B per point per launch)."""
+    from paper_2010_15069_amd import probe_exchange
+    out = []
+    for n in (512, 1024, 2048):
+        configs = []
+        for L, rt, ct in [(1, 1, 1), (1, 1, 2), (1, 1, 4), (1, 1, 8), (1, 2, 4), (2, 2, 2), (2, 2, 4),
+                          (2, 1, 4), (4, 4, 1), (4, 4, 2), (4, 1, 2), (4, 2, 2), (8, 8, 1), (8, 1, 1), (8, 2, 1)]:
+            if 2 * rt * (n // 16) > 1024 or 2 * ct * (n // 16) > 1024:
+                continue
+            configs.append((L, rt, ct))
+        for L, rt, ct in configs:
+            for wt in (True, False):
+                r, c = probe_exchange(n, n, L, rt, ct, wt, reps=40)
+                gbs = 2 * 32.0 * n * n / ((r + c) * 1e-3) / 1e9
+                rec = {"n": n, "layout_rows": L, "row_tile": rt, "col_tile": ct, "write_through": wt,
+                       "row_us": round(1e3 * r, 3), "col_us": round(1e3 * c, 3), "pair_GBps": round(gbs, 1)}
+                out.append(rec)
+                print(json.dumps(rec), flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,9 +420,14 @@ def main():
     ap.add_argument("--no-other-grids", action="store_true", help="skip the 512^2 and 2048^2 lines")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched parameter sweep")
     ap.add_argument("--no-spin-hall", action="store_true", help="skip the spin-Hall trial")
-    ap.add_argument("--ground-2048", type=int, default=0, metavar="MAX_STEPS",
-                    help="also run the 2048^2 ground state to |dE|/E < 1e-9 per 10 steps (at most MAX_STEPS)")
+    ap.add_argument("--ground-2048", type=int, default=60000, metavar="MAX_STEPS",
+                    help="the 2048^2 ground state to |dE|/E < 1e-9 per 10 steps, at most MAX_STEPS (0: skip)")
     ap.add_argument("--workload", default="metric_1024")
+    ap.add_argument("--heldout-sets", type=int, default=256,
+                    help="held-out parameter sets of the learned-start comparison (256 in the workload)")
+    ap.add_argument("--exchange-floor", action="store_true",
+                    help="only measure the arithmetic-free copy with a step's data movement "
+                         "(sgpe_probe_exchange) over layouts and tiles at 512^2-2048^2, print JSON, exit")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -392,6 +438,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.exchange_floor:
+        exchange_floor()
+        return
 
     if args.copy_reference:
         n = args.copy_reference * (1 << 20) // 4
@@ -445,16 +495,20 @@ def main():
     med_r, mad_r = median_mad(per_r)
     s_real.close()
 
-    # Dominant kernel's launch duration in the real (alternating) schedule: HIP events around
-    # every launch of 200 further steps give each pass's duration plus the events' own overhead;
-    # that overhead per launch is what the event-bracketed steps take beyond the plain timed
-    # region's step time, and is taken off both passes alike.
-    step_ms = total_ms / args.steps
+    # Dominant kernel's launch duration in the real (alternating) schedule.  The steady-state step
+    # time is the difference of two timed calls (one HIP event pair each, on the solver's stream),
+    # step_imag(n + 1000) and step_imag(n), over 1000: the call boundary's sweeps (the first x
+    # transform and half K, the last inverse x transform) cancel.  HIP events around every launch
+    # of 200 further steps split that time between the two passes (the events' own overhead is
+    # the same for both launches, so only their ratio is used).
     s.set_psi(psi0)
     s.step_imag(20)
+    t_short, _ = timed(s.step_imag, 200, 200)
+    t_long, _ = timed(s.step_imag, 1200, 1200)
+    steady_ms = (t_long - t_short) / 1000.0
     ev_row, ev_col = s.profile_steps(200, imag=True)
-    overhead = max(0.0, (ev_row + ev_col - step_ms) / 2.0)
-    row_ms, col_ms = ev_row - overhead, ev_col - overhead
+    row_ms = steady_ms * ev_row / (ev_row + ev_col)
+    col_ms = steady_ms * ev_col / (ev_row + ev_col)
     dom_name, dom_ms = ("col_pass", col_ms) if col_ms >= row_ms else ("row_pass", row_ms)
     alg_bytes = BYTES_PER_POINT_PASS * npts
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
@@ -483,12 +537,24 @@ def main():
             "grid": [p.ny, p.nx], "components": 2, "dt": p_imag.dt, "dt_real": p.dt,
             "batch": args.batch,
         },
-        "step_ms_median": med, "step_ms_mad": mad,
+        # one batch (K <= batch): a single timed call, whose time includes the call boundary's
+        # sweeps (2K + 2 sweeps for K steps); no spread to report
+        "step_ms_median": med, "step_ms_mad": mad if len(per) > 1 else None,
+        "timed_calls": len(per),
+        "note": f"the timed region is {len(per)} step_imag call(s) of at most {args.batch} steps; each call runs "
+                f"2n + 2 sweeps for n steps (the first x transform with half K, and the last inverse x "
+                f"transform, belong to the call)",
         "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts * value / (HBM_PEAK_GBS * 1e9),
+        "steady_state": {"step_ms": steady_ms, "split_steps_per_s": 1e3 / steady_ms,
+                         "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts / (steady_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                         "method": "(time of step_imag(1200) - time of step_imag(200)) / 1000, one event pair each"},
         "real_time": {"value": args.steps / (total_r * 1e-3), "unit": "split-steps/s",
-                      "step_ms_median": med_r, "step_ms_mad": mad_r},
-        "kernels_ms": {"row_pass": row_ms, "col_pass": col_ms, "event_overhead_per_launch": overhead,
-                       "method": "per-launch HIP events, less the events' own overhead"},
+                      "step_ms_median": med_r, "step_ms_mad": mad_r if len(per_r) > 1 else None},
+        "kernels_ms": {"row_pass": row_ms, "col_pass": col_ms,
+                       "per_launch_events": {"row_pass": ev_row, "col_pass": ev_col},
+                       "method": "steady-state step time split between the passes in the ratio of "
+                                 "per-launch HIP event durations"},
+        "paper_context": PAPER_CONTEXT,
         "energy_after_timed_steps": e_final,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -508,11 +574,12 @@ def main():
         progress("ground state 256^2")
         if args.ground_2048:
             out["ground_2048"] = ground_2048_convergence(torch, stream, max_steps=args.ground_2048)
+            progress("ground state 2048^2")
         model = _load_surrogate(torch)
         if model is not None:
             out["ground_state"]["learned_start"] = ground_state_learned(torch, stream, model)
             if not args.no_batch:
-                out["learned_start_sweep"] = learned_start_sweep(torch, stream, model)
+                out["learned_start_sweep"] = learned_start_sweep(torch, stream, model, n_sets=args.heldout_sets)
             del model
             progress("learned start")
     if not args.no_batch:

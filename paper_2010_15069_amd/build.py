@@ -91,10 +91,15 @@ def build(verbose: bool = False) -> str:
     with tempfile.TemporaryDirectory(prefix="sgpe_build_") as tmp:
         objs = []
         jobs = []
-        for src in ("row_pass.hip", "col_pass.hip", "reductions.hip", "observables.hip"):
+        # every HIP source (kernels, and host code that must share a translation unit with them)
+        # and every host-only C++ source of csrc/; the largest first, so that it starts first
+        hip_srcs = sorted((f for f in os.listdir(CSRC) if f.endswith(".hip")),
+                          key=lambda f: -os.path.getsize(os.path.join(CSRC, f)))
+        cpp_srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".cpp"))
+        for src in hip_srcs:
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             jobs.append(([hipcc, "-c"] + HIP_FLAGS + incs + [os.path.join(CSRC, src), "-o", obj], obj))
-        for src in ("api.cpp", "batch.cpp", "observables_api.cpp"):
+        for src in cpp_srcs:
             obj = os.path.join(tmp, src.replace(".cpp", ".o"))
             jobs.append(([hipcc, "-c", "-x", "c++"] + HOST_FLAGS + incs +
                          [os.path.join(CSRC, src), "-o", obj], obj))

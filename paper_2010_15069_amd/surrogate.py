@@ -13,8 +13,10 @@ Model (one instance of the neural-operator family: lift, Fourier layers, project
     mode with a learned complex matrix, and W is pointwise linear;
   * project: pointwise linear (width -> 128 -> 4): re and im of the up and down components;
   * the output is normalised to the atom number.
-The spectral channel mixing is one batched complex matrix product over the kept modes; the
-pointwise layers run under bfloat16 autocast (matrix cores) with fp32 accumulation.
+On the GPU every channel mixing runs on the bfloat16 matrix cores with fp32 accumulation: the
+pointwise layers under bfloat16 autocast, and the spectral mixing as one batched real product that
+holds the complex one ([re a | im a] times the real 2x2-block form of the complex weight).  On the
+host the spectral mixing stays a complex fp32 product.
 
 Training minimises the phase-invariant infidelity 1 - |<p, t>|^2 / (<p, p> <t, t>) between the
 predicted and the relaxed states (both components, one global phase), so the arbitrary global phase
@@ -67,6 +69,23 @@ def to_channels(psi_list, device) -> torch.Tensor:
     return torch.from_numpy(a).to(device)
 
 
+def spectral_mix(a: torch.Tensor, wmat: torch.Tensor, bf16: bool) -> torch.Tensor:
+    """Batched complex product (M, b, cin) @ (M, cin, cout).  bf16: on the bfloat16 matrix cores
+    with fp32 accumulation, as one real product [re a | im a] (b x 2 cin) @ [[re W, im W],
+    [-im W, re W]] (2 cin x 2 cout); else a complex fp32 product."""
+    cout = wmat.shape[-1]
+    if not bf16:
+        return torch.bmm(a.contiguous(), wmat.contiguous())
+    ar = torch.cat([a.real, a.imag], dim=-1).to(torch.bfloat16).contiguous()
+    wr = torch.cat([torch.cat([wmat.real, wmat.imag], dim=-1),
+                    torch.cat([-wmat.imag, wmat.real], dim=-1)], dim=1).to(torch.bfloat16).contiguous()
+    if ar.device.type == "cuda":
+        pr = torch.bmm(ar, wr, out_dtype=torch.float32)   # fp32 result of the fp32 accumulation
+    else:
+        pr = torch.bmm(ar, wr).float()                    # the host's bf16 product rounds its result
+    return torch.complex(pr[..., :cout], pr[..., cout:])
+
+
 class SpectralConv2d(torch.nn.Module):
     """Channel mixing of the lowest modes x modes Fourier modes (k_y of both signs)."""
 
@@ -83,9 +102,10 @@ class SpectralConv2d(torch.nn.Module):
         uh = torch.fft.rfft2(u.float())                                   # (b, c, h, w//2+1)
         sel = torch.cat([uh[:, :, :m, :m], uh[:, :, h - m:, :m]], dim=2)  # (b, c, 2m, m)
         # per mode: (b, cin) @ (cin, cout) as one batched product over the 2m*m modes
-        a = sel.permute(2, 3, 0, 1).reshape(2 * m * m, b, c).contiguous()
-        wmat = self.weight.reshape(2 * m * m, c, self.cout).contiguous()
-        prod = torch.bmm(a, wmat).reshape(2 * m, m, b, self.cout).permute(2, 3, 0, 1)
+        a = sel.permute(2, 3, 0, 1).reshape(2 * m * m, b, c)
+        wmat = self.weight.reshape(2 * m * m, c, self.cout)
+        prod = spectral_mix(a, wmat, bf16=(u.device.type == "cuda"))
+        prod = prod.reshape(2 * m, m, b, self.cout).permute(2, 3, 0, 1)
         out = torch.zeros(b, self.cout, h, w // 2 + 1, dtype=torch.cfloat, device=u.device)
         out[:, :, :m, :m] = prod[:, :, :m]
         out[:, :, h - m:, :m] = prod[:, :, m:]

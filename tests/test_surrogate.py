@@ -69,3 +69,24 @@ def test_encoding_and_prediction_shapes():
         dx = 2 * p.xmax / p.nx
         assert s.shape == (2, 32, 32)
         assert abs(dx * dx * np.sum(np.abs(s) ** 2) - p.norm0) < 1e-9
+
+
+def test_bf16_spectral_mix_is_the_complex_product():
+    # the GPU path's real-block bfloat16 form against the complex fp32 product
+    import torch
+    from paper_2010_15069_amd.surrogate import spectral_mix
+    g = torch.Generator().manual_seed(0)
+    a = torch.complex(torch.randn(12, 3, 32, generator=g), torch.randn(12, 3, 32, generator=g))
+    w = torch.complex(torch.randn(12, 32, 32, generator=g), torch.randn(12, 32, 32, generator=g)) / 32
+    ref = spectral_mix(a, w, bf16=False)
+    got = spectral_mix(a, w, bf16=True)
+    assert got.dtype == ref.dtype and got.shape == ref.shape
+    rel = float((got - ref).abs().max() / ref.abs().max())
+    assert rel < 3e-2, rel           # bfloat16 inputs: 8 significant bits
+    # with inputs exact in bfloat16 what remains is the rounding of the result (bfloat16 on the
+    # host; the GPU returns the fp32 accumulation)
+    a16 = torch.complex(a.real.bfloat16().float(), a.imag.bfloat16().float())
+    w16 = torch.complex(w.real.bfloat16().float(), w.imag.bfloat16().float())
+    rel16 = float((spectral_mix(a16, w16, bf16=True) - spectral_mix(a16, w16, bf16=False)).abs().max()
+                  / ref.abs().max())
+    assert rel16 < 4e-3, rel16
