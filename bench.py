@@ -327,11 +327,24 @@ def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_ever
     sp, tp = first(tr_p, ck_p)
     sl, tl = first(tr_l, ck_l)
     med = lambda v: float(np.median(v)) if v else None  # noqa: E731
+    # the first held-out sets against the FP64 oracle's converged energies
+    oracle_check = None
+    gpath = os.path.join(ROOT, "tests", "golden", "heldout_energies.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))["sets"]
+        k = min(len(gold), len(ps))
+        eo = np.array([g["energy"] for g in gold[:k]])
+        oracle_check = {"sets": k,
+                        "max_rel_error_plain_final": float(np.max(np.abs(tr_p[-1, :k] - eo) / np.abs(eo))),
+                        "max_rel_error_learned_final": float(np.max(np.abs(tr_l[-1, :k] - eo) / np.abs(eo))),
+                        "max_rel_error_e_ref": float(np.max(np.abs(e_ref[:k] - eo) / np.abs(eo)))}
     return {"workload": f"{n_sets} held-out sets (seed 2): 256^2, g ~ U[1,100] (all couplings), Omega ~ U[0,3], "
                         f"delta ~ U[-0.5,0.5], k_L = 2, dt = 1e-3; one batch per arm; energy every {check_every} steps",
             "max_steps": steps,
+            "e_ref": "per set, the lower of the two arms' final energies (the plain solver judges)",
             "plain": {"reached": len(sp), "steps_median": med(sp), "batch_seconds_median": med(tp)},
-            "learned": {"reached": len(sl), "steps_median": med(sl), "batch_seconds_median": med(tl)}}
+            "learned": {"reached": len(sl), "steps_median": med(sl), "batch_seconds_median": med(tl)},
+            "oracle_check": oracle_check}
 
 
 def splitting_variants(torch, stream, timed, p, p_imag, psi0, steps=600, warmup=30):
@@ -385,23 +398,27 @@ def spin_hall_trial(torch):
 
 def exchange_floor():
     """The arithmetic-free copy with the two passes' data movement, per layout and tile: mean
-    microseconds per launch of each partition, and the bandwidth of a row + column pair on the
-    algorithmic bytes (32 B per point per launch)."""
+    microseconds per launch of each partition (events between launches), per row + column round
+    back to back, and the bandwidth of a round on the algorithmic bytes (32 B per point per launch).
+    Tiles as the step kernels' lanes hold them (a lane pair per point), and wave-local (a wave per
+    row or column, both components per lane)."""
     from paper_2010_15069_amd import probe_exchange
     out = []
     for n in (512, 1024, 2048):
         configs = []
-        for L, rt, ct in [(1, 1, 1), (1, 1, 2), (1, 1, 4), (1, 1, 8), (1, 2, 4), (2, 2, 2), (2, 2, 4),
-                          (2, 1, 4), (4, 4, 1), (4, 4, 2), (4, 1, 2), (4, 2, 2), (8, 8, 1), (8, 1, 1), (8, 2, 1)]:
+        for L, rt, ct in [(1, 1, 2), (1, 1, 4), (1, 1, 8), (2, 2, 2), (2, 2, 4), (4, 4, 1), (4, 4, 2),
+                          (8, 8, 1)]:
             if 2 * rt * (n // 16) > 1024 or 2 * ct * (n // 16) > 1024:
                 continue
-            configs.append((L, rt, ct))
-        for L, rt, ct in configs:
+            configs.append((L, rt, ct, False))
+        for L, rt, ct in [(1, 1, 1), (1, 2, 4), (1, 4, 4), (4, 1, 1), (4, 4, 4), (8, 1, 1), (8, 2, 2), (8, 4, 4)]:
+            configs.append((L, rt, ct, True))
+        for L, rt, ct, wl in configs:
             for wt in (True, False):
-                r, c = probe_exchange(n, n, L, rt, ct, wt, reps=40)
-                gbs = 2 * 32.0 * n * n / ((r + c) * 1e-3) / 1e9
-                rec = {"n": n, "layout_rows": L, "row_tile": rt, "col_tile": ct, "write_through": wt,
-                       "row_us": round(1e3 * r, 3), "col_us": round(1e3 * c, 3), "pair_GBps": round(gbs, 1)}
+                r, c, pr = probe_exchange(n, n, L, rt, ct, wt, wl, reps=40)
+                rec = {"n": n, "layout_rows": L, "row_tile": rt, "col_tile": ct, "wave_local": wl,
+                       "write_through": wt, "row_us": round(1e3 * r, 3), "col_us": round(1e3 * c, 3),
+                       "round_us": round(1e3 * pr, 3), "round_GBps": round(2 * 32.0 * n * n / (pr * 1e-3) / 1e9, 1)}
                 out.append(rec)
                 print(json.dumps(rec), flush=True)
     return out

@@ -235,18 +235,24 @@ sgpe_status sgpe_winding(sgpe_ctx* ctx, double radius, int32_t* n, double* raw);
  * partition the grid among workgroups by rows, then by columns.  This probe copies an nx x ny grid
  * of 16-byte points between two buffers of its own, alternating the two partitions: each point
  * stays at its address, and what alternates is which workgroup (and so which XCD) reads and writes
- * it.  Each lane moves the 16 eight-byte values its transform would own.
+ * it.
  *   layout_rows L (1, 2, 4, 8): point (x, y) at index ((y / L) nx + x) L + y % L (L = 1: the
  *                 state's [ny][nx] layout; larger L makes L rows of a column contiguous);
- *   row_tile:     rows per row-partition workgroup; col_tile: columns per column-partition
- *                 workgroup (2 row_tile nx / 16 and 2 col_tile ny / 16 threads, at most 1024);
- *   write_through: device-scope stores, as the single-instance step kernels use.
- * One untimed round, then reps rounds; row_ms / col_ms (either may be NULL) receive the mean
- * HIP-event duration of one launch of each partition.  Allocates and frees its buffers on the
- * current device, synchronises.  Errors: SGPE_EINVAL (sizes not powers of two, out of range, or a
- * workgroup above 1024 threads), SGPE_ENOMEM, SGPE_EDEVICE. */
+ *   flags:        SGPE_PROBE_WRITE_THROUGH: device-scope stores, as the single-instance step kernels
+ *                 use; SGPE_PROBE_WAVE_LOCAL: a wave owns a whole row (column) with both components
+ *                 per lane, as transforms that run inside one wave would (lengths 512..2048);
+ *   row_tile, col_tile: rows per row-partition workgroup and columns per column-partition workgroup
+ *                 -- without WAVE_LOCAL each lane moves the 16 eight-byte values a lane of the step
+ *                 kernels owns (2 row_tile nx / 16 and 2 col_tile ny / 16 threads, at most 1024);
+ *                 with it, 1..8 waves (lines) per workgroup.
+ * One untimed round, then reps rounds with a HIP event after every launch (row_ms / col_ms: mean
+ * per launch of each partition, back to back with no host wait), then reps rounds between one event
+ * pair (pair_ms: mean per round, a row and a column launch).  Any output may be NULL.  Allocates
+ * and frees its buffers on the current device, synchronises.  Errors: SGPE_EINVAL (sizes not powers
+ * of two, out of range, unknown flags), SGPE_ENOMEM, SGPE_EDEVICE. */
+enum { SGPE_PROBE_WRITE_THROUGH = 1, SGPE_PROBE_WAVE_LOCAL = 2 };
 sgpe_status sgpe_probe_exchange(int32_t nx, int32_t ny, int32_t layout_rows, int32_t row_tile, int32_t col_tile,
-                                int32_t write_through, int32_t reps, double* row_ms, double* col_ms);
+                                int32_t flags, int32_t reps, double* row_ms, double* col_ms, double* pair_ms);
 
 /* Static description of a status code.  Never NULL. */
 const char* sgpe_strerror(sgpe_status s);

@@ -154,7 +154,8 @@ def _lib():
         "sgpe_winding": ([vp, ctypes.c_double, PI32, P(ctypes.c_double)], st),
         "sgpe_set_splitting": ([vp, i32, i32], st),
         "sgpe_create_ex": ([P(SgpeParams), i32, vp, vp, P(vp)], st),
-        "sgpe_probe_exchange": ([i32, i32, i32, i32, i32, i32, i32, P(ctypes.c_double), P(ctypes.c_double)], st),
+        "sgpe_probe_exchange": ([i32, i32, i32, i32, i32, i32, i32, P(ctypes.c_double), P(ctypes.c_double),
+                                 P(ctypes.c_double)], st),
     })
     for name, (args, res) in batch_sigs.items():
         f = getattr(lib, name)

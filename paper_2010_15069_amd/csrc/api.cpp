@@ -630,7 +630,9 @@ const char* sgpe_strerror(sgpe_status s) {
 // within the LDS (double2 slots take twice the bytes).
 static int c128_cols(int nx, int ny, size_t max_lds) {
   int c = 4;
-  while (c > 1 && (2 * c * (ny / 16) > 256 || !sgpe::col_cols_supported(nx, ny, c, 1, 16, max_lds / 2))) c >>= 1;
+  while (c > 1 && (2 * c * (ny / 16) > 256 || c > nx || nx % c != 0 || !sgpe::schedule_supported(ny, c, 1, 16) ||
+                   sgpe::col_lds_bytes_c128(ny, c) > max_lds))
+    c >>= 1;
   return c;
 }
 
@@ -677,7 +679,8 @@ sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_st
   }
   c->full2x2 = (p->omega_r0 != 0.0);
   const size_t wb = c128 ? 2 : 1;   // LDS bytes per slot relative to complex64
-  if (wb * sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || wb * sgpe::col_lds_bytes(p->ny, c->cols) > c->max_lds ||
+  const size_t col_lds = c128 ? sgpe::col_lds_bytes_c128(p->ny, c->cols) : sgpe::col_lds_bytes(p->ny, c->cols);
+  if (wb * sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || col_lds > c->max_lds ||
       !sgpe::energy_fits(p->nx, p->ny, c->max_lds)) {
     delete c;
     return SGPE_ENOMEM;

@@ -61,11 +61,15 @@ __device__ __forceinline__ void col_body(const ColArgsT<R>& a, int wg, int ngrou
   // them.  With 8 or 4 points per lane the lane's own P values are loaded into registers up front
   // instead (measured: 13.45 -> 13.07 us per step at 512^2; at 16 points per lane the extra
   // registers cost 1 us at 1024^2).
-  constexpr bool KY_LDS = P == 16;
+  // complex128 columns of 4096 points leave no LDS for the k_y row (the exchange slots take 139 KB):
+  // there each point's value is loaded after the forward transform, from the L2-resident table.
+  constexpr bool KY_GLOBAL = sizeof(R) == 8 && N >= 4096;
+  constexpr bool KY_LDS = P == 16 && !KY_GLOBAL;
   constexpr int KY_MAX = KY_LDS ? P / 2 : 1;
   const int nth = blockDim.x;
-  CX kyv[KY_MAX], kyr[KY_LDS ? 1 : P];
-  if constexpr (KY_LDS) {
+  CX kyv[KY_MAX], kyr[(KY_LDS || KY_GLOBAL) ? 1 : P];
+  if constexpr (KY_GLOBAL) {
+  } else if constexpr (KY_LDS) {
 #pragma unroll
     for (int k = 0; k < KY_MAX; ++k)
       if (k * nth < N) kyv[k] = a.ky_tab[min(tid + k * nth, N - 1)];
@@ -104,7 +108,8 @@ __device__ __forceinline__ void col_body(const ColArgsT<R>& a, int wg, int ngrou
       const CX w = v[m];
       const CX o = pair_swap(w);
       CX q;
-      if constexpr (KY_LDS) q = kyl[t + T * m];
+      if constexpr (KY_GLOBAL) q = a.ky_tab[t + T * m];
+      else if constexpr (KY_LDS) q = kyl[t + T * m];
       else q = kyr[m];
       const R c1r = fma_(-d.w, o.y, fma_(d.z, o.x, fma_(-d.y, w.y, d.x * w.x)));
       const R c1i = fma_(d.w, o.x, fma_(d.z, o.y, fma_(d.y, w.x, d.x * w.y)));
@@ -215,7 +220,7 @@ static hipError_t col_launch_c128(const ColArgsT<double>& a, hipStream_t s) {
   const dim3 block(2 * a.cols * (N / 16));
   const dim3 grid(a.nx / a.cols);
   if (block.x > (2 * N / 16 > 256 ? 512u : 256u)) return hipErrorInvalidValue;
-  const size_t lds = 2 * col_lds_bytes(N, a.cols);   // double2 slots and k_y row
+  const size_t lds = col_lds_bytes_c128(N, a.cols);   // double2 slots and (below 4096 points) the k_y row
   hipLaunchKernelGGL((col_kernel_c128<N, NORM>), grid, block, lds, s, a);
   return hipGetLastError();
 }

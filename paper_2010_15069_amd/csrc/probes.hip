@@ -64,6 +64,84 @@ __global__ void __launch_bounds__(1024) probe_cols(const float2* __restrict__ sr
   for (int m = 0; m < 16; ++m) store_state<WT>(&dst[2 * probe_index(x, t + tt * m, lnx, ll) + comp], v[m]);
 }
 
+// Wave-local variants: a wave owns one whole row (or column) with both spinor components per lane
+// (16-byte point loads), lane t holding the P = length / 64 positions t + 64 m; a workgroup of W
+// waves owns W adjacent rows (columns).  This is the access pattern of transforms that run inside
+// one wave.
+template <int P, bool WT>
+__device__ __forceinline__ void probe_line_wl(const float4* __restrict__ src, float4* __restrict__ dst, uint32_t fixed,
+                                              bool along_x, int lnx, int ll) {
+  const uint32_t t = threadIdx.x & 63u;
+  float4 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const uint32_t pos = t + 64u * m;
+    v[m] = src[along_x ? probe_index(pos, fixed, lnx, ll) : probe_index(fixed, pos, lnx, ll)];
+  }
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const uint32_t pos = t + 64u * m;
+    float4* q = &dst[along_x ? probe_index(pos, fixed, lnx, ll) : probe_index(fixed, pos, lnx, ll)];
+    if constexpr (WT) {
+      store_through(reinterpret_cast<float2*>(q), make_float2(v[m].x, v[m].y));
+      store_through(reinterpret_cast<float2*>(q) + 1, make_float2(v[m].z, v[m].w));
+    } else {
+      *q = v[m];
+    }
+  }
+}
+
+template <int P, bool WT>
+__global__ void __launch_bounds__(512) probe_rows_wl(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     int lnx, int ll) {
+  const uint32_t y = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  probe_line_wl<P, WT>(src, dst, y, true, lnx, ll);
+}
+
+template <int P, bool WT>
+__global__ void __launch_bounds__(512) probe_cols_wl(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     int lnx, int ll) {
+  const int ng = gridDim.x;
+  const int w = (ng & 7) == 0 ? (blockIdx.x & 7) * (ng >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+  const uint32_t x = uint32_t(w) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  probe_line_wl<P, WT>(src, dst, x, false, lnx, ll);
+}
+
+template <int P>
+static hipError_t probe_wl_launch(bool rows, const float4* src, float4* dst, int nx, int ny, int layout_rows,
+                                  int waves, bool wt, hipStream_t s) {
+  const int lnx = __builtin_ctz(nx), ll = __builtin_ctz(layout_rows);
+  const dim3 block(64 * waves), grid((rows ? ny : nx) / waves);
+  if (rows) {
+    if (wt) hipLaunchKernelGGL((probe_rows_wl<P, true>), grid, block, 0, s, src, dst, lnx, ll);
+    else hipLaunchKernelGGL((probe_rows_wl<P, false>), grid, block, 0, s, src, dst, lnx, ll);
+  } else {
+    if (wt) hipLaunchKernelGGL((probe_cols_wl<P, true>), grid, block, 0, s, src, dst, lnx, ll);
+    else hipLaunchKernelGGL((probe_cols_wl<P, false>), grid, block, 0, s, src, dst, lnx, ll);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t probe_wl(bool rows, const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
+                           bool wt, hipStream_t s) {
+  switch (rows ? nx : ny) {
+    case 512: return probe_wl_launch<8>(rows, src, dst, nx, ny, layout_rows, waves, wt, s);
+    case 1024: return probe_wl_launch<16>(rows, src, dst, nx, ny, layout_rows, waves, wt, s);
+    case 2048: return probe_wl_launch<32>(rows, src, dst, nx, ny, layout_rows, waves, wt, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_probe_rows_wl(const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
+                                bool write_through, hipStream_t s) {
+  return probe_wl(true, src, dst, nx, ny, layout_rows, waves, write_through, s);
+}
+
+hipError_t launch_probe_cols_wl(const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
+                                bool write_through, hipStream_t s) {
+  return probe_wl(false, src, dst, nx, ny, layout_rows, waves, write_through, s);
+}
+
 hipError_t launch_probe_rows(const float4* src, float4* dst, int nx, int ny, int layout_rows, int row_tile,
                              bool write_through, hipStream_t s) {
   const int lnx = __builtin_ctz(nx), ll = __builtin_ctz(layout_rows), lr = __builtin_ctz(row_tile);

@@ -168,6 +168,12 @@ hipError_t launch_probe_rows(const float4* src, float4* dst, int nx, int ny, int
                              bool write_through, hipStream_t s);
 hipError_t launch_probe_cols(const float4* src, float4* dst, int nx, int ny, int layout_rows, int col_tile,
                              bool write_through, hipStream_t s);
+// the same with a wave owning a whole row (column), both components per lane; `waves` lines per
+// workgroup; lengths 512, 1024, 2048
+hipError_t launch_probe_rows_wl(const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
+                                bool write_through, hipStream_t s);
+hipError_t launch_probe_cols_wl(const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
+                                bool write_through, hipStream_t s);
 
 // Workgroup geometry helpers (shared with the host so that partial counts match).
 // max_lds: the device's LDS bytes per workgroup (minus the kernels' static LDS).
@@ -178,6 +184,7 @@ bool energy_fits(int nx, int ny, size_t max_lds);
 int energy_cols_per_block(int nx, int ny, size_t max_lds);
 size_t row_lds_bytes(int nx, int rows);
 size_t col_lds_bytes(int ny, int cols);
+size_t col_lds_bytes_c128(int ny, int cols);
 int norm_blocks();
 
 }  // namespace sgpe

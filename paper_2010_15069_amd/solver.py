@@ -304,11 +304,13 @@ def validate_params(params) -> int:
     return int(lib().sgpe_validate_params(ctypes.byref(p)))
 
 
-def probe_exchange(nx, ny, layout_rows=1, row_tile=1, col_tile=4, write_through=True, reps=50):
-    """sgpe_probe_exchange: mean milliseconds of one (row-partition, column-partition) launch of the
-    arithmetic-free copy with a step's data movement (see include/sgpe.h)."""
-    r, c = ctypes.c_double(), ctypes.c_double()
-    check(lib().sgpe_probe_exchange(int(nx), int(ny), int(layout_rows), int(row_tile), int(col_tile),
-                                    int(bool(write_through)), int(reps), ctypes.byref(r), ctypes.byref(c)),
+def probe_exchange(nx, ny, layout_rows=1, row_tile=1, col_tile=4, write_through=True, wave_local=False, reps=50):
+    """sgpe_probe_exchange: mean milliseconds of (row-partition launch, column-partition launch,
+    row + column round back to back) of the arithmetic-free copy with a step's data movement (see
+    include/sgpe.h)."""
+    r, c, pr = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    flags = (1 if write_through else 0) | (2 if wave_local else 0)
+    check(lib().sgpe_probe_exchange(int(nx), int(ny), int(layout_rows), int(row_tile), int(col_tile), flags,
+                                    int(reps), ctypes.byref(r), ctypes.byref(c), ctypes.byref(pr)),
           "sgpe_probe_exchange")
-    return r.value, c.value
+    return r.value, c.value, pr.value

@@ -215,3 +215,13 @@ def test_header_documents_the_nonfinite_latch():
     assert "SGPE_ENONFINITE" in _comment_before("sgpe_synchronize")
     assert "clears" in _comment_before("sgpe_set_psi").lower()
     assert "status word" in h
+
+
+def test_probe_rejects_invalid_arguments_before_device_work(lib):
+    d = ctypes.c_double()
+    assert lib.sgpe_probe_exchange(1000, 1024, 1, 1, 4, 0, 10, None, None, None) == 1   # not a power of two
+    assert lib.sgpe_probe_exchange(1024, 1024, 3, 1, 4, 0, 10, None, None, None) == 1   # layout
+    assert lib.sgpe_probe_exchange(1024, 1024, 1, 1, 4, 4, 10, None, None, None) == 1   # unknown flag
+    assert lib.sgpe_probe_exchange(1024, 1024, 1, 16, 4, 0, 10, None, None, None) == 1  # 2048 threads
+    assert lib.sgpe_probe_exchange(256, 1024, 1, 1, 1, 2, 10, None, None, None) == 1    # wave-local: >= 512
+    assert lib.sgpe_probe_exchange(1024, 1024, 1, 1, 4, 0, 0, ctypes.byref(d), None, None) == 1   # reps

@@ -12,7 +12,11 @@ point index by a vote of its lanes.  The workloads below put those angles where 
   that cross it split their vote) to 2 pi and beyond; the 1e-3 seeded noise puts weight there;
 * the same box with a spatial Raman profile Omega_x(x) + Omega_y(y) that is zero for |x|, |y| <= 4
   and grows quadratically outside, so that h|B| of the full 2x2 form reaches 7 rad;
-* imaginary time with Omega(x) = 200 tanh(x / 4) and dt = 5e-3: h|B| = h Omega / 2 up to 0.5.
+* imaginary time with Omega(x) = 50 tanh(x / 4) and dt = 2e-2: h|B| = h Omega / 2 up to 0.5, at least
+  0.25 on three quarters of the grid.  (Omega_0 = 200 with dt = 5e-3 reaches the same angles but is
+  ill-conditioned for any complex64 transform: the oracle's own step with its FFTs taken in single
+  precision, everything else exact, moves the state by 1e-3 within 100 steps.  The case here moves
+  by 3e-6 under that emulation after 300 steps.)
 
 Bars: complex64 psi relative L2 <= 1e-5 after 200 steps and energy within 1e-6; complex128 1e-12
 and 1e-11.  The angles are rounded once to fp32 on the GPU (the oracle works in fp64), and that
@@ -99,9 +103,9 @@ def test_premise_angles_span_the_branches():
     ox, oy = edge_profile(p)
     th = p.dt * 0.5 * (ox[None, :] + oy[:, None])
     assert th.max() > 2 * math.pi and np.mean(th > math.pi / 4) > 0.3
-    g = preset("ground_2048", nx=128, ny=128, omega_r0=200.0, dt=5e-3)
+    g = cosh_case()
     xg, _, _, _ = grid_axes(g)
-    thi = g.dt * 0.5 * np.abs(g.omega_r0 * np.tanh(xg / g.omega_rw))
+    thi = g.dt * np.sqrt((0.5 * g.omega_r0 * np.tanh(xg / g.omega_rw)) ** 2 + (0.5 * g.delta) ** 2)
     assert thi.max() > 0.45 and np.mean(thi >= 0.25) > 0.5
 
 
@@ -127,8 +131,12 @@ def test_real_time_full_2x2_nln_large_rotation(Solver):
     check(o, s, *TOL["c64"])
 
 
+def cosh_case():
+    return preset("ground_2048", nx=128, ny=128, omega_r0=50.0, dt=2e-2, delta=0.4)
+
+
 @pytest.mark.parametrize("precision", ["c64", "c128"])
 def test_imaginary_time_full_2x2_cosh_branch(Solver, precision):
-    p = preset("ground_2048", nx=128, ny=128, omega_r0=200.0, dt=5e-3, delta=0.4)
+    p = cosh_case()
     o, s = run_pair(Solver, p, initial_state(p, "tf", seed=6), "imag", 300, precision)
     check(o, s, *TOL[precision])
