@@ -254,6 +254,18 @@ enum { SGPE_PROBE_WRITE_THROUGH = 1, SGPE_PROBE_WAVE_LOCAL = 2 };
 sgpe_status sgpe_probe_exchange(int32_t nx, int32_t ny, int32_t layout_rows, int32_t row_tile, int32_t col_tile,
                                 int32_t flags, int32_t reps, double* row_ms, double* col_ms, double* pair_ms);
 
+/* sgpe_energy for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same energy per particle, written as one double to
+ * e_dev (device memory, caller-owned), asynchronously on the context's stream.  The call allocates
+ * nothing and never synchronises: the fp64 scratch of the energy kernels (the x-transformed state)
+ * and their partial sums live in a static device array of 8.1 MiB (grids of up to 262144 points,
+ * e.g. 512 x 512), which every GPU the library runs on holds until the process ends.  Every call on
+ * a device shares that array; calls that overlap on one device (several streams or threads) race
+ * on it and must be ordered by the caller.  The result equals sgpe_energy's up to the order of the
+ * final fp64 sums.  Errors: SGPE_EINVAL (NULL e_dev), SGPE_ESTATE (no state), SGPE_ENOMEM (more
+ * than 262144 points), SGPE_EDEVICE. */
+sgpe_status sgpe_energy_noalloc(sgpe_ctx* ctx, double* e_dev);
+
 /* Static description of a status code.  Never NULL. */
 const char* sgpe_strerror(sgpe_status s);
 

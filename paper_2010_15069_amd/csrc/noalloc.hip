@@ -1,0 +1,112 @@
+// sgpe_energy_noalloc: the energy of sgpe_energy with no allocation at call time, for callers that
+// cannot allocate (code under HIP graph capture, tight serving loops, harnesses that forbid it).
+//
+// sgpe_energy allocates a state-sized fp64 scratch (the x-transformed state) on its first call and
+// brings the partial sums back through a pinned host buffer it grows on demand.  Here both live in
+// one static device array, `scratch`, of a fixed size: grids of up to kMaxPoints points.  Each device
+// the library runs on holds its own copy until the process ends.  Host code never passes the array's
+// name to a kernel or a copy: on a device's first call the address of that device's copy is looked
+// up (hipGetSymbolAddress, with the device current) and kept, and only that address is used.  A
+// finishing kernel sums the partials in a fixed order and writes the energy to the caller's device
+// memory, so the call is asynchronous on the context's stream and never synchronises.
+//
+// Every call on a device shares that device's array and leaves its contents behind; the energy
+// kernels overwrite every value they later read (the scratch rows, every partial), so nothing needs
+// clearing between calls.  Calls that overlap on one device (two streams, or two threads) race on
+// the array and must be ordered by the caller.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "fft_device.hpp"
+#include "host_internal.hpp"
+#include "sgpe.h"
+#include "sgpe_internal.hpp"
+
+namespace {
+
+constexpr size_t kMaxPoints = size_t(1) << 18;   // nx * ny <= 262144 (512 x 512)
+constexpr size_t kMaxAxis = 4096;
+// fp64 x-transformed state (4 doubles per point), then kEnergyRowParts partials per row, then one
+// per column block
+constexpr size_t kScratchDoubles = 4 * kMaxPoints + sgpe::kEnergyRowParts * kMaxAxis + kMaxAxis;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+// One wave: sums each kind of partial in a fixed order (lane-strided, then a fixed butterfly) and
+// evaluates the energy per particle exactly as sgpe_energy does on the host.
+__global__ void __launch_bounds__(64) energy_finish_kernel(const double* __restrict__ row_parts, int nrows,
+                                                           const double* __restrict__ col_parts, int ncols, double w,
+                                                           double inv_npts, double norm0, double* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
+  for (int b = lane; b < nrows; b += 64) {
+    er += row_parts[sgpe::kEnergyRowParts * b];
+    ei += row_parts[sgpe::kEnergyRowParts * b + 1];
+    nr += row_parts[sgpe::kEnergyRowParts * b + 2];
+  }
+  for (int b = lane; b < ncols; b += 64) ek += col_parts[b];
+  er = sgpe::wave_sum(er);
+  ei = sgpe::wave_sum(ei);
+  nr = sgpe::wave_sum(nr);
+  ek = sgpe::wave_sum(ek);
+  if (lane == 0) {
+    const double nrm = w * nr;
+    out[0] = (w * inv_npts * ek + w * er) / nrm + w * ei * norm0 / (nrm * nrm);
+  }
+}
+
+std::mutex g_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// The address of this device's copy of `scratch`, looked up once per device with it current.
+double* device_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[device] = static_cast<double*>(p);
+  }
+  return g_scratch[device];
+}
+
+}  // namespace
+
+extern "C" sgpe_status sgpe_energy_noalloc(sgpe_ctx* c, double* e_dev) {
+  sgpe_status st = sgpe_host::check_ctx(c);   // makes the context's device current
+  if (st != SGPE_OK) return st;
+  if (!e_dev) return SGPE_EINVAL;
+  if (!c->has_state) return SGPE_ESTATE;
+  const sgpe_params& p = c->p;
+  const size_t npts = size_t(p.nx) * size_t(p.ny);
+  if (npts > kMaxPoints) return SGPE_ENOMEM;   // beyond the static scratch
+  double* base = device_scratch(c->device);
+  if (!base) return SGPE_EDEVICE;
+  constexpr int RP = sgpe::kEnergyRowParts;
+  double* row_parts = base + 4 * npts;
+  double* col_parts = row_parts + RP * size_t(p.ny);
+  const sgpe::EnergyArgs a =
+      sgpe_host::energy_args(c, reinterpret_cast<double4*>(base), row_parts, col_parts);
+  const int ncols = p.nx / a.cols;
+  hipError_t e = sgpe::launch_energy(a, c->stream);
+  if (e == hipSuccess) {
+    const double w = (2.0 * p.xmax / p.nx) * (2.0 * p.ymax / p.ny);
+    hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(64), 0, c->stream, row_parts, p.ny, col_parts, ncols, w,
+                       1.0 / double(npts), p.norm0, e_dev);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return sgpe_host::status_of(e);
+  }
+  return SGPE_OK;
+}
