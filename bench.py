@@ -161,15 +161,32 @@ def batched_sweep(torch, stream, steps=500, tune_steps=5):
     t_direct = timed_call()
     pts = sum(p.nx * p.ny for p in ps)
     e = [b.energy(i) for i in (0, 32, 64)]
+    # persistent mode: one cooperative launch for every steady-state step of every instance
+    for i, p in enumerate(ps):
+        b.set_psi(i, initial_state(p, "tf", seed=i))
+    b.use_graph(True)
+    b.use_persistent(True)
+    tp_first = timed_call()
+    tp = timed_call()
+    b.use_graph(False)
+    tp_direct = timed_call()
+    e_p = [b.energy(i) for i in (0, 32, 64)]
     b.close()
+    best = min(t_graph, tp, tp_direct)
     return {"workload": "96 instances: 32 x 128^2, 32 x 256^2, 32 x 512^2, g ~ U[1,100], Omega ~ U[0,3], "
                         "delta ~ U[-0.5,0.5] (seed 0), k_L = 2, imaginary time dt = 1e-3, Thomas-Fermi starts",
             "steps": steps, "seconds_graph": t_graph, "seconds_direct": t_direct,
             "seconds_first_call_with_capture": t_capture,
-            "instance_steps_per_s": len(ps) * steps / t_graph,
-            "hbm_roofline_frac": BYTES_PER_POINT_STEP * pts * steps / t_graph / (HBM_PEAK_GBS * 1e9),
-            "autotune_seconds": tune_s, "schedules": schedules,
-            "tuned_ms_per_step_per_class": tuned_ms, "energies_sample": e}
+            "instance_steps_per_s": len(ps) * steps / best,
+            "hbm_roofline_frac": BYTES_PER_POINT_STEP * pts * steps / best / (HBM_PEAK_GBS * 1e9),
+            "per_class_launches": {"instance_steps_per_s": len(ps) * steps / t_graph, "seconds_graph": t_graph,
+                                   "seconds_direct": t_direct, "autotune_seconds": tune_s, "schedules": schedules,
+                                   "tuned_ms_per_step_per_class": tuned_ms, "energies_sample": e},
+            "persistent": {"instance_steps_per_s": len(ps) * steps / min(tp, tp_direct),
+                           "seconds_graph_replay": tp, "seconds_direct": tp_direct,
+                           "seconds_first_call": tp_first, "energies_sample": e_p,
+                           "note": "one cooperative launch for steps 1..n-1 of all 96 instances; the call's "
+                                   "first and last passes per class"}}
 
 
 def ground_state_time(torch, stream, check_every=50, max_steps=200000):

@@ -352,6 +352,25 @@ sgpe_status sgpe_batch_use_graph(sgpe_batch* batch, int32_t on);
 sgpe_status sgpe_batch_get_schedule(const sgpe_batch* batch, int32_t k, sgpe_schedule* out);
 sgpe_status sgpe_batch_set_schedule(sgpe_batch* batch, int32_t k, const sgpe_schedule* schedule);
 
+/* Persistent mode (on = 1): each step_* call runs every steady-state step of every instance in one
+ * cooperative launch of a persistent kernel (workgroups stay resident; work items of 1024 points
+ * per component -- 1024 / nx rows or 1024 / ny columns of one instance -- taken round-robin; a
+ * bounded grid-wide barrier between the row and the column phase of each step), with the call's
+ * first and last passes as per-class launches: about 3 x classes + 1 launches per call instead of
+ * 2 n + 2 per class.  Requires every class to be a square grid with nx = ny in {128, 256, 512} and
+ * no spatial Raman coupling (SGPE_EINVAL otherwise), and a device with cooperative launches
+ * (SGPE_EDEVICE).  The resident workgroups are split among the classes in proportion to their work.
+ * Enabling sets every class's schedule to 8 points per lane, 1024 / nx rows per row workgroup and
+ * 1024 / ny columns per column workgroup; while it is on, sgpe_batch_set_schedule and
+ * sgpe_batch_autotune return SGPE_ESTATE.  Results: every instance bit-identical to a single
+ * context with that schedule.  If a barrier wait ever gives up (it polls a bounded number of
+ * times), every workgroup leaves, the states are invalid and sgpe_batch_synchronize returns
+ * SGPE_EDEVICE (the environment variable SGPE_PERSIST_SPIN_LIMIT, read when the mode is enabled,
+ * replaces the poll bound; 0 forces that path, for tests).  With graphs on, the call is captured as usual when the runtime can capture the
+ * cooperative launch, and runs directly otherwise.  on = 0 returns to per-class launches (the
+ * schedules stay).  Synchronises. */
+sgpe_status sgpe_batch_use_persistent(sgpe_batch* batch, int32_t on);
+
 /* Autotuner: for every class, time `steps` real-time steps under each supported schedule (points
  * per lane 4/8/16 in each pass, column tiles 1..16) and keep the fastest.  The instances' states
  * are saved before and restored after (so results do not depend on tuning); the captured graphs

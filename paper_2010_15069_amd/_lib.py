@@ -60,7 +60,7 @@ EXPORTS = [
     "sgpe_batch_class_info", "sgpe_batch_instance_class", "sgpe_batch_set_psi", "sgpe_batch_get_psi",
     "sgpe_batch_energy", "sgpe_batch_norm", "sgpe_batch_step_real", "sgpe_batch_step_imag",
     "sgpe_batch_synchronize", "sgpe_batch_use_graph", "sgpe_batch_get_schedule",
-    "sgpe_batch_set_schedule", "sgpe_batch_autotune",
+    "sgpe_batch_set_schedule", "sgpe_batch_autotune", "sgpe_batch_use_persistent",
     "sgpe_set_raman_profile", "sgpe_add_noise", "sgpe_phase_separation", "sgpe_population_radius",
     "sgpe_winding", "sgpe_set_splitting", "sgpe_create_ex", "sgpe_probe_exchange", "sgpe_energy_noalloc",
 ]
@@ -145,6 +145,7 @@ def _lib():
         "sgpe_batch_get_schedule": ([vp, i32, P(Schedule)], st),
         "sgpe_batch_set_schedule": ([vp, i32, P(Schedule)], st),
         "sgpe_batch_autotune": ([vp, i32, P(ctypes.c_double)], st),
+        "sgpe_batch_use_persistent": ([vp, i32], st),
     }
     batch_sigs.update({
         "sgpe_set_raman_profile": ([vp, vp, vp], st),

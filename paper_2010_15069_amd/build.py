@@ -50,7 +50,8 @@ def source_hash() -> str:
 
 # The sources the step kernels compile from (with the device compile flags): a record measured on
 # these kernels stays valid while this hash is unchanged, whatever happens to the host library.
-KERNEL_SOURCES = ("row_pass.hip", "col_pass.hip", "fft_device.hpp", "sgpe_internal.hpp")
+KERNEL_SOURCES = ("row_pass.hip", "col_pass.hip", "row_body.hpp", "col_body.hpp", "fft_device.hpp",
+                  "sgpe_internal.hpp")
 
 
 def kernel_hash() -> str:

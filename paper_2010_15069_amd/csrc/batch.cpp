@@ -14,10 +14,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
 #include <utility>
+#include <type_traits>
 #include <vector>
 
 #include "host_internal.hpp"
@@ -58,6 +60,21 @@ struct sgpe_batch {
   hipEvent_t enter = nullptr, leave = nullptr;
   bool use_graph = true;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (steps, imag) -> executable graph
+  // persistent mode (sgpe_batch_use_persistent): every steady-state step of every instance in one
+  // cooperative launch of the persistent kernel
+  bool persistent = false;
+  bool persist_graph_ok = true;     // cleared if capturing the cooperative launch fails
+  RowArgs* p_row_first = nullptr;   // device, [instances]
+  RowArgs* p_row_imag = nullptr;    // device, [instances]: scale from the norm partials
+  ColArgs* p_col[2] = {nullptr, nullptr};   // device, [instances]: K(dt), real / imaginary time
+  int4* p_row_items = nullptr;
+  int4* p_col_items = nullptr;
+  sgpe::PersistClass p_cls[sgpe::kPersistClasses] = {};
+  unsigned* p_words = nullptr;      // device: the grid barrier's words (sgpe::kPersistWords)
+  unsigned* p_abort_host = nullptr; // pinned, mapped: a barrier wait gave up
+  unsigned* p_abort_host_dev = nullptr;
+  int p_grid = 0;                   // workgroups of the persistent launch (all co-resident)
+  unsigned p_spin_limit = sgpe::kPersistSpinLimit;
 };
 
 namespace {
@@ -125,8 +142,58 @@ hipError_t enqueue_class(const sgpe_batch* b, const BatchClass& k, int64_t n, bo
   return e;
 }
 
+// Persistent mode: per class the call's first x transform and half K, then one cooperative launch
+// for steps 1..n-1 of every instance, then per class the last step (its row pass, the half K with
+// the final norm) and the last inverse x transform.  The same passes, in the same order per
+// instance, as the per-class launches.
+hipError_t enqueue_persistent(sgpe_batch* b, int64_t n, bool imag, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (const auto& k : b->cls) {
+    const int cnt = int(k.members.size());
+    const sgpe_ctx* c0 = b->inst[k.members[0]];
+    const RowArgs shape_r = row_args(c0);
+    const ColArgs shape_c = col_args(c0, imag, false);
+    if (e == hipSuccess)
+      e = sgpe::launch_row_batch(shape_r, k.row_tab + ROWTAB_FWD * cnt, cnt, sgpe::ROW_FWD, false, false, 8, s);
+    if (e == hipSuccess)
+      e = sgpe::launch_col_batch(shape_c, k.col_tab + (2 * int(imag) + 1) * cnt, cnt, sgpe::NORM_NONE, 8, s);
+  }
+  if (e == hipSuccess && n > 1) {
+    sgpe::PersistArgs a{};
+    a.row_first = b->p_row_first;
+    a.row_step = imag ? b->p_row_imag : b->p_row_first;
+    a.col = b->p_col[imag ? 1 : 0];
+    a.row_items = b->p_row_items;
+    a.col_items = b->p_col_items;
+    for (int k = 0; k < sgpe::kPersistClasses; ++k) a.cls[k] = b->p_cls[k];
+    a.steps = int(n - 1);
+    a.first_is_first = 1;
+    a.barrier = b->p_words;
+    a.abort_host = b->p_abort_host_dev;
+    a.spin_limit = b->p_spin_limit;
+    e = sgpe::launch_persist(a, imag, b->p_grid, s);
+  }
+  for (const auto& k : b->cls) {
+    const int cnt = int(k.members.size());
+    const sgpe_ctx* c0 = b->inst[k.members[0]];
+    const RowArgs shape_r = row_args(c0);
+    const ColArgs shape_c = col_args(c0, imag, false);
+    const RowArgs* t_sc = k.row_tab + ROWTAB_SCALE * cnt;
+    const RowArgs* t_pa = k.row_tab + ROWTAB_PARTIALS * cnt;
+    if (e == hipSuccess)
+      e = sgpe::launch_row_batch(shape_r, (imag && n > 1) ? t_pa : t_sc, cnt, sgpe::ROW_STEP, imag, false, 8, s);
+    if (e == hipSuccess)
+      e = sgpe::launch_col_batch(shape_c, k.col_tab + (2 * int(imag) + 1) * cnt, cnt,
+                                 imag ? sgpe::NORM_SQ : sgpe::NORM_NONE, 8, s);
+    if (e == hipSuccess)
+      e = sgpe::launch_row_batch(shape_r, imag ? t_pa : t_sc, cnt, sgpe::ROW_INV, false, false, 8, s);
+  }
+  return e;
+}
+
 // All classes, each on its own stream, forked from and joined back to stream `origin`.
 hipError_t enqueue_all(sgpe_batch* b, int64_t n, bool imag, hipStream_t origin) {
+  if (b->persistent) return enqueue_persistent(b, n, imag, origin);
   hipError_t e = hipEventRecord(b->fork, origin);
   for (auto& k : b->cls) {
     if (e == hipSuccess) e = hipStreamWaitEvent(k.stream, b->fork, 0);
@@ -144,7 +211,7 @@ sgpe_status run(sgpe_batch* b, int64_t n, bool imag) {
   for (const sgpe_ctx* c : b->inst)
     if (!c->has_state) return SGPE_ESTATE;
   if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
-  if (!b->use_graph) return hip_status(enqueue_all(b, n, imag, b->stream));
+  if (!b->use_graph || (b->persistent && !b->persist_graph_ok)) return hip_status(enqueue_all(b, n, imag, b->stream));
   const auto key = std::make_pair(n, int(imag));
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
@@ -155,6 +222,12 @@ sgpe_status run(sgpe_batch* b, int64_t n, bool imag) {
     e = hipStreamEndCapture(b->graph_stream, &g);
     if (e2 != hipSuccess || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      if (b->persistent) {
+        // the runtime could not capture the cooperative launch: run the call directly from now on
+        b->persist_graph_ok = false;
+        return hip_status(enqueue_all(b, n, imag, b->stream));
+      }
       return hip_status(e2 != hipSuccess ? e2 : e);
     }
     hipGraphExec_t x = nullptr;
@@ -282,6 +355,12 @@ void sgpe_batch_destroy(sgpe_batch* b) {
     (void)hipStreamSynchronize(b->graph_stream);
     (void)hipStreamDestroy(b->graph_stream);
   }
+  for (void* ptr : {static_cast<void*>(b->p_row_first), static_cast<void*>(b->p_row_imag),
+                    static_cast<void*>(b->p_col[0]), static_cast<void*>(b->p_col[1]),
+                    static_cast<void*>(b->p_row_items), static_cast<void*>(b->p_col_items),
+                    static_cast<void*>(b->p_words)})
+    if (ptr) (void)hipFree(ptr);
+  if (b->p_abort_host) (void)hipHostFree(b->p_abort_host);
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->enter) (void)hipEventDestroy(b->enter);
   if (b->leave) (void)hipEventDestroy(b->leave);
@@ -340,11 +419,167 @@ sgpe_status sgpe_batch_synchronize(sgpe_batch* b) {
   if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
   const sgpe_status st = hip_status(hipStreamSynchronize(b->stream));
   if (st != SGPE_OK) return st;
+  if (b->p_abort_host && __atomic_load_n(b->p_abort_host, __ATOMIC_ACQUIRE) != 0u) {
+    // a grid-barrier wait of the persistent kernel gave up: the states are not valid
+    __atomic_store_n(b->p_abort_host, 0u, __ATOMIC_RELEASE);
+    return SGPE_EDEVICE;
+  }
   // an instance whose imaginary-time norm went non-finite is reported (and stays latched in it)
   sgpe_status out = SGPE_OK;
   for (sgpe_ctx* c : b->inst)
     if (latched_status(c) != SGPE_OK && out == SGPE_OK) out = c->latched;
   return out;
+}
+
+// Persistent mode: validate the classes, give them the persistent kernel's work-item schedule,
+// build the per-instance argument tables and the item lists.
+static sgpe_status enable_persistent(sgpe_batch* b) {
+  auto supported = [](int n) { return n == 128 || n == 256 || n == 512; };
+  if (b->cls.size() > size_t(sgpe::kPersistClasses)) return SGPE_EINVAL;
+  for (const auto& k : b->cls)
+    if (k.nx != k.ny || !supported(k.nx) || k.full2x2) return SGPE_EINVAL;
+  for (const sgpe_ctx* c : b->inst)
+    if (c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) return SGPE_EINVAL;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return hip_status(hipErrorUnknown);
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device) != hipSuccess || !coop)
+    return hip_status(hipErrorNotSupported);
+  // the per-class launches of the first and last step use the same 8-point, 1024-point-item schedule
+  for (auto& k : b->cls) {
+    sgpe_schedule s{};
+    s.row_points = 8;
+    s.col_points = 8;
+    s.row_iters = 1;
+    s.col_iters = 1;
+    s.row_tile = 1024 / k.nx;
+    s.col_tile = 1024 / k.ny;
+    const sgpe_status st = set_class_schedule(b, k, s);
+    if (st != SGPE_OK) return st;
+  }
+  const size_t n = b->inst.size();
+  std::vector<RowArgs> first(n), imag(n);
+  std::vector<ColArgs> col_r(n), col_i(n);
+  std::vector<int4> ri, ci;
+  for (size_t i = 0; i < n; ++i) {
+    const sgpe_ctx* c = b->inst[i];
+    RowArgs a = row_args(c);
+    a.scale = float(1.0 / (double(c->p.nx) * double(c->p.ny)));
+    first[i] = a;
+    a.partials = c->partials;
+    a.n_partials = col_groups(c);
+    imag[i] = a;
+    col_r[i] = col_args(c, false, false);
+    col_i[i] = col_args(c, true, false);
+  }
+  // items per class: row groups of 1024 / n rows and column tiles of 1024 / n columns
+  sgpe::PersistClass pc[sgpe::kPersistClasses] = {};
+  double weight[sgpe::kPersistClasses] = {};
+  for (size_t kk = 0; kk < b->cls.size(); ++kk) {
+    const auto& k = b->cls[kk];
+    const int groups = k.nx * k.ny / 1024;
+    pc[kk].log2n = __builtin_ctz(k.nx);
+    pc[kk].row_begin = int(ri.size());
+    pc[kk].col_begin = int(ci.size());
+    for (int m : k.members)
+      for (int g = 0; g < groups; ++g) ri.push_back(make_int4(m, g, 0, groups));
+    for (int m : k.members)
+      for (int g = 0; g < groups; ++g) ci.push_back(make_int4(m, g, 0, groups));
+    pc[kk].n_row = int(ri.size()) - pc[kk].row_begin;
+    pc[kk].n_col = int(ci.size()) - pc[kk].col_begin;
+    weight[kk] = double(pc[kk].n_row) * double(pc[kk].log2n);   // an item's cost grows with log2 n
+  }
+  auto up = [](auto** dst, const auto& v) {
+    using T = std::remove_reference_t<decltype(v[0])>;
+    if (!*dst && hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T)) != hipSuccess) return false;
+    return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+  };
+  if (!up(&b->p_row_first, first) || !up(&b->p_row_imag, imag) || !up(&b->p_col[0], col_r) ||
+      !up(&b->p_col[1], col_i)) {
+    (void)hipGetLastError();
+    return SGPE_ENOMEM;
+  }
+  if (b->p_row_items) (void)hipFree(b->p_row_items);
+  if (b->p_col_items) (void)hipFree(b->p_col_items);
+  b->p_row_items = nullptr;
+  b->p_col_items = nullptr;
+  if (!up(&b->p_row_items, ri) || !up(&b->p_col_items, ci)) {
+    (void)hipGetLastError();
+    return SGPE_ENOMEM;
+  }
+  if (!b->p_words) {
+    if (hipMalloc(reinterpret_cast<void**>(&b->p_words), sgpe::kPersistWords * sizeof(unsigned)) != hipSuccess ||
+        hipMemset(b->p_words, 0, sgpe::kPersistWords * sizeof(unsigned)) != hipSuccess) {
+      (void)hipGetLastError();
+      return SGPE_ENOMEM;
+    }
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, sizeof(unsigned), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      (void)hipGetLastError();
+      return SGPE_ENOMEM;
+    }
+    b->p_abort_host = static_cast<unsigned*>(h);
+    *b->p_abort_host = 0u;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return SGPE_EDEVICE;
+    }
+    b->p_abort_host_dev = static_cast<unsigned*>(d);
+  }
+  // workgroups: as many as stay co-resident (the smaller of the two instantiations' limits), split
+  // among the classes in proportion to their work, each class at least one and at most its items
+  const int n_cu = b->inst[0]->n_cu;
+  int gmax = 0;
+  for (int imagi = 0; imagi < 2; ++imagi) {
+    int g = 0;
+    hipError_t e = sgpe::persist_max_grid(imagi != 0, n_cu, &g);
+    if (e != hipSuccess) return hip_status(e);
+    gmax = imagi == 0 ? g : std::min(gmax, g);
+  }
+  const int nk = int(b->cls.size());
+  if (gmax < nk) return SGPE_EDEVICE;
+  double wsum = 0.0;
+  for (int k = 0; k < nk; ++k) wsum += weight[k];
+  int total = 0;
+  for (int k = 0; k < nk; ++k) {
+    int w = int(double(gmax) * weight[k] / wsum);
+    w = std::max(1, std::min(w, pc[k].n_row));
+    pc[k].wg_count = w;
+    total += w;
+  }
+  while (total > gmax) {   // rounding: take back from the largest share
+    int kmax = 0;
+    for (int k = 1; k < nk; ++k)
+      if (pc[k].wg_count > pc[kmax].wg_count) kmax = k;
+    --pc[kmax].wg_count;
+    --total;
+  }
+  int begin = 0;
+  for (int k = 0; k < nk; ++k) {
+    pc[k].wg_begin = begin;
+    begin += pc[k].wg_count;
+  }
+  for (int k = 0; k < sgpe::kPersistClasses; ++k) b->p_cls[k] = pc[k];
+  b->p_grid = total;
+  // test hook: SGPE_PERSIST_SPIN_LIMIT lowers the bound of the barrier waits, so that a test can
+  // make them give up (every workgroup still leaves the kernel normally)
+  b->p_spin_limit = sgpe::kPersistSpinLimit;
+  if (const char* env = std::getenv("SGPE_PERSIST_SPIN_LIMIT")) b->p_spin_limit = unsigned(std::strtoul(env, nullptr, 10));
+  drop_graphs(b);
+  b->persistent = true;
+  b->persist_graph_ok = true;
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_batch_use_persistent(sgpe_batch* b, int32_t on) {
+  if (!b) return SGPE_EINVAL;
+  if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
+  if (!on) {
+    if (b->persistent) drop_graphs(b);
+    b->persistent = false;
+    return SGPE_OK;
+  }
+  return enable_persistent(b);
 }
 
 sgpe_status sgpe_batch_use_graph(sgpe_batch* b, int32_t on) {
@@ -360,6 +595,7 @@ sgpe_status sgpe_batch_get_schedule(const sgpe_batch* b, int32_t k, sgpe_schedul
 }
 
 sgpe_status sgpe_batch_set_schedule(sgpe_batch* b, int32_t k, const sgpe_schedule* s) {
+  if (b && b->persistent) return SGPE_ESTATE;   // the persistent kernel fixes the schedule
   if (!valid_class(b, k)) return SGPE_EINVAL;
   if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
   if (hipStreamSynchronize(b->stream) != hipSuccess) return hip_status(hipErrorUnknown);
@@ -368,6 +604,7 @@ sgpe_status sgpe_batch_set_schedule(sgpe_batch* b, int32_t k, const sgpe_schedul
 }
 
 sgpe_status sgpe_batch_autotune(sgpe_batch* b, int32_t steps, double* best_ms) {
+  if (b && b->persistent) return SGPE_ESTATE;
   if (!b || steps < 1) return SGPE_EINVAL;
   for (const sgpe_ctx* c : b->inst)
     if (!c->has_state) return SGPE_ESTATE;

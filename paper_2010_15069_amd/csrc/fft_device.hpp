@@ -322,11 +322,15 @@ constexpr int last_radix() {
 // products at use (its rounding, ~1e-15, lies far below the fp32 rounding it feeds).  Table
 // entries are float4 {cos, sin, eta, 0} of exp(-2 pi i j / N).  Loaded once per kernel (they
 // depend only on the thread index); three registers per root.
+// fp64 roots carry no modulus correction (their |w~| - 1 is ~1e-16; see Roots<double>), so the fp64
+// instantiation holds no eta and its inverse multiplies by conj(w~) alone: 2 registers per root
+// fewer, and the 4-instruction product instead of the corrected one.
 template <int N, int P = 16, class T = float>
 struct TwPlain {
   static constexpr int COUNT = tw_count_p<N, P>() > 0 ? tw_count_p<N, P>() : 1;
+  static constexpr bool CORRECTED = sizeof(T) == 4;
   cplx_t<T> cs[COUNT];
-  T eta[COUNT];
+  T eta[CORRECTED ? COUNT : 1];
 };
 
 template <int N, int P, int L = 1, int BASE = 0, class TR>
@@ -346,7 +350,7 @@ __device__ __forceinline__ void load_twiddles(TwPlain<N, P, TR>& tr, int t, cons
       for (int r = 1; r < R; ++r) {
         const Q w = *reinterpret_cast<const Q*>(reinterpret_cast<const char*>(tw) + o * r);
         tr.cs[BASE + u * (R - 1) + (r - 1)] = mk2(w.x, w.y);
-        tr.eta[BASE + u * (R - 1) + (r - 1)] = w.z;
+        if constexpr (TwPlain<N, P, TR>::CORRECTED) tr.eta[BASE + u * (R - 1) + (r - 1)] = w.z;
       }
     }
   }
@@ -429,8 +433,12 @@ __device__ __forceinline__ void pi_stage(C (&v)[P], const LdsView<C>& lds, int t
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const C w = tr.cs[BASE + u * (R - 1) + (r - 1)];
-        const TR eta = tr.eta[BASE + u * (R - 1) + (r - 1)];
-        a[r] = pi_cmul(a[r], w.x, w.y, w.x * eta, w.y * eta);
+        if constexpr (TwPlain<N, P, TR>::CORRECTED) {
+          const TR eta = tr.eta[BASE + u * (R - 1) + (r - 1)];
+          a[r] = pi_cmul(a[r], w.x, w.y, w.x * eta, w.y * eta);
+        } else {
+          a[r] = mk2(fma_(a[r].x, w.x, -a[r].y * w.y), fma_(a[r].y, w.x, a[r].x * w.y));   // * conj(w~)
+        }
       }
     }
 #pragma unroll

@@ -162,6 +162,43 @@ hipError_t launch_winding(const float4* psi, int nx, int ny, double xmax, double
 hipError_t launch_winding(const double4* psi, int nx, int ny, double xmax, double ymax, double radius, int m,
                           double* out, hipStream_t s);
 
+// Persistent step kernel of a batch (persist.hip).  Square grids of n = 128, 256 or 512 points per
+// axis, one class per n.  Work items are int4 {instance, group, -, groups of that instance in the
+// pass}; a row item is 1024 / n rows, a column item 1024 / n columns, 8 points per lane, 256
+// threads.  The workgroups are split among the classes in proportion to their work; a workgroup
+// takes its class's items round-robin.
+constexpr int kPersistClasses = 3;
+struct PersistClass {
+  int log2n;                  // 0: unused slot
+  int wg_begin, wg_count;     // this class's workgroups
+  int row_begin, n_row;       // its row items in row_items
+  int col_begin, n_col;       // its column items in col_items
+};
+struct PersistArgs {
+  const RowArgs* row_first;   // per instance: the row pass of a call's first step (fixed scale)
+  const RowArgs* row_step;    // per instance: later steps (imaginary time: scale from the partials)
+  const ColArgs* col;         // per instance: K(dt), norm partials in imaginary time
+  const int4* row_items;
+  const int4* col_items;
+  PersistClass cls[kPersistClasses];
+  int steps;                  // steady-state steps in this launch
+  int first_is_first;         // 1: the launch's first step is the call's first (row_first)
+  unsigned* barrier;          // device words of the grid barrier, kPersistWords (zeroed per launch)
+  unsigned* abort_host;       // host-visible: a barrier wait gave up
+  unsigned spin_limit;        // polls before a barrier wait gives up
+};
+constexpr unsigned kPersistSpinLimit = 4u << 20;   // ~4M polls of ~0.5 us or more: seconds, not a hang
+// barrier words, each on its own 256-byte line: 8 slot counters, the global counter, 8 slot
+// releases, the abort word
+constexpr int kPersistWordStride = 64;
+constexpr int kPersistAbortWord = kPersistWordStride * 17;
+constexpr int kPersistWords = kPersistWordStride * 18;
+size_t persist_lds_bytes();
+// Largest co-resident grid of the persistent kernel on a device with n_cu compute units.
+hipError_t persist_max_grid(bool imag, int n_cu, int* grid);
+// Zero the barrier words, then launch cooperatively (all workgroups resident) on stream s.
+hipError_t launch_persist(const PersistArgs& a, bool imag, int grid, hipStream_t s);
+
 // Measurement probes (probes.hip): the data movement of the row and column partitions with no
 // arithmetic, on a layout with `layout_rows` interleaved rows (1 = the state's layout).
 hipError_t launch_probe_rows(const float4* src, float4* dst, int nx, int ny, int layout_rows, int row_tile,

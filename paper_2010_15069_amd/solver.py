@@ -265,6 +265,12 @@ class Batch:
         check(self._lib.sgpe_batch_norm(self._b, int(i), ctypes.byref(v)), "sgpe_batch_norm")
         return v.value
 
+    def use_persistent(self, on=True):
+        """Every steady-state step of every instance in one cooperative persistent launch per call
+        (see sgpe_batch_use_persistent)."""
+        check(self._lib.sgpe_batch_use_persistent(self._b, int(bool(on))), "sgpe_batch_use_persistent")
+        return self
+
     def use_graph(self, on=True):
         check(self._lib.sgpe_batch_use_graph(self._b, 1 if on else 0), "sgpe_batch_use_graph")
         return self
