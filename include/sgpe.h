@@ -103,9 +103,10 @@ typedef enum {
 /* sgpe_create with a precision.  SGPE_C128: the state is [ny][nx] of {re_up, im_up, re_dn, im_dn}
  * as fp64 (32*nx*ny bytes; a borrowed psi_dev must hold that many, 16-byte aligned), set_psi and
  * get_psi copy without rounding, and the step kernels, tables and the imaginary-time norm run in
- * fp64 (Sec. 4 uses complex128 throughout).  Its launch schedule is fixed (16 points per lane, no
- * prefetch): sgpe_set_schedule and sgpe_set_col_tile return SGPE_EINVAL, sgpe_set_splitting accepts
- * only the default, sgpe_profile_steps / sgpe_profile_kernels return SGPE_ESTATE.  Batches are
+ * fp64 (Sec. 4 uses complex128 throughout).  Its schedules have no prefetch (row_iters = col_iters
+ * = 1), 16 or 8 points per lane (8 for lengths up to 1024), and at most 256 threads per workgroup
+ * unless one line alone needs 512; sgpe_set_schedule accepts those (SGPE_EINVAL otherwise),
+ * sgpe_set_col_tile returns SGPE_EINVAL, sgpe_set_splitting accepts only the default, sgpe_profile_steps / sgpe_profile_kernels return SGPE_ESTATE.  Batches are
  * complex64 only.  Errors: as sgpe_create, and SGPE_EINVAL for an unknown precision. */
 sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_stream, void* psi_dev,
                            sgpe_ctx** out);
@@ -254,6 +255,16 @@ enum { SGPE_PROBE_WRITE_THROUGH = 1, SGPE_PROBE_WAVE_LOCAL = 2 };
 sgpe_status sgpe_probe_exchange(int32_t nx, int32_t ny, int32_t layout_rows, int32_t row_tile, int32_t col_tile,
                                 int32_t flags, int32_t reps, double* row_ms, double* col_ms, double* pair_ms);
 
+/* Measurement helper: where workgroups run.  Launches a gx x gy grid of `threads`-thread
+ * workgroups on the current device; thread 0 of workgroup (x, y) writes the index of the XCD that
+ * ran it (hardware register XCC_ID) to xcd[y gx + x] (host memory, gx gy entries).  The batched
+ * and persistent launches (Sec. 3.2's steps of many instances) place work by the dispatcher's order,
+ * workgroup L of a launch on XCD (s + L) mod 8 with s where its rotation stood; this probe shows
+ * that order on the device at hand.  Synchronises.
+ * Errors: SGPE_EINVAL (NULL xcd, gx < 1, gy not in 1..65535, threads not in 1..1024, more than
+ * 2^24 workgroups), SGPE_ENOMEM, SGPE_EDEVICE. */
+sgpe_status sgpe_probe_placement(int32_t gx, int32_t gy, int32_t threads, uint32_t* xcd);
+
 /* sgpe_energy for callers that cannot allocate (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): the same energy per particle, written as one double to
  * e_dev (device memory, caller-owned), asynchronously on the context's stream.  The call allocates
@@ -274,9 +285,11 @@ const char* sgpe_strerror(sgpe_status s);
  * unsupported value returns SGPE_EINVAL and changes nothing.  See sgpe_schedule. */
 sgpe_status sgpe_set_col_tile(sgpe_ctx* ctx, int32_t columns);
 
-/* Launch schedule of the two passes -- how the work is cut into lanes and workgroups.  It does
- * not change the arithmetic of any point: real-time results are bit-identical under every valid
- * schedule; imaginary-time results differ only in the grouping of the fp64 norm partials.
+/* Launch schedule of the two passes -- how the work is cut into lanes and workgroups.  Tiles and
+ * prefetching do not change the arithmetic of any point: with the same points per lane, real-time
+ * results are bit-identical under every valid schedule, and imaginary-time results differ only in
+ * the grouping of the fp64 norm partials.  The points per lane set the transforms' radix
+ * decomposition, so changing them changes results at the level of rounding.
  *   col_tile    columns per column-pass workgroup (power of two)
  *   row_iters   row groups per row-pass workgroup, 1 or 2: with 2, the next group's data is loaded
  *               while the current one is transformed (8 or 16 points per lane, <= 256 threads)

@@ -4,7 +4,7 @@ The compute path is the HIP library libsgpe.so (C ABI in include/sgpe.h); this p
 thin Python binding.  Build it with ``python -m paper_2010_15069_amd.build``.
 """
 from ._lib import LIB_PATH, SgpeError, SgpeParams, STATUS_NAMES
-from .solver import Batch, Solver, device_count, probe_exchange, validate_params
+from .solver import Batch, Solver, device_count, probe_exchange, probe_placement, validate_params
 
 __all__ = ["Batch", "Solver", "SgpeError", "SgpeParams", "STATUS_NAMES", "LIB_PATH", "device_count",
-           "probe_exchange", "validate_params"]
+           "probe_exchange", "probe_placement", "validate_params"]

@@ -63,6 +63,7 @@ EXPORTS = [
     "sgpe_batch_set_schedule", "sgpe_batch_autotune", "sgpe_batch_use_persistent",
     "sgpe_set_raman_profile", "sgpe_add_noise", "sgpe_phase_separation", "sgpe_population_radius",
     "sgpe_winding", "sgpe_set_splitting", "sgpe_create_ex", "sgpe_probe_exchange", "sgpe_energy_noalloc",
+    "sgpe_probe_placement",
 ]
 
 
@@ -158,6 +159,7 @@ def _lib():
         "sgpe_probe_exchange": ([i32, i32, i32, i32, i32, i32, i32, P(ctypes.c_double), P(ctypes.c_double),
                                  P(ctypes.c_double)], st),
         "sgpe_energy_noalloc": ([vp, vp], st),
+        "sgpe_probe_placement": ([i32, i32, i32, P(ctypes.c_uint32)], st),
     })
     for name, (args, res) in batch_sigs.items():
         f = getattr(lib, name)

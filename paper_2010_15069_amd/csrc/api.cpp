@@ -340,13 +340,13 @@ sgpe::ColArgsT<T> col_args_t(const sgpe_ctx* c, bool imag, bool half) {
 ColArgs col_args(const sgpe_ctx* c, bool imag, bool half) { return col_args_t<float>(c, imag, half); }
 
 // The fused schedule on a complex128 state: the same sequence of passes as run_steps, with the
-// fp64 instantiations of the kernels (16 points per lane, no prefetch).
+// fp64 instantiations of the kernels (16 or 8 points per lane, no prefetch).
 static sgpe_status run_steps_c128(sgpe_ctx* c, int64_t n, bool imag) {
   const double npts = double(c->p.nx) * double(c->p.ny);
   hipStream_t s = c->stream;
   sgpe::RowArgsT<double> ra = row_args_t<double>(c, 0.0);
-  hipError_t e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, s);
-  if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, true), sgpe::NORM_NONE, s);
+  hipError_t e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_points, s);
+  if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, true), sgpe::NORM_NONE, c->col_points, s);
   for (int64_t i = 1; i <= n && e == hipSuccess; ++i) {
     sgpe::RowArgsT<double> r = ra;
     r.scale = 1.0 / npts;
@@ -354,10 +354,10 @@ static sgpe_status run_steps_c128(sgpe_ctx* c, int64_t n, bool imag) {
       r.partials = c->partials;
       r.n_partials = col_groups(c);
     }
-    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, s);
+    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, c->row_points, s);
     const bool last = (i == n);
     const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
-    if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, last), nm, s);
+    if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, last), nm, c->col_points, s);
   }
   if (e == hipSuccess) {
     sgpe::RowArgsT<double> r = ra;
@@ -366,7 +366,7 @@ static sgpe_status run_steps_c128(sgpe_ctx* c, int64_t n, bool imag) {
       r.partials = c->partials;
       r.n_partials = col_groups(c);
     }
-    e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, s);
+    e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_points, s);
   }
   return status_of(e);
 }
@@ -627,13 +627,64 @@ const char* sgpe_strerror(sgpe_status s) {
 }
 
 // Columns per column-pass tile for complex128: at most 4, 256 threads where one column allows it,
-// within the LDS (double2 slots take twice the bytes).
-static int c128_cols(int nx, int ny, size_t max_lds) {
+// within the LDS (double2 slots take twice the bytes); at 8 points per lane also at least as many
+// workgroups as compute units where one column allows it (measured at 256^2 and 512^2: 1 and 2
+// columns, 90.8k and 48.3k imaginary steps/s, against 88.5k and 44.2k for 2 and 1).
+static int c128_cols(int nx, int ny, int points, int n_cu, size_t max_lds) {
   int c = 4;
-  while (c > 1 && (2 * c * (ny / 16) > 256 || c > nx || nx % c != 0 || !sgpe::schedule_supported(ny, c, 1, 16) ||
-                   sgpe::col_lds_bytes_c128(ny, c) > max_lds))
+  while (c > 1 && (2 * c * (ny / points) > 256 || c > nx || nx % c != 0 ||
+                   !sgpe::schedule_supported(ny, c, 1, points) ||
+                   sgpe::col_lds_bytes_c128(ny, c, points) > max_lds || (points == 8 && nx / c < n_cu)))
     c >>= 1;
   return c;
+}
+
+static int c128_rows(const sgpe_ctx* c, int points) {
+  // one row per workgroup where a row takes at least one wave (measured: 29.1 -> 27.5 us per
+  // imaginary step at 512^2, 64.3 -> 63.8 at 1024^2, unchanged at 2048^2), else the derived tile
+  const sgpe_params& p = c->p;
+  return p.nx / points >= 32 ? 1 : sgpe::row_rows_per_block(p.nx, p.ny, points, c->max_lds / 2);
+}
+
+// 8 points per lane where the length allows it, 16 beyond.  An fp64 lane at 16 points holds 64
+// registers of points and more of roots (over 200 in all, two waves per SIMD, the column kernel
+// spilling); at 8 it runs about 1.1-1.5x the steps/s (1024^2: 17.6k -> 19.3k imaginary, 16.1k ->
+// 21.7k real; 512^2: 37.3k -> 48.3k; 256^2: 61.7k -> 90.8k imaginary steps/s).
+static void default_schedule_c128(sgpe_ctx* c) {
+  const int rp = c->p.nx <= sgpe::kMaxNSmallP ? 8 : 16;
+  const int cp = c->p.ny <= sgpe::kMaxNSmallP ? 8 : 16;
+  c->rows = c128_rows(c, rp);
+  c->cols = c128_cols(c->p.nx, c->p.ny, cp, c->n_cu, c->max_lds);
+  c->row_points = rp;
+  c->col_points = cp;
+  c->row_iters = c->col_iters = 1;
+}
+
+// complex128 schedules: 16 or 8 points per lane in each pass (8 for lengths up to kMaxNSmallP),
+// one row group / column tile per workgroup, at most 256 threads per workgroup unless one line
+// alone needs 512, double2 LDS slots within the device's LDS.
+static sgpe_status apply_schedule_c128(sgpe_ctx* c, const sgpe_schedule& s) {
+  const sgpe_params& p = c->p;
+  auto points_ok = [](int pts, int n) { return pts == 16 || (pts == 8 && n <= sgpe::kMaxNSmallP); };
+  auto bound = [](int n, int pts) { return 2 * n / pts > 256 ? 512 : 256; };
+  if (!points_ok(s.row_points, p.nx) || !points_ok(s.col_points, p.ny)) return SGPE_EINVAL;
+  if (s.row_iters != 1 || s.col_iters != 1 || s.row_tile < 0 || s.col_tile < 1) return SGPE_EINVAL;
+  const int rows = s.row_tile > 0 ? s.row_tile : c128_rows(c, s.row_points);
+  if (rows > p.ny || p.ny % rows != 0 || !sgpe::schedule_supported(p.nx, rows, 1, s.row_points) ||
+      2 * rows * (p.nx / s.row_points) > bound(p.nx, s.row_points) ||
+      2 * sgpe::row_lds_bytes(p.nx, rows) > c->max_lds)
+    return SGPE_EINVAL;
+  const int cols = s.col_tile;
+  if (cols > p.nx || p.nx % cols != 0 || !sgpe::schedule_supported(p.ny, cols, 1, s.col_points) ||
+      2 * cols * (p.ny / s.col_points) > bound(p.ny, s.col_points) ||
+      sgpe::col_lds_bytes_c128(p.ny, cols, s.col_points) > c->max_lds)
+    return SGPE_EINVAL;
+  c->rows = rows;
+  c->cols = cols;
+  c->row_points = s.row_points;
+  c->col_points = s.col_points;
+  c->row_iters = c->col_iters = 1;
+  return SGPE_OK;
 }
 
 sgpe_status sgpe_create(const sgpe_params* p, void* hip_stream, void* psi_dev, sgpe_ctx** out) {
@@ -669,17 +720,10 @@ sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_st
   c->prec = precision;
   default_schedule(c);
   const bool c128 = precision == SGPE_C128;
-  if (c128) {
-    // one row per workgroup where a row takes at least one wave (measured: 29.1 -> 27.5 us per
-    // imaginary step at 512^2, 64.3 -> 63.8 at 1024^2, unchanged at 2048^2), else the derived tile
-    c->rows = p->nx / 16 >= 32 ? 1 : sgpe::row_rows_per_block(p->nx, p->ny, 16, c->max_lds / 2);
-    c->cols = c128_cols(p->nx, p->ny, c->max_lds);
-    c->row_points = c->col_points = 16;
-    c->row_iters = c->col_iters = 1;
-  }
+  if (c128) default_schedule_c128(c);
   c->full2x2 = (p->omega_r0 != 0.0);
   const size_t wb = c128 ? 2 : 1;   // LDS bytes per slot relative to complex64
-  const size_t col_lds = c128 ? sgpe::col_lds_bytes_c128(p->ny, c->cols) : sgpe::col_lds_bytes(p->ny, c->cols);
+  const size_t col_lds = c128 ? sgpe::col_lds_bytes_c128(p->ny, c->cols, c->col_points) : sgpe::col_lds_bytes(p->ny, c->cols);
   if (wb * sgpe::row_lds_bytes(p->nx, c->rows) > c->max_lds || col_lds > c->max_lds ||
       !sgpe::energy_fits(p->nx, p->ny, c->max_lds)) {
     delete c;
@@ -795,7 +839,14 @@ sgpe_status sgpe_get_schedule(sgpe_ctx* c, sgpe_schedule* out) {
 }
 
 sgpe_status sgpe_set_schedule(sgpe_ctx* c, const sgpe_schedule* s) {
-  if (!c || c->prec == SGPE_C128) return SGPE_EINVAL;
+  if (!c) return SGPE_EINVAL;
+  if (c->prec == SGPE_C128) {
+    if (!s) {
+      default_schedule_c128(c);
+      return SGPE_OK;
+    }
+    return apply_schedule_c128(c, *s);
+  }
   if (!s) {
     default_schedule(c);
     return SGPE_OK;

@@ -3,7 +3,7 @@
 //
 // Instances of one grid shape and one real-space operator form (diagonal, or full 2x2 with a
 // spatial Raman coupling) form a class.  Each pass of a class is one launch over all of its
-// members (blockIdx.y = member), the members' arguments read from a device table, so a class of
+// members (each member's workgroups on one XCD), the members' arguments read from a device table, so a class of
 // small grids fills the device where one instance cannot.  Classes run on streams of their own,
 // forked from and joined back to the batch stream, so classes of different sizes overlap.  A
 // call's whole launch sequence can be captured once into a HIP graph and replayed.  Each member
@@ -69,7 +69,7 @@ struct sgpe_batch {
   ColArgs* p_col[2] = {nullptr, nullptr};   // device, [instances]: K(dt), real / imaginary time
   int4* p_row_items = nullptr;
   int4* p_col_items = nullptr;
-  sgpe::PersistClass p_cls[sgpe::kPersistClasses] = {};
+  sgpe::PersistClass* p_cls_dev = nullptr;   // [kPersistGroups][kPersistClasses]
   unsigned* p_words = nullptr;      // device: the grid barrier's words (sgpe::kPersistWords)
   unsigned* p_abort_host = nullptr; // pinned, mapped: a barrier wait gave up
   unsigned* p_abort_host_dev = nullptr;
@@ -165,7 +165,7 @@ hipError_t enqueue_persistent(sgpe_batch* b, int64_t n, bool imag, hipStream_t s
     a.col = b->p_col[imag ? 1 : 0];
     a.row_items = b->p_row_items;
     a.col_items = b->p_col_items;
-    for (int k = 0; k < sgpe::kPersistClasses; ++k) a.cls[k] = b->p_cls[k];
+    a.cls = b->p_cls_dev;
     a.steps = int(n - 1);
     a.first_is_first = 1;
     a.barrier = b->p_words;
@@ -358,7 +358,7 @@ void sgpe_batch_destroy(sgpe_batch* b) {
   for (void* ptr : {static_cast<void*>(b->p_row_first), static_cast<void*>(b->p_row_imag),
                     static_cast<void*>(b->p_col[0]), static_cast<void*>(b->p_col[1]),
                     static_cast<void*>(b->p_row_items), static_cast<void*>(b->p_col_items),
-                    static_cast<void*>(b->p_words)})
+                    static_cast<void*>(b->p_words), static_cast<void*>(b->p_cls_dev)})
     if (ptr) (void)hipFree(ptr);
   if (b->p_abort_host) (void)hipHostFree(b->p_abort_host);
   if (b->fork) (void)hipEventDestroy(b->fork);
@@ -459,7 +459,6 @@ static sgpe_status enable_persistent(sgpe_batch* b) {
   const size_t n = b->inst.size();
   std::vector<RowArgs> first(n), imag(n);
   std::vector<ColArgs> col_r(n), col_i(n);
-  std::vector<int4> ri, ci;
   for (size_t i = 0; i < n; ++i) {
     const sgpe_ctx* c = b->inst[i];
     RowArgs a = row_args(c);
@@ -471,23 +470,6 @@ static sgpe_status enable_persistent(sgpe_batch* b) {
     col_r[i] = col_args(c, false, false);
     col_i[i] = col_args(c, true, false);
   }
-  // items per class: row groups of 1024 / n rows and column tiles of 1024 / n columns
-  sgpe::PersistClass pc[sgpe::kPersistClasses] = {};
-  double weight[sgpe::kPersistClasses] = {};
-  for (size_t kk = 0; kk < b->cls.size(); ++kk) {
-    const auto& k = b->cls[kk];
-    const int groups = k.nx * k.ny / 1024;
-    pc[kk].log2n = __builtin_ctz(k.nx);
-    pc[kk].row_begin = int(ri.size());
-    pc[kk].col_begin = int(ci.size());
-    for (int m : k.members)
-      for (int g = 0; g < groups; ++g) ri.push_back(make_int4(m, g, 0, groups));
-    for (int m : k.members)
-      for (int g = 0; g < groups; ++g) ci.push_back(make_int4(m, g, 0, groups));
-    pc[kk].n_row = int(ri.size()) - pc[kk].row_begin;
-    pc[kk].n_col = int(ci.size()) - pc[kk].col_begin;
-    weight[kk] = double(pc[kk].n_row) * double(pc[kk].log2n);   // an item's cost grows with log2 n
-  }
   auto up = [](auto** dst, const auto& v) {
     using T = std::remove_reference_t<decltype(v[0])>;
     if (!*dst && hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T)) != hipSuccess) return false;
@@ -495,14 +477,6 @@ static sgpe_status enable_persistent(sgpe_batch* b) {
   };
   if (!up(&b->p_row_first, first) || !up(&b->p_row_imag, imag) || !up(&b->p_col[0], col_r) ||
       !up(&b->p_col[1], col_i)) {
-    (void)hipGetLastError();
-    return SGPE_ENOMEM;
-  }
-  if (b->p_row_items) (void)hipFree(b->p_row_items);
-  if (b->p_col_items) (void)hipFree(b->p_col_items);
-  b->p_row_items = nullptr;
-  b->p_col_items = nullptr;
-  if (!up(&b->p_row_items, ri) || !up(&b->p_col_items, ci)) {
     (void)hipGetLastError();
     return SGPE_ENOMEM;
   }
@@ -526,8 +500,8 @@ static sgpe_status enable_persistent(sgpe_batch* b) {
     }
     b->p_abort_host_dev = static_cast<unsigned*>(d);
   }
-  // workgroups: as many as stay co-resident (the smaller of the two instantiations' limits), split
-  // among the classes in proportion to their work, each class at least one and at most its items
+  // workgroups: as many as stay co-resident (the smaller of the two instantiations' limits), in
+  // kPersistGroups groups by index mod kPersistGroups
   const int n_cu = b->inst[0]->n_cu;
   int gmax = 0;
   for (int imagi = 0; imagi < 2; ++imagi) {
@@ -536,31 +510,108 @@ static sgpe_status enable_persistent(sgpe_batch* b) {
     if (e != hipSuccess) return hip_status(e);
     gmax = imagi == 0 ? g : std::min(gmax, g);
   }
-  const int nk = int(b->cls.size());
-  if (gmax < nk) return SGPE_EDEVICE;
-  double wsum = 0.0;
-  for (int k = 0; k < nk; ++k) wsum += weight[k];
-  int total = 0;
-  for (int k = 0; k < nk; ++k) {
-    int w = int(double(gmax) * weight[k] / wsum);
-    w = std::max(1, std::min(w, pc[k].n_row));
-    pc[k].wg_count = w;
-    total += w;
+  constexpr int NG = sgpe::kPersistGroups;
+  int members[NG];
+  int usable = 0;
+  for (int g = 0; g < NG; ++g) {
+    members[g] = gmax > g ? (gmax - g + NG - 1) / NG : 0;
+    usable += members[g] > 0;
   }
-  while (total > gmax) {   // rounding: take back from the largest share
-    int kmax = 0;
-    for (int k = 1; k < nk; ++k)
-      if (pc[k].wg_count > pc[kmax].wg_count) kmax = k;
-    --pc[kmax].wg_count;
-    --total;
+  if (usable == 0) return SGPE_EDEVICE;
+  // every instance to one group: a class of a multiple of 8 members in eight equal runs of members
+  // (the runs that batched launches place on one XCD each), otherwise each member to the group with
+  // the fewest points so far
+  std::vector<int> group_of(n, 0);
+  double load[NG] = {};
+  for (const auto& k : b->cls) {
+    const int cnt = int(k.members.size());
+    for (int j = 0; j < cnt; ++j) {
+      int g = 0;
+      if (cnt % NG == 0 && usable == NG) {
+        g = j / (cnt / NG);
+      } else {
+        for (int h = 1; h < NG; ++h)
+          if (members[h] > 0 && load[h] < load[g]) g = h;
+      }
+      group_of[size_t(k.members[j])] = g;
+      load[g] += double(k.nx) * double(k.ny);
+    }
   }
-  int begin = 0;
-  for (int k = 0; k < nk; ++k) {
-    pc[k].wg_begin = begin;
-    begin += pc[k].wg_count;
+  // per group: the classes present, their items (row groups of 1024 / n rows and column tiles of
+  // 1024 / n columns), and the group's workgroups split among them in proportion to their work
+  sgpe::PersistClass pc[NG][sgpe::kPersistClasses] = {};
+  std::vector<int4> ri, ci;
+  for (int g = 0; g < NG; ++g) {
+    int slot = 0;
+    double weight[sgpe::kPersistClasses] = {};
+    for (const auto& k : b->cls) {
+      const int groups = k.nx * k.ny / 1024;
+      sgpe::PersistClass c{};
+      c.log2n = __builtin_ctz(k.nx);
+      c.row_begin = int(ri.size());
+      c.col_begin = int(ci.size());
+      for (int m : k.members)
+        if (group_of[size_t(m)] == g)
+          for (int q = 0; q < groups; ++q) {
+            ri.push_back(make_int4(m, q, 0, groups));
+            ci.push_back(make_int4(m, q, 0, groups));
+          }
+      c.n_row = int(ri.size()) - c.row_begin;
+      c.n_col = int(ci.size()) - c.col_begin;
+      if (c.n_row == 0) continue;
+      weight[slot] = double(c.n_row) * double(c.log2n);   // an item's cost grows with log2 n
+      pc[g][slot++] = c;
+    }
+    if (slot == 0) continue;
+    if (members[g] < slot) return SGPE_EDEVICE;
+    double wsum = 0.0;
+    for (int k = 0; k < slot; ++k) wsum += weight[k];
+    int total = 0;
+    for (int k = 0; k < slot; ++k) {
+      int w = int(double(members[g]) * weight[k] / wsum);
+      w = std::max(1, std::min(w, pc[g][k].n_row));
+      pc[g][k].wg_count = w;
+      total += w;
+    }
+    while (total > members[g]) {   // rounding: take back from the largest share
+      int kmax = 0;
+      for (int k = 1; k < slot; ++k)
+        if (pc[g][k].wg_count > pc[g][kmax].wg_count) kmax = k;
+      --pc[g][kmax].wg_count;
+      --total;
+    }
+    for (;;) {                      // and hand out the rest where a workgroup has most items
+      int kbest = -1;
+      double best = 0.0;
+      for (int k = 0; k < slot; ++k) {
+        if (pc[g][k].wg_count >= pc[g][k].n_row) continue;
+        const double per = weight[k] / pc[g][k].wg_count;
+        if (kbest < 0 || per > best) kbest = k, best = per;
+      }
+      if (total >= members[g] || kbest < 0) break;
+      ++pc[g][kbest].wg_count;
+      ++total;
+    }
+    int begin = 0;
+    for (int k = 0; k < slot; ++k) {
+      pc[g][k].wg_begin = begin;
+      begin += pc[g][k].wg_count;
+    }
   }
-  for (int k = 0; k < sgpe::kPersistClasses; ++k) b->p_cls[k] = pc[k];
-  b->p_grid = total;
+  if (b->p_row_items) (void)hipFree(b->p_row_items);
+  if (b->p_col_items) (void)hipFree(b->p_col_items);
+  b->p_row_items = nullptr;
+  b->p_col_items = nullptr;
+  if (!up(&b->p_row_items, ri) || !up(&b->p_col_items, ci)) {
+    (void)hipGetLastError();
+    return SGPE_ENOMEM;
+  }
+  std::vector<sgpe::PersistClass> flat(&pc[0][0], &pc[0][0] + NG * sgpe::kPersistClasses);
+  if (!up(&b->p_cls_dev, flat)) {
+    (void)hipGetLastError();
+    return SGPE_ENOMEM;
+  }
+  b->p_grid = gmax;
   // test hook: SGPE_PERSIST_SPIN_LIMIT lowers the bound of the barrier waits, so that a test can
   // make them give up (every workgroup still leaves the kernel normally)
   b->p_spin_limit = sgpe::kPersistSpinLimit;

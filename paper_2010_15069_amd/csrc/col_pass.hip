@@ -18,7 +18,8 @@ namespace sgpe {
 
 
 // One instance: workgroup blockIdx.x of the pass.  A batch of instances of one grid shape:
-// instance blockIdx.y, its arguments from a device table.
+// grid of (items, instances) read by batch_item (all of an instance on one XCD), the instance's
+// arguments from a device table.
 template <int N, int NORM, int ITERS, int P>
 __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) {
   col_body<N, NORM, ITERS, P, true>(a, blockIdx.x, gridDim.x);
@@ -26,14 +27,15 @@ __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) col_kernel(ColArgs a) 
 
 template <int N, int NORM, int P>
 __global__ void __launch_bounds__(512) col_kernel_batch(const ColArgs* __restrict__ tab) {
-  col_body<N, NORM, 1, P, false>(tab[blockIdx.y], blockIdx.x, gridDim.x);
+  const int2 w = batch_item();
+  col_body<N, NORM, 1, P, false>(tab[w.x], w.y, gridDim.x);
 }
 
-// complex128: 16 points per lane, one tile per workgroup; the host keeps tiles at 256 threads
-// except where one column alone needs more (N = 4096)
-template <int N, int NORM>
-__global__ void __launch_bounds__(2 * N / 16 > 256 ? 512 : 256) col_kernel_c128(ColArgsT<double> a) {
-  col_body<N, NORM, 1, 16, false>(a, blockIdx.x, gridDim.x);
+// complex128: 16 (or, for columns up to kMaxNSmallP, 8) points per lane, one tile per workgroup;
+// the host keeps tiles at 256 threads except where one column alone needs more
+template <int N, int NORM, int P>
+__global__ void __launch_bounds__(2 * N / P > 256 ? 512 : 256) col_kernel_c128(ColArgsT<double> a) {
+  col_body<N, NORM, 1, P, false>(a, blockIdx.x, gridDim.x);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -92,37 +94,43 @@ static hipError_t col_dispatch(const ColArgs& a, const ColArgs* tab, int count, 
 }
 
 template <int N, int NORM>
-static hipError_t col_launch_c128(const ColArgsT<double>& a, hipStream_t s) {
-  const dim3 block(2 * a.cols * (N / 16));
+static hipError_t col_launch_c128(const ColArgsT<double>& a, int points, hipStream_t s) {
+  const dim3 block(2 * a.cols * (N / points));
   const dim3 grid(a.nx / a.cols);
-  if (block.x > (2 * N / 16 > 256 ? 512u : 256u)) return hipErrorInvalidValue;
-  const size_t lds = col_lds_bytes_c128(N, a.cols);   // double2 slots and (below 4096 points) the k_y row
-  hipLaunchKernelGGL((col_kernel_c128<N, NORM>), grid, block, lds, s, a);
+  if (block.x > (2 * N / points > 256 ? 512u : 256u)) return hipErrorInvalidValue;
+  const size_t lds = col_lds_bytes_c128(N, a.cols, points);   // double2 slots (and the k_y row)
+  if (points == 16) {
+    hipLaunchKernelGGL((col_kernel_c128<N, NORM, 16>), grid, block, lds, s, a);
+  } else if constexpr (N <= kMaxNSmallP) {
+    hipLaunchKernelGGL((col_kernel_c128<N, NORM, 8>), grid, block, lds, s, a);
+  }
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t col_launch_c128_n(const ColArgsT<double>& a, int norm_mode, hipStream_t s) {
+static hipError_t col_launch_c128_n(const ColArgsT<double>& a, int norm_mode, int points, hipStream_t s) {
   switch (norm_mode) {
-    case NORM_NONE: return col_launch_c128<N, NORM_NONE>(a, s);
-    case NORM_DOT: return col_launch_c128<N, NORM_DOT>(a, s);
-    case NORM_SQ: return col_launch_c128<N, NORM_SQ>(a, s);
+    case NORM_NONE: return col_launch_c128<N, NORM_NONE>(a, points, s);
+    case NORM_DOT: return col_launch_c128<N, NORM_DOT>(a, points, s);
+    case NORM_SQ: return col_launch_c128<N, NORM_SQ>(a, points, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_col(const ColArgsT<double>& a, int norm_mode, hipStream_t s) {
-  if (!schedule_supported(a.ny, a.cols, 1, 16) || a.cols > a.nx || a.nx % a.cols != 0) return hipErrorInvalidValue;
+hipError_t launch_col(const ColArgsT<double>& a, int norm_mode, int points, hipStream_t s) {
+  if ((points != 16 && points != 8) || !schedule_supported(a.ny, a.cols, 1, points) || a.cols > a.nx ||
+      a.nx % a.cols != 0)
+    return hipErrorInvalidValue;
   switch (a.ny) {
-    case 16: return col_launch_c128_n<16>(a, norm_mode, s);
-    case 32: return col_launch_c128_n<32>(a, norm_mode, s);
-    case 64: return col_launch_c128_n<64>(a, norm_mode, s);
-    case 128: return col_launch_c128_n<128>(a, norm_mode, s);
-    case 256: return col_launch_c128_n<256>(a, norm_mode, s);
-    case 512: return col_launch_c128_n<512>(a, norm_mode, s);
-    case 1024: return col_launch_c128_n<1024>(a, norm_mode, s);
-    case 2048: return col_launch_c128_n<2048>(a, norm_mode, s);
-    case 4096: return col_launch_c128_n<4096>(a, norm_mode, s);
+    case 16: return col_launch_c128_n<16>(a, norm_mode, points, s);
+    case 32: return col_launch_c128_n<32>(a, norm_mode, points, s);
+    case 64: return col_launch_c128_n<64>(a, norm_mode, points, s);
+    case 128: return col_launch_c128_n<128>(a, norm_mode, points, s);
+    case 256: return col_launch_c128_n<256>(a, norm_mode, points, s);
+    case 512: return col_launch_c128_n<512>(a, norm_mode, points, s);
+    case 1024: return col_launch_c128_n<1024>(a, norm_mode, points, s);
+    case 2048: return col_launch_c128_n<2048>(a, norm_mode, points, s);
+    case 4096: return col_launch_c128_n<4096>(a, norm_mode, points, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -6,20 +6,26 @@
 // one instance, a column item 1024 / ny columns.  Each item runs in a 256-thread workgroup at 8 points
 // per lane, with the same device bodies (row_body, col_body) and the same per-instance arguments
 // as the single-instance and per-class launches, so every instance computes exactly what a single
-// context with that schedule computes.  The workgroups stay resident for the whole launch and take
-// items round-robin; the steps of the split step (Sec. 3.2's K(dt/2) R(dt) K(dt/2) with the adjacent
-// K halves merged) alternate a row phase (inverse x-FFT, scale, R(dt), forward x-FFT for every row
-// item of every instance) and a column phase (forward y-FFT, K(dt) and the imaginary-time norm
-// partials, inverse y-FFT for every column item), with a grid-wide barrier after each phase.
+// context with that schedule computes.  The steps of the split step (Sec. 3.2's K(dt/2) R(dt) K(dt/2)
+// with the adjacent K halves merged) alternate a row phase (inverse x-FFT, scale, R(dt), forward
+// x-FFT for every row item) and a column phase (forward y-FFT, K(dt) and the imaginary-time norm
+// partials, inverse y-FFT for every column item), with a barrier after each phase.
+//
+// The workgroups stay resident for the whole launch.  They form eight groups by blockIdx.x mod 8:
+// the dispatcher deals a launch's workgroups to the eight XCDs in turn, so a group is the
+// workgroups of one XCD (which one depends on where its rotation stood).  Every instance belongs to one group and is stepped by that group's workgroups alone, so the
+// all-to-all between the row and the column phase of its transforms stays within one L2, and a
+// barrier joins one group's workgroups only; groups never wait for each other.  Correctness does
+// not depend on where a group runs: the barrier counts the group's workgroups, whatever their XCD.
 //
 // The barrier: after a workgroup's __syncthreads, its first thread makes the workgroup's writes
-// visible device-wide (an agent-scope fence; the state stores go through the L2 as they are issued)
-// and adds one to a device counter, then waits until the counter reaches the phase's target
-// (in two levels, see persist_barrier), then fences again so that its reads see every other
-// workgroup's writes.  The wait is bounded: after spin_limit polls a workgroup gives up, sets an abort word
-// that every other waiting workgroup also polls, records the failure in host-visible memory and
-// returns; every workgroup then leaves at its next barrier, and the host reports SGPE_EDEVICE.  A
-// small kernel zeroes the counter and the abort word before each launch (graph-replay safe).
+// visible device-wide (an agent-scope fence; the state stores go through the L2 as they are
+// issued), adds one to its group's counter and waits until the counter reaches the phase's target,
+// then fences again so that its reads see every other workgroup's writes.  The wait is bounded:
+// after spin_limit polls a workgroup gives up, sets an abort word that every waiting workgroup also
+// polls, records the failure in host-visible memory and returns; every workgroup then leaves at its
+// next barrier, and the host reports SGPE_EDEVICE.  A small kernel zeroes the counters and the abort
+// word before each launch (graph-replay safe).
 #include "col_body.hpp"
 #include "row_body.hpp"
 
@@ -42,32 +48,17 @@ __device__ __forceinline__ bool persist_wait(const PersistArgs& a, const unsigne
   }
 }
 
-// Grid barrier number `nb` (1, 2, ...) of the launch, in two levels so that no counter takes more
-// than about a ninth of the workgroups' atomics: the workgroups with the same blockIdx.x mod 8 (one
-// slot; workgroups are dealt to the 8 XCDs in that order) count on their slot's word; the last of a
-// slot counts on the global word and, once every slot has, releases its slot.  The counts of a slot
-// are known from gridDim.x alone, so correctness does not depend on where the workgroups run.
+// Barrier number `nb` (1, 2, ...) of the launch among the workgroups of this one's group.
 __device__ __forceinline__ bool persist_barrier(const PersistArgs& a, unsigned nb) {
   __shared__ int ok_s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned g = gridDim.x;
-    const unsigned slot = blockIdx.x & 7u;
-    const unsigned per_slot = (g - slot + 7u) / 8u;
-    const unsigned slots = g < 8u ? g : 8u;
-    unsigned* count = a.barrier + kPersistWordStride * slot;
-    unsigned* global = a.barrier + kPersistWordStride * 8;
-    unsigned* release = a.barrier + kPersistWordStride * (9 + slot);
+    const unsigned grp = blockIdx.x % kPersistGroups;
+    const unsigned members = (gridDim.x - grp + kPersistGroups - 1) / kPersistGroups;
+    unsigned* count = a.barrier + kPersistWordStride * grp;
     __threadfence();
-    const unsigned old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool ok;
-    if (old == per_slot * nb - 1u) {
-      __hip_atomic_fetch_add(global, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ok = persist_wait(a, global, slots * nb);
-      if (ok) __hip_atomic_store(release, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      ok = persist_wait(a, release, nb);
-    }
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool ok = persist_wait(a, count, members * nb);
     __threadfence();
     ok_s = ok ? 1 : 0;
   }
@@ -75,22 +66,23 @@ __device__ __forceinline__ bool persist_barrier(const PersistArgs& a, unsigned n
   return ok_s != 0;
 }
 
-// One class's workgroups run all the launch's steps of that class's instances with the body of its
-// grid size, so only that body's per-lane constants are live in them; every workgroup of every
-// class meets at every barrier.
+// One class's workgroups (in one group) run all the launch's steps of that class's instances in the
+// group with the body of its grid size, so only that body's per-lane constants are live in them;
+// every workgroup of the group meets at every barrier (one beyond its class's share takes no items).
 template <int N, bool IMAG>
 __device__ __forceinline__ void persist_class(const PersistArgs& a, const PersistClass& k, int local) {
   constexpr int NORM = IMAG ? NORM_DOT : NORM_NONE;
+  const int first = local < k.wg_count ? local : k.n_row + k.n_col;   // past every item: idle
   unsigned nb = 0;
   for (int s = 0; s < a.steps; ++s) {
     const RowArgs* rows = (s == 0 && a.first_is_first) ? a.row_first : a.row_step;
-    for (int i = local; i < k.n_row; i += k.wg_count) {
+    for (int i = first; i < k.n_row; i += k.wg_count) {
       const int4 it = a.row_items[k.row_begin + i];
       row_body<N, ROW_STEP, IMAG, false, 1, 8, true>(rows[it.x], it.y);
       __syncthreads();
     }
     if (!persist_barrier(a, ++nb)) return;
-    for (int i = local; i < k.n_col; i += k.wg_count) {
+    for (int i = first; i < k.n_col; i += k.wg_count) {
       const int4 it = a.col_items[k.col_begin + i];
       col_body<N, NORM, 1, 8, true>(a.col[it.x], it.y, it.w);
       __syncthreads();
@@ -99,13 +91,19 @@ __device__ __forceinline__ void persist_class(const PersistArgs& a, const Persis
   }
 }
 
+// Two waves per SIMD: the three grid sizes' bodies and their item loops need ~219 VGPRs; held to
+// 168 for three waves they spill 200 bytes per lane, and the sweep ran at 243k instead of 311k
+// instance-steps/s.
 template <bool IMAG>
-__global__ void __launch_bounds__(256, 3) persist_kernel(PersistArgs a) {
-  const int b = static_cast<int>(blockIdx.x);
+__global__ void __launch_bounds__(256, 2) persist_kernel(PersistArgs a) {
+  const int grp = static_cast<int>(blockIdx.x % kPersistGroups);
+  const int j = static_cast<int>(blockIdx.x / kPersistGroups);
+  const PersistClass* cg = a.cls + grp * kPersistClasses;
+  if (cg[0].log2n == 0) return;   // a group without instances: nobody waits for it
   int k = 0;
-  while (k + 1 < kPersistClasses && a.cls[k + 1].log2n != 0 && b >= a.cls[k + 1].wg_begin) ++k;
-  const PersistClass& c = a.cls[k];
-  const int local = b - c.wg_begin;
+  while (k + 1 < kPersistClasses && cg[k + 1].log2n != 0 && j >= cg[k + 1].wg_begin) ++k;
+  const PersistClass c = cg[k];
+  const int local = j - c.wg_begin;
   switch (c.log2n) {
     case 7: persist_class<128, IMAG>(a, c, local); break;
     case 8: persist_class<256, IMAG>(a, c, local); break;

@@ -1,4 +1,5 @@
-// Host side of the measurement probe declared in include/sgpe.h (sgpe_probe_exchange).
+// Host side of the measurement probes declared in include/sgpe.h (sgpe_probe_exchange,
+// sgpe_probe_placement).
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -95,5 +96,25 @@ extern "C" sgpe_status sgpe_probe_exchange(int32_t nx, int32_t ny, int32_t layou
   if (row_ms) *row_ms = tr / reps;
   if (col_ms) *col_ms = tc / reps;
   if (pair_ms) *pair_ms = tp / reps;
+  return SGPE_OK;
+}
+
+extern "C" sgpe_status sgpe_probe_placement(int32_t gx, int32_t gy, int32_t threads, uint32_t* xcd) {
+  if (!xcd || gx < 1 || gy < 1 || gy > 65535 || threads < 1 || threads > 1024 ||
+      int64_t(gx) * int64_t(gy) > (int64_t(1) << 24))
+    return SGPE_EINVAL;
+  const size_t n = size_t(gx) * size_t(gy);
+  void* d = nullptr;
+  if (hipMalloc(&d, n * sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_ENOMEM;
+  }
+  hipError_t e = sgpe::launch_probe_xcc(static_cast<unsigned*>(d), gx, gy, threads, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(xcd, d, n * sizeof(unsigned), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
   return SGPE_OK;
 }

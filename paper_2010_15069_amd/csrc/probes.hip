@@ -165,4 +165,18 @@ hipError_t launch_probe_cols(const float4* src, float4* dst, int nx, int ny, int
   return hipGetLastError();
 }
 
+// Placement: thread 0 of every workgroup records the XCD it runs on (hardware register XCC_ID,
+// bits 3:0) at out[blockIdx.y * gridDim.x + blockIdx.x].
+__global__ void probe_xcc_kernel(unsigned* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    const unsigned id = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u;   // hwreg(XCC_ID, 0, 4)
+    out[blockIdx.y * gridDim.x + blockIdx.x] = id;
+  }
+}
+
+hipError_t launch_probe_xcc(unsigned* out, int gx, int gy, int threads, hipStream_t s) {
+  hipLaunchKernelGGL(probe_xcc_kernel, dim3(gx, gy), dim3(threads), 0, s, out);
+  return hipGetLastError();
+}
+
 }  // namespace sgpe

@@ -15,9 +15,10 @@ size_t row_lds_bytes(int nx, int rows) { return size_t(rows) * size_t(nx + nx / 
 // column pass: the transforms' exchange slots, then the k_y operator row (one float2 per k_y)
 size_t col_lds_bytes(int ny, int cols) { return size_t(cols) * size_t(ny + ny / 16) * 16 + size_t(ny) * 8; }
 
-// complex128 column pass: double2 slots, and the k_y row (one double2 per k_y) below 4096 points
-size_t col_lds_bytes_c128(int ny, int cols) {
-  return size_t(cols) * size_t(ny + ny / 16) * 32 + (ny >= 4096 ? 0 : size_t(ny) * 16);
+// complex128 column pass: double2 slots, and the k_y row (one double2 per k_y) where the kernel
+// stages it in LDS (16 points per lane, below 4096 points)
+size_t col_lds_bytes_c128(int ny, int cols, int points) {
+  return size_t(cols) * size_t(ny + ny / 16) * 32 + (points != 16 || ny >= 4096 ? 0 : size_t(ny) * 16);
 }
 
 int row_rows_per_block(int nx, int ny, int points, size_t max_lds) {

@@ -35,22 +35,24 @@ __global__ void __launch_bounds__(2 * N / P > 256 ? 512 : 256) row_var_kernel(Ro
 }
 
 // One instance: workgroup blockIdx.x of the pass.  A batch of instances of one grid shape:
-// instance blockIdx.y, its arguments from a device table.
+// grid of (items, instances) read by batch_item (all of an instance on one XCD), the instance's
+// arguments from a device table.
 template <int N, int MODE, bool IMAG, bool FULL, int ITERS, int P>
 __global__ void __launch_bounds__(ITERS == 2 ? 256 : 512) row_kernel(RowArgs a) {
   row_body<N, MODE, IMAG, FULL, ITERS, P, true>(a, blockIdx.x);
 }
 
-// complex128: 16 points per lane, one row group per workgroup; row groups are sized for 256
-// threads except at N = 4096 (512)
-template <int N, int MODE, bool IMAG, bool FULL>
-__global__ void __launch_bounds__(2 * N / 16 > 256 ? 512 : 256) row_kernel_c128(RowArgsT<double> a) {
-  row_body<N, MODE, IMAG, FULL, 1, 16, false>(a, blockIdx.x);
+// complex128: 16 (or, for rows up to kMaxNSmallP, 8) points per lane, one row group per
+// workgroup; row groups are sized for 256 threads except where one row needs 512
+template <int N, int MODE, bool IMAG, bool FULL, int P>
+__global__ void __launch_bounds__(2 * N / P > 256 ? 512 : 256) row_kernel_c128(RowArgsT<double> a) {
+  row_body<N, MODE, IMAG, FULL, 1, P, false>(a, blockIdx.x);
 }
 
 template <int N, int MODE, bool IMAG, bool FULL, int P>
 __global__ void __launch_bounds__(512) row_kernel_batch(const RowArgs* __restrict__ tab) {
-  row_body<N, MODE, IMAG, FULL, 1, P, false>(tab[blockIdx.y], blockIdx.x);
+  const int2 w = batch_item();
+  row_body<N, MODE, IMAG, FULL, 1, P, false>(tab[w.x], w.y);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -127,40 +129,48 @@ static hipError_t row_dispatch(const RowArgs& a, const RowArgs* tab, int count, 
 }
 
 template <int N, int MODE, bool IMAG, bool FULL>
-static hipError_t row_launch_c128(const RowArgsT<double>& a, hipStream_t s) {
-  const dim3 block(2 * a.rows_per_block * (N / 16));
+static hipError_t row_launch_c128(const RowArgsT<double>& a, int points, hipStream_t s) {
+  const dim3 block(2 * a.rows_per_block * (N / points));
   const dim3 grid(a.ny / a.rows_per_block);
-  if (block.x > (2 * N / 16 > 256 ? 512u : 256u)) return hipErrorInvalidValue;
+  if (block.x > (2 * N / points > 256 ? 512u : 256u)) return hipErrorInvalidValue;
   const size_t lds = 2 * row_lds_bytes(N, a.rows_per_block);   // double2 slots
-  hipLaunchKernelGGL((row_kernel_c128<N, MODE, IMAG, FULL>), grid, block, lds, s, a);
+  if (points == 16) {
+    hipLaunchKernelGGL((row_kernel_c128<N, MODE, IMAG, FULL, 16>), grid, block, lds, s, a);
+  } else if constexpr (N <= kMaxNSmallP) {
+    hipLaunchKernelGGL((row_kernel_c128<N, MODE, IMAG, FULL, 8>), grid, block, lds, s, a);
+  }
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t row_launch_c128_n(const RowArgsT<double>& a, int mode, bool imag, bool full, hipStream_t s) {
+static hipError_t row_launch_c128_n(const RowArgsT<double>& a, int mode, bool imag, bool full, int points,
+                                    hipStream_t s) {
   switch (mode) {
-    case ROW_FWD: return row_launch_c128<N, ROW_FWD, false, false>(a, s);
-    case ROW_INV: return row_launch_c128<N, ROW_INV, false, false>(a, s);
+    case ROW_FWD: return row_launch_c128<N, ROW_FWD, false, false>(a, points, s);
+    case ROW_INV: return row_launch_c128<N, ROW_INV, false, false>(a, points, s);
     case ROW_STEP:
-      if (imag) return full ? row_launch_c128<N, ROW_STEP, true, true>(a, s) : row_launch_c128<N, ROW_STEP, true, false>(a, s);
-      return full ? row_launch_c128<N, ROW_STEP, false, true>(a, s) : row_launch_c128<N, ROW_STEP, false, false>(a, s);
+      if (imag) return full ? row_launch_c128<N, ROW_STEP, true, true>(a, points, s)
+                            : row_launch_c128<N, ROW_STEP, true, false>(a, points, s);
+      return full ? row_launch_c128<N, ROW_STEP, false, true>(a, points, s)
+                  : row_launch_c128<N, ROW_STEP, false, false>(a, points, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_row(const RowArgsT<double>& a, int mode, bool imag, bool full, hipStream_t s) {
-  if (!schedule_supported(a.nx, a.rows_per_block, 1, 16)) return hipErrorInvalidValue;
+hipError_t launch_row(const RowArgsT<double>& a, int mode, bool imag, bool full, int points, hipStream_t s) {
+  if ((points != 16 && points != 8) || !schedule_supported(a.nx, a.rows_per_block, 1, points))
+    return hipErrorInvalidValue;
   if (a.ny % a.rows_per_block != 0) return hipErrorInvalidValue;
   switch (a.nx) {
-    case 16: return row_launch_c128_n<16>(a, mode, imag, full, s);
-    case 32: return row_launch_c128_n<32>(a, mode, imag, full, s);
-    case 64: return row_launch_c128_n<64>(a, mode, imag, full, s);
-    case 128: return row_launch_c128_n<128>(a, mode, imag, full, s);
-    case 256: return row_launch_c128_n<256>(a, mode, imag, full, s);
-    case 512: return row_launch_c128_n<512>(a, mode, imag, full, s);
-    case 1024: return row_launch_c128_n<1024>(a, mode, imag, full, s);
-    case 2048: return row_launch_c128_n<2048>(a, mode, imag, full, s);
-    case 4096: return row_launch_c128_n<4096>(a, mode, imag, full, s);
+    case 16: return row_launch_c128_n<16>(a, mode, imag, full, points, s);
+    case 32: return row_launch_c128_n<32>(a, mode, imag, full, points, s);
+    case 64: return row_launch_c128_n<64>(a, mode, imag, full, points, s);
+    case 128: return row_launch_c128_n<128>(a, mode, imag, full, points, s);
+    case 256: return row_launch_c128_n<256>(a, mode, imag, full, points, s);
+    case 512: return row_launch_c128_n<512>(a, mode, imag, full, points, s);
+    case 1024: return row_launch_c128_n<1024>(a, mode, imag, full, points, s);
+    case 2048: return row_launch_c128_n<2048>(a, mode, imag, full, points, s);
+    case 4096: return row_launch_c128_n<4096>(a, mode, imag, full, points, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -127,12 +127,14 @@ inline bool schedule_supported(int n, int groups, int iters, int points) {
 
 hipError_t launch_row(const RowArgs& a, int mode, bool imag, bool full2x2, int iters, int points, hipStream_t s);
 hipError_t launch_col(const ColArgs& a, int norm_mode, int iters, int points, hipStream_t s);
-// complex128: 16 points per lane, one row group / column tile per workgroup, the step modes only
-hipError_t launch_row(const RowArgsT<double>& a, int mode, bool imag, bool full2x2, hipStream_t s);
-hipError_t launch_col(const ColArgsT<double>& a, int norm_mode, hipStream_t s);
+// complex128: 16 or 8 points per lane (8 for lengths up to kMaxNSmallP), one row group / column
+// tile per workgroup, the step modes only
+hipError_t launch_row(const RowArgsT<double>& a, int mode, bool imag, bool full2x2, int points, hipStream_t s);
+hipError_t launch_col(const ColArgsT<double>& a, int norm_mode, int points, hipStream_t s);
 // Batches of instances of one grid shape: `shape` gives the geometry (every table entry must
 // share nx, ny, rows_per_block / cols); instance i's arguments are tab[i] (device memory), and
-// it is blockIdx.y = i of one launch.  One row group / column tile per workgroup.
+// the launch holds (ny / rows or nx / cols) x count workgroups, and batch_item places all of an
+// instance's workgroups on one XCD.  One row group / column tile per workgroup.
 hipError_t launch_row_batch(const RowArgs& shape, const RowArgs* tab, int count, int mode, bool imag, bool full2x2,
                             int points, hipStream_t s);
 hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count, int norm_mode, int points,
@@ -165,12 +167,15 @@ hipError_t launch_winding(const double4* psi, int nx, int ny, double xmax, doubl
 // Persistent step kernel of a batch (persist.hip).  Square grids of n = 128, 256 or 512 points per
 // axis, one class per n.  Work items are int4 {instance, group, -, groups of that instance in the
 // pass}; a row item is 1024 / n rows, a column item 1024 / n columns, 8 points per lane, 256
-// threads.  The workgroups are split among the classes in proportion to their work; a workgroup
-// takes its class's items round-robin.
+// threads.  The workgroups form kPersistGroups groups by blockIdx.x mod kPersistGroups (one XCD
+// each); every instance belongs to one group, whose workgroups alone step it and meet at the
+// group's barriers.  Within a group the workgroups are split among the classes present in
+// proportion to their work; a workgroup takes its class's items round-robin.
 constexpr int kPersistClasses = 3;
+constexpr int kPersistGroups = 8;
 struct PersistClass {
-  int log2n;                  // 0: unused slot
-  int wg_begin, wg_count;     // this class's workgroups
+  int log2n;                  // 0: unused slot (the group's classes come first)
+  int wg_begin, wg_count;     // this class's workgroups, by index within the group
   int row_begin, n_row;       // its row items in row_items
   int col_begin, n_col;       // its column items in col_items
 };
@@ -180,19 +185,18 @@ struct PersistArgs {
   const ColArgs* col;         // per instance: K(dt), norm partials in imaginary time
   const int4* row_items;
   const int4* col_items;
-  PersistClass cls[kPersistClasses];
+  const PersistClass* cls;    // [kPersistGroups][kPersistClasses], device memory
   int steps;                  // steady-state steps in this launch
   int first_is_first;         // 1: the launch's first step is the call's first (row_first)
-  unsigned* barrier;          // device words of the grid barrier, kPersistWords (zeroed per launch)
+  unsigned* barrier;          // device words of the group barriers, kPersistWords (zeroed per launch)
   unsigned* abort_host;       // host-visible: a barrier wait gave up
   unsigned spin_limit;        // polls before a barrier wait gives up
 };
 constexpr unsigned kPersistSpinLimit = 4u << 20;   // ~4M polls of ~0.5 us or more: seconds, not a hang
-// barrier words, each on its own 256-byte line: 8 slot counters, the global counter, 8 slot
-// releases, the abort word
+// barrier words, each on its own 256-byte line: one counter per group, then the abort word
 constexpr int kPersistWordStride = 64;
-constexpr int kPersistAbortWord = kPersistWordStride * 17;
-constexpr int kPersistWords = kPersistWordStride * 18;
+constexpr int kPersistAbortWord = kPersistWordStride * kPersistGroups;
+constexpr int kPersistWords = kPersistWordStride * (kPersistGroups + 1);
 size_t persist_lds_bytes();
 // Largest co-resident grid of the persistent kernel on a device with n_cu compute units.
 hipError_t persist_max_grid(bool imag, int n_cu, int* grid);
@@ -207,6 +211,8 @@ hipError_t launch_probe_cols(const float4* src, float4* dst, int nx, int ny, int
                              bool write_through, hipStream_t s);
 // the same with a wave owning a whole row (column), both components per lane; `waves` lines per
 // workgroup; lengths 512, 1024, 2048
+// One record per workgroup of a gx x gy grid of `threads`: the XCD that ran it.
+hipError_t launch_probe_xcc(unsigned* out, int gx, int gy, int threads, hipStream_t s);
 hipError_t launch_probe_rows_wl(const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
                                 bool write_through, hipStream_t s);
 hipError_t launch_probe_cols_wl(const float4* src, float4* dst, int nx, int ny, int layout_rows, int waves,
@@ -221,7 +227,7 @@ bool energy_fits(int nx, int ny, size_t max_lds);
 int energy_cols_per_block(int nx, int ny, size_t max_lds);
 size_t row_lds_bytes(int nx, int rows);
 size_t col_lds_bytes(int ny, int cols);
-size_t col_lds_bytes_c128(int ny, int cols);
+size_t col_lds_bytes_c128(int ny, int cols, int points);
 int norm_blocks();
 
 }  // namespace sgpe

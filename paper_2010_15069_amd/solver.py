@@ -320,3 +320,11 @@ def probe_exchange(nx, ny, layout_rows=1, row_tile=1, col_tile=4, write_through=
                                     int(reps), ctypes.byref(r), ctypes.byref(c), ctypes.byref(pr)),
           "sgpe_probe_exchange")
     return r.value, c.value, pr.value
+
+
+def probe_placement(gx, gy=1, threads=256):
+    """sgpe_probe_placement: the XCD index that ran each workgroup of a gx x gy grid, as a numpy
+    array of shape (gy, gx)."""
+    out = (ctypes.c_uint32 * (int(gx) * int(gy)))()
+    check(lib().sgpe_probe_placement(int(gx), int(gy), int(threads), out), "sgpe_probe_placement")
+    return np.frombuffer(out, dtype=np.uint32).reshape(int(gy), int(gx)).copy()

@@ -225,3 +225,8 @@ def test_probe_rejects_invalid_arguments_before_device_work(lib):
     assert lib.sgpe_probe_exchange(1024, 1024, 1, 16, 4, 0, 10, None, None, None) == 1  # 2048 threads
     assert lib.sgpe_probe_exchange(256, 1024, 1, 1, 1, 2, 10, None, None, None) == 1    # wave-local: >= 512
     assert lib.sgpe_probe_exchange(1024, 1024, 1, 1, 4, 0, 0, ctypes.byref(d), None, None) == 1   # reps
+    out = (ctypes.c_uint32 * 8)()
+    assert lib.sgpe_probe_placement(8, 1, 64, None) == 1            # NULL output
+    assert lib.sgpe_probe_placement(0, 1, 64, out) == 1             # empty grid
+    assert lib.sgpe_probe_placement(8, 70000, 64, out) == 1         # gy beyond the 2D limit
+    assert lib.sgpe_probe_placement(8, 1, 2048, out) == 1           # more than 1024 threads

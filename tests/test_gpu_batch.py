@@ -137,3 +137,17 @@ def test_batch_errors(sgpe):
     with pytest.raises(sgpe.SgpeError):
         b.set_schedule(0, row_iters=2)   # batched launches take one tile per workgroup
     b.close()
+
+
+def test_workgroup_placement_follows_dispatch_order(sgpe):
+    # The batched and persistent launches keep an instance's workgroups on one XCD by relying on
+    # the dispatcher's order: workgroup L of a launch (x fastest) runs on XCD (s + L) mod 8, where s
+    # is where the dispatcher's rotation stood when the launch began.  Results never depend on it,
+    # only the locality does.  The probe reads each workgroup's hardware XCC_ID.
+    from paper_2010_15069_amd import probe_placement
+    for gx, gy, threads in [(1024, 1, 256), (64, 32, 256), (7, 32, 128), (768, 1, 256), (13, 1, 64)]:
+        xcd = probe_placement(gx, gy, threads).ravel()
+        print(f"case: placement {gx}x{gy}x{threads}: first 16 {xcd[:16].tolist()}", flush=True)
+        assert xcd.max() < 8
+        shift = (xcd.astype(np.int64) - np.arange(gx * gy)) % 8
+        assert np.all(shift == shift[0]), np.unique(shift)

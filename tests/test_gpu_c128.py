@@ -4,7 +4,7 @@ parameter of the same kernels) against the FP64 oracle, through the C ABI.
 Both sides compute in fp64, so the bar is rounding: psi relative L2 <= 1e-12 and energies within
 1e-11 (the two FFT algorithms round differently; measured after hundreds of steps: 2e-14 to 7e-14).  Cases: the tiny workload as written (64^2, complex128, imaginary then real time), the
 512^2 real-time physics, the spatial Raman full 2x2 exponential, ragged and extreme shapes, the
-full 1024^2 grid, unitarity, observables, and the error paths of the fixed complex128 schedule."""
+full 1024^2 grid, 8 points per lane, unitarity, observables, and the complex128 schedule's limits."""
 import os
 
 import numpy as np
@@ -98,6 +98,33 @@ def test_ragged_shapes(Solver, nx, ny):
     check(o, s)
 
 
+SCHEDULES_C128 = [dict(row_points=16, col_points=16, col_tile=1), dict(row_points=8, col_points=16, col_tile=1),
+                  dict(row_points=16, col_points=8, col_tile=1), dict(row_points=8, col_points=8, col_tile=2)]
+
+
+@pytest.mark.parametrize("nx,ny", [(1024, 1024), (64, 512), (512, 32)])
+@pytest.mark.parametrize("sched", range(len(SCHEDULES_C128)))
+def test_points_per_lane_schedules(Solver, nx, ny, sched):
+    # the transforms at 16 and 8 points per lane in either pass (different radix decompositions,
+    # the same bar); the default (8 up to 1024 points) runs in every other test here
+    p = Params(nx=nx, ny=ny, xmax=10.0, ymax=9.0, g_uu=8.0, g_dd=6.0, g_ud=7.0, k_l=2.0, omega=1.0, delta=0.2,
+               dt=1e-3)
+    psi0 = initial_state(p, "tf", seed=7)
+    o, s = pair(Solver, p, psi0)
+    try:
+        s.set_schedule(**SCHEDULES_C128[sched], row_tile=0)
+    except Exception as e:
+        assert "SGPE_EINVAL" in str(e)
+        pytest.skip(f"schedule not supported at {nx}x{ny}")
+    print(f"case: c128 {nx}x{ny} schedule {s.get_schedule()}", flush=True)
+    steps = 5 if nx * ny >= 1 << 20 else 100
+    o.step_imag(steps)
+    s.step_imag(steps)
+    o.step_real(steps)
+    s.step_real(steps)
+    check(o, s)
+
+
 def test_full_size_1024(Solver):
     p = preset("metric_1024")
     o, s = pair(Solver, p, initial_state(p, "tf", seed=0))
@@ -143,11 +170,24 @@ def test_fixed_schedule_and_limits(Solver):
     from paper_2010_15069_amd._lib import lib
     p = preset("tiny")
     s = Solver(p, precision="c128").set_psi(initial_state(p, "gauss", seed=0))
-    assert s.get_schedule()["row_points"] == 16 and s.get_schedule()["row_iters"] == 1
-    with pytest.raises(SgpeError, match="SGPE_EINVAL"):
-        s.set_schedule(col_tile=1)
+    # 8 points per lane up to 1024 points per axis by default
+    assert s.get_schedule()["row_points"] == 8 and s.get_schedule()["row_iters"] == 1
+    default = s.get_schedule()
+    # no prefetch, 16 or 8 points per lane only, at most 256 threads where a line needs fewer
+    for bad in (dict(row_iters=2), dict(col_iters=2), dict(row_points=4), dict(col_points=4),
+                dict(col_tile=64), dict(row_tile=64)):
+        with pytest.raises(SgpeError, match="SGPE_EINVAL"):
+            s.set_schedule(**bad)
+        assert s.get_schedule() == default, bad
     with pytest.raises(SgpeError, match="SGPE_EINVAL"):
         s.set_col_tile(2)
+    s.set_schedule(row_points=16, col_points=16, col_tile=1)
+    assert s.get_schedule()["row_points"] == 16
+    s.set_schedule(None)
+    assert s.get_schedule() == default
+    q = Params(nx=2048, ny=16, xmax=8.0, ymax=6.0)
+    with pytest.raises(SgpeError, match="SGPE_EINVAL"):
+        Solver(q, precision="c128").set_schedule(row_points=8)   # 8 points per lane up to 1024
     with pytest.raises(SgpeError, match="SGPE_EINVAL"):
         s.set_splitting("rkr", "frozen")
     with pytest.raises(SgpeError, match="SGPE_ESTATE"):
