@@ -13,36 +13,39 @@ namespace sgpe {
 // -------------------------------------------------------------------------------------------
 // Sum of the previous column pass's partials -> scale for the row pass.  Every wave computes
 // the same sum in the same order (lane l adds partials l, l + 64, ... in turn, then a fixed
-// butterfly across the wave), so every workgroup applies bit-identical scales.  Up to 256
-// partials are loaded at kernel start as four masked loads per lane, ahead of the data (a
+// butterfly across the wave), so every workgroup applies bit-identical scales.  Up to 64 K
+// partials are loaded at kernel start as K masked loads per lane, ahead of the data (a
 // runtime-length loop of loads would make the wave wait for every outstanding load); more
 // partials, or workgroups narrower than a wave, take the loop after the inverse transform.
+// K = 4 (256 partials), and 16 (1024) for complex128 rows of up to 1024 points, whose 1-column
+// tiles leave nx partials.
 // -------------------------------------------------------------------------------------------
-constexpr int kPrefetchPartials = 256;
+template <class R, int N>
+constexpr int prefetch_per_lane() { return sizeof(R) == 8 && N <= 1024 ? 16 : 4; }
 
-template <class A>
-__device__ __forceinline__ void prefetch_partials(const A& a, double (&pv)[4]) {
+template <class A, int K>
+__device__ __forceinline__ void prefetch_partials(const A& a, double (&pv)[K]) {
   const int lane = threadIdx.x & 63;
   // a uniform branch around unconditional loads (indices clamped into range; the surplus
   // masked out at the sum), so no lane-dependent control flow waits on a load
-  if (a.partials != nullptr && a.n_partials <= kPrefetchPartials && blockDim.x >= 64) {
+  if (a.partials != nullptr && a.n_partials <= 64 * K && blockDim.x >= 64) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pv[k] = a.partials[min(lane + 64 * k, a.n_partials - 1)];
+    for (int k = 0; k < K; ++k) pv[k] = a.partials[min(lane + 64 * k, a.n_partials - 1)];
   } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pv[k] = 0.0;
+    for (int k = 0; k < K; ++k) pv[k] = 0.0;
   }
 }
 
-template <class A>
-__device__ __forceinline__ decltype(A::scale) row_scale(const A& a, const double (&pv)[4]) {
+template <class A, int K>
+__device__ __forceinline__ decltype(A::scale) row_scale(const A& a, const double (&pv)[K]) {
   if (a.partials == nullptr) return a.scale;
   double s = 0.0;
   if (blockDim.x >= 64) {
-    if (a.n_partials <= kPrefetchPartials) {
+    if (a.n_partials <= 64 * K) {
       const int lane = threadIdx.x & 63;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s += (lane + 64 * k < a.n_partials) ? pv[k] : 0.0;
+      for (int k = 0; k < K; ++k) s += (lane + 64 * k < a.n_partials) ? pv[k] : 0.0;
     } else {
       const int lane = threadIdx.x & 63;
       for (int i = lane; i < a.n_partials; i += 64) s += a.partials[i];
@@ -280,7 +283,7 @@ __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
   const uint32_t lane_off = static_cast<uint32_t>(t) * PB + CB * comp;
   const uint32_t group_stride = static_cast<uint32_t>(a.rows_per_block) * (PB * N);
 
-  double pv[4];
+  double pv[prefetch_per_lane<R, N>()];
   if constexpr (MODE != ROW_FWD) prefetch_partials(a, pv);
   C v[P], nxt[P];
   uint32_t off = static_cast<uint32_t>(row0) * (PB * N) + lane_off;
@@ -359,7 +362,7 @@ __device__ __forceinline__ void row_var_body(const RowArgs& a, int wg) {
   const uint32_t off = static_cast<uint32_t>(row) * (16u * N) + static_cast<uint32_t>(t) * 16u + 8u * comp;
   const int flags = a.var_flags;
 
-  double pv[4];
+  double pv[prefetch_per_lane<float, N>()];
   prefetch_partials(a, pv);
   float2 v[P];
 #pragma unroll
