@@ -42,8 +42,8 @@ struct sgpe_ctx {
   int row_points = 16;      // points per lane of the x transforms
   int col_points = 16;      // points per lane of the y transforms
   int n_cu = 1;             // compute units of the device
-  // complex128 contexts (prec == SGPE_C128): the state and the step tables in fp64; psi, the fp32
-  // tables and the schedule fields above are then unused (16 points per lane, no prefetch)
+  // complex128 contexts (prec == SGPE_C128): the state and the step tables in fp64; psi and the
+  // fp32 tables are then unused (the schedule fields above apply, with no prefetch)
   int prec = 0;             // sgpe_precision
   double4* psi64 = nullptr;
   double4* twp64_x = nullptr;
