@@ -413,6 +413,36 @@ def spin_hall_trial(torch):
     return res
 
 
+def roofline_references(torch, n, steady_step_ms, dominant_gbps):
+    """Measured references for the roofline on this device: a plain device copy of 256 MiB (torch
+    copy_, the best of five), and the arithmetic-free copy with a step's data movement at n x n
+    (sgpe_probe_exchange: the row partition, then the column partition, plain stores, 4-column
+    tiles; mean of 50 rounds)."""
+    from paper_2010_15069_amd import probe_exchange
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    best = None
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    copy_gbps = 2 * a.numel() * 4 / (best * 1e-3) / 1e9
+    del a, b
+    _, _, round_ms = probe_exchange(n, n, 1, 1, 4, write_through=False, wave_local=False, reps=50)
+    return {"plain_copy_GBps": copy_gbps,
+            "dominant_pass_frac_of_plain_copy": dominant_gbps / copy_gbps,
+            "exchange_copy_step_us": 1e3 * round_ms,
+            "exchange_copy_frac_of_peak": BYTES_PER_POINT_STEP * n * n / (round_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            "steady_step_over_exchange_copy": steady_step_ms / round_ms,
+            "method": "plain copy: torch copy_ of 256 MiB, best of 6 (read + written bytes); exchange copy: "
+                      "sgpe_probe_exchange at the headline size, 64 B per point per round"}
+
+
 def exchange_floor():
     """The arithmetic-free copy with the two passes' data movement, per layout and tile: mean
     microseconds per launch of each partition (events between launches), per row + column round
@@ -597,6 +627,7 @@ def main():
                      "launch_ms": dom_ms},
     }
     s.close()
+    out["roofline_references"] = roofline_references(torch, p.nx, steady_ms, achieved)
     progress("real-time 1024^2 and per-pass timing")
     if not args.no_other_grids:
         out["other_grids"] = other_grids(torch, stream, timed, p)
