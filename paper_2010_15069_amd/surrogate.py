@@ -79,7 +79,11 @@ def spectral_mix(a: torch.Tensor, wmat: torch.Tensor, bf16: bool) -> torch.Tenso
     ar = torch.cat([a.real, a.imag], dim=-1).to(torch.bfloat16).contiguous()
     wr = torch.cat([torch.cat([wmat.real, wmat.imag], dim=-1),
                     torch.cat([-wmat.imag, wmat.real], dim=-1)], dim=1).to(torch.bfloat16).contiguous()
-    if ar.device.type == "cuda":
+    if ar.device.type == "cuda" and torch.is_grad_enabled() and (ar.requires_grad or wr.requires_grad):
+        # training: the same bf16-rounded operands in an fp32 product, a differentiable stand-in for
+        # the fp32-accumulating bf16 product (equal to it up to the order of summation)
+        pr = torch.bmm(ar.float(), wr.float())
+    elif ar.device.type == "cuda":
         pr = torch.bmm(ar, wr, out_dtype=torch.float32)   # fp32 result of the fp32 accumulation
     else:
         pr = torch.bmm(ar, wr).float()                    # the host's bf16 product rounds its result
