@@ -51,15 +51,39 @@ def encode(params_list, device) -> torch.Tensor:
     return torch.from_numpy(np.stack(maps)).to(device)
 
 
+def encode_on(params_list, device) -> torch.Tensor:
+    """`encode` computed with torch on `device` (fp64 there, one rounding to fp32 at the end), so a
+    prediction on the GPU starts without a host round trip.  The Thomas-Fermi amplitudes scaled to
+    unit maximum do not depend on the state's normalisation: sqrt((mu - V)_+ / g_s) over its maximum.
+    Parameter sets with a non-positive coupling sum fall back to `encode`."""
+    if any(p.g_uu + p.g_ud <= 0.0 or p.g_dd + p.g_ud <= 0.0 for p in params_list):
+        return encode(params_list, device)
+    maps = []
+    for p in params_list:
+        x, y, _, _ = grid_axes(p)
+        X = torch.as_tensor(x, dtype=torch.float64, device=device).expand(p.ny, p.nx)
+        Y = torch.as_tensor(y, dtype=torch.float64, device=device)[:, None].expand(p.ny, p.nx)
+        V = 0.5 * (p.wx ** 2 * X * X + p.wy ** 2 * Y * Y)
+        gu, gd = p.g_uu + p.g_ud, p.g_dd + p.g_ud
+        mu = math.sqrt(p.norm0 * p.wx * p.wy * gu / (2.0 * math.pi))
+        n = torch.clamp(mu - V, min=0.0)
+        amp = torch.stack([torch.sqrt(n / gu), torch.sqrt(n / gd)])
+        amp = amp / torch.clamp(amp.max(), min=1e-30)
+        ones = torch.ones_like(X)
+        maps.append(torch.stack([V / V.max(), ones * (p.g_uu / 100.0), ones * (p.omega / 3.0),
+                                 ones * (p.delta / 0.5), X / p.xmax, Y / p.ymax, amp[0], amp[1]]))
+    return torch.stack(maps).to(torch.float32)
+
+
 def to_psi(out: torch.Tensor, params_list) -> list:
     """Network output (B, 4, ny, nx) -> list of (2, ny, nx) complex128 states normalised to norm0."""
-    o = out.detach().float().cpu().numpy().astype(np.float64)
+    o = out.detach().to(torch.float64)
+    psi = torch.complex(o[:, 0::2], o[:, 1::2])                       # (B, 2, ny, nx): up, down
     res = []
     for b, p in enumerate(params_list):
         _, _, dx, dy = grid_axes(p)
-        psi = np.stack([o[b, 0] + 1j * o[b, 1], o[b, 2] + 1j * o[b, 3]])
-        nrm = dx * dy * float(np.sum(np.abs(psi) ** 2))
-        res.append(psi * math.sqrt(p.norm0 / max(nrm, 1e-300)))
+        nrm = dx * dy * float((psi[b].real ** 2 + psi[b].imag ** 2).sum())
+        res.append((psi[b] * math.sqrt(p.norm0 / max(nrm, 1e-300))).cpu().numpy())
     return res
 
 
@@ -216,4 +240,4 @@ def load(path: str, device="cpu") -> FNO2d:
 def predict(model: FNO2d, params_list, device) -> list:
     """Initial states (complex128, normalised) for a list of same-grid parameter sets."""
     with torch.no_grad():
-        return to_psi(model(encode(params_list, device)), params_list)
+        return to_psi(model(encode_on(params_list, device)), params_list)

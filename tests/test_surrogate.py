@@ -90,3 +90,17 @@ def test_bf16_spectral_mix_is_the_complex_product():
     rel16 = float((spectral_mix(a16, w16, bf16=True) - spectral_mix(a16, w16, bf16=False)).abs().max()
                   / ref.abs().max())
     assert rel16 < 4e-3, rel16
+
+
+def test_encoding_on_the_device_matches_the_host_encoding():
+    # encode_on (torch, any device) and encode (numpy) give the same input maps; a set with a
+    # non-positive coupling sum takes the host path
+    from paper_2010_15069_amd import surrogate
+    from workloads import Params, preset, sweep_instances
+    ps = sweep_instances(seed=4, sizes=(256,), per_size=3) + [preset("ground_256")]
+    a = surrogate.encode(ps, "cpu")
+    b = surrogate.encode_on(ps, "cpu")
+    assert a.dtype == b.dtype == torch.float32 and a.shape == b.shape
+    assert float((a - b).abs().max()) <= 1e-6 * float(a.abs().max())
+    odd = [Params(nx=64, ny=64, g_uu=-1.0, g_dd=1.0, g_ud=0.5)]
+    assert torch.equal(surrogate.encode_on(odd, "cpu"), surrogate.encode(odd, "cpu"))
