@@ -276,7 +276,30 @@ def ground_2048_convergence(torch, stream, every=10, tol=1e-9, max_steps=150000)
                         "k_L = 2, wx = 1, wy = 1.5, imaginary-time dt = 1e-3, Thomas-Fermi start",
             "stop_rule": f"|E_n - E_(n-{every})| < {tol:g} |E_n|, checked every {every} steps (checks timed)",
             "converged": converged, "steps": steps, "seconds": el, "energy": e_fin,
-            "steps_to_1e-6_of_final": hit[0], "seconds_to_1e-6_of_final": hit[1]}
+            "steps_to_1e-6_of_final": hit[0], "seconds_to_1e-6_of_final": hit[1],
+            "fixed_point_estimate": _aitken_estimate(trace)}
+
+
+def _aitken_estimate(trace, spacing=5000):
+    """Distance of the last energy from the imaginary-time fixed point, estimated from the energy
+    trace alone: with E_n - E_inf ~ A r^n (one slowest mode), Aitken's delta-squared over three checks
+    `spacing` steps apart gives E_inf.  Reported for the last triple, with the first step whose
+    estimated distance was below 1e-6 |E| (None if none)."""
+    by_step = {st: e for st, _, e in trace}
+    marks = [st for st in sorted(by_step) if st % spacing == 0]
+    first, last = None, None
+    for i in range(2, len(marks)):
+        e0, e1, e2 = by_step[marks[i - 2]], by_step[marks[i - 1]], by_step[marks[i]]
+        d1, d2 = e1 - e0, e2 - e1
+        if d2 == d1 or d1 == 0.0:
+            continue
+        e_inf = e2 - d2 * d2 / (d2 - d1)
+        dist = abs(e2 - e_inf) / abs(e_inf)
+        last = {"steps": marks[i], "energy_inf": e_inf, "distance_rel": dist, "ratio_per_spacing": d2 / d1}
+        if first is None and dist < 1e-6:
+            first = marks[i]
+    return {"method": f"Aitken delta^2 over energies {spacing} steps apart", "last": last,
+            "steps_to_estimated_1e-6": first}
 
 
 def ground_state_learned(torch, stream, model, check_every=50, max_steps=200000):
