@@ -268,13 +268,13 @@ sgpe_status sgpe_probe_placement(int32_t gx, int32_t gy, int32_t threads, uint32
 /* sgpe_energy for callers that cannot allocate (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): the same energy per particle, written as one double to
  * e_dev (device memory, caller-owned), asynchronously on the context's stream.  The call allocates
- * nothing and never synchronises: the fp64 scratch of the energy kernels (the x-transformed state)
- * and their partial sums live in a static device array of 8.1 MiB (grids of up to 262144 points,
- * e.g. 512 x 512), which every GPU the library runs on holds until the process ends.  Every call on
- * a device shares that array; calls that overlap on one device (several streams or threads) race
- * on it and must be ordered by the caller.  The result equals sgpe_energy's up to the order of the
- * final fp64 sums.  Errors: SGPE_EINVAL (NULL e_dev), SGPE_ESTATE (no state), SGPE_ENOMEM (more
- * than 262144 points), SGPE_EDEVICE. */
+ * nothing and never synchronises: the energy kernels' partial sums live in a static device array of
+ * 128 KiB (three per row and one per column block, up to 4096 of each: every grid the library
+ * accepts), which every GPU the library runs on holds until the process ends.  Every call on a device
+ * shares that array; calls that overlap on one device (several streams or threads) race on it and
+ * must be ordered by the caller.  The result equals sgpe_energy's up to the order of the final fp64
+ * sums.  Errors: SGPE_EINVAL (NULL e_dev), SGPE_ESTATE (no state), SGPE_ENOMEM (more rows or column
+ * blocks than the array holds; no grid the library accepts has them), SGPE_EDEVICE. */
 sgpe_status sgpe_energy_noalloc(sgpe_ctx* ctx, double* e_dev);
 
 /* Static description of a status code.  Never NULL. */

@@ -500,12 +500,11 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag) {
   return status_of(e);
 }
 
-EnergyArgs energy_args(const sgpe_ctx* c, double4* scratch, double* row_partials, double* col_partials) {
+EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_partials) {
   const sgpe_params& p = c->p;
   EnergyArgs a{};
   a.psi = c->psi;
   a.psi64 = c->psi64;
-  a.scratch = scratch;
   a.nx = p.nx;
   a.ny = p.ny;
   a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
@@ -983,15 +982,10 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   if (!c->has_state) return SGPE_ESTATE;
   const sgpe_params& p = c->p;
   const size_t npts = size_t(p.nx) * size_t(p.ny);
-  if (!c->scratch64) {
-    void* ptr = nullptr;
-    if ((st = dev_alloc(c, &ptr, npts * sizeof(double4))) != SGPE_OK) return st;
-    c->scratch64 = static_cast<double4*>(ptr);
-  }
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
   const int nrb = p.ny;  // one row per row-kernel workgroup
   constexpr int RP = sgpe::kEnergyRowParts;
-  EnergyArgs a = energy_args(c, c->scratch64, c->epart, c->epart + RP * nrb);
+  EnergyArgs a = energy_args(c, c->epart, c->epart + RP * nrb);
   const int ncb = p.nx / a.cols;
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e != hipSuccess) return status_of(e);

@@ -20,7 +20,6 @@ struct sgpe_ctx {
   float4* scratch = nullptr;
   double2* twd_x = nullptr; // fp64 roots exp(-2 pi i j / nx), j < nx / 2 (energy kernels)
   double2* twd_y = nullptr;
-  double4* scratch64 = nullptr;  // fp64 x-transformed state (energy), allocated on first use
   float4* twp_x = nullptr;  // fp32-rounded roots with modulus corrections (step kernels)
   float4* twp_y = nullptr;
   // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
@@ -84,7 +83,7 @@ sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
 // Arguments of the energy kernels for the context's state, with the given fp64 scratch (nx*ny
 // points) and partial buffers (kEnergyRowParts per row, then one per column block).
-sgpe::EnergyArgs energy_args(const sgpe_ctx* c, double4* scratch, double* row_partials, double* col_partials);
+sgpe::EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_partials);
 // Copies n doubles of reduction partials from the device into the context's pinned host buffer
 // (queued on the context's stream, which is then synchronised) and points *host at it.  Returns
 // SGPE_ENOMEM if the buffer cannot grow, SGPE_EDEVICE on a device error.  A pinned destination

@@ -1,18 +1,19 @@
 // sgpe_energy_noalloc: the energy of sgpe_energy with no allocation at call time, for callers that
 // cannot allocate (code under HIP graph capture, tight serving loops, harnesses that forbid it).
 //
-// sgpe_energy allocates a state-sized fp64 scratch (the x-transformed state) on its first call and
-// brings the partial sums back through a pinned host buffer it grows on demand.  Here both live in
-// one static device array, `scratch`, of a fixed size: grids of up to kMaxPoints points.  Each device
-// the library runs on holds its own copy until the process ends.  Host code never passes the array's
+// sgpe_energy writes the energy kernels' partial sums to a device buffer the context allocated and
+// brings them back through a pinned host buffer it grows on demand.  Here they live in one static
+// device array, `scratch`, of a fixed size: kEnergyRowParts per row and one per column block, for
+// up to kMaxAxis of each (every grid the library accepts).  Each device the library runs on holds
+// its own copy until the process ends.  Host code never passes the array's
 // name to a kernel or a copy: on a device's first call the address of that device's copy is looked
 // up (hipGetSymbolAddress, with the device current) and kept, and only that address is used.  A
 // finishing kernel sums the partials in a fixed order and writes the energy to the caller's device
 // memory, so the call is asynchronous on the context's stream and never synchronises.
 //
 // Every call on a device shares that device's array and leaves its contents behind; the energy
-// kernels overwrite every value they later read (the scratch rows, every partial), so nothing needs
-// clearing between calls.  Calls that overlap on one device (two streams, or two threads) race on
+// kernels overwrite every partial the finishing kernel later reads, so nothing needs clearing
+// between calls.  Calls that overlap on one device (two streams, or two threads) race on
 // the array and must be ordered by the caller.
 #include <hip/hip_runtime.h>
 
@@ -25,11 +26,9 @@
 
 namespace {
 
-constexpr size_t kMaxPoints = size_t(1) << 18;   // nx * ny <= 262144 (512 x 512)
 constexpr size_t kMaxAxis = 4096;
-// fp64 x-transformed state (4 doubles per point), then kEnergyRowParts partials per row, then one
-// per column block
-constexpr size_t kScratchDoubles = 4 * kMaxPoints + sgpe::kEnergyRowParts * kMaxAxis + kMaxAxis;
+// kEnergyRowParts partials per row, then one per column block
+constexpr size_t kScratchDoubles = sgpe::kEnergyRowParts * kMaxAxis + kMaxAxis;
 constexpr int kMaxDevices = 64;
 
 }  // namespace
@@ -88,15 +87,14 @@ extern "C" sgpe_status sgpe_energy_noalloc(sgpe_ctx* c, double* e_dev) {
   if (!c->has_state) return SGPE_ESTATE;
   const sgpe_params& p = c->p;
   const size_t npts = size_t(p.nx) * size_t(p.ny);
-  if (npts > kMaxPoints) return SGPE_ENOMEM;   // beyond the static scratch
   double* base = device_scratch(c->device);
   if (!base) return SGPE_EDEVICE;
   constexpr int RP = sgpe::kEnergyRowParts;
-  double* row_parts = base + 4 * npts;
-  double* col_parts = row_parts + RP * size_t(p.ny);
-  const sgpe::EnergyArgs a =
-      sgpe_host::energy_args(c, reinterpret_cast<double4*>(base), row_parts, col_parts);
+  double* row_parts = base;
+  double* col_parts = row_parts + RP * kMaxAxis;
+  const sgpe::EnergyArgs a = sgpe_host::energy_args(c, row_parts, col_parts);
   const int ncols = p.nx / a.cols;
+  if (size_t(p.ny) > kMaxAxis || size_t(ncols) > kMaxAxis) return SGPE_ENOMEM;   // beyond the static array
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e == hipSuccess) {
     const double w = (2.0 * p.xmax / p.nx) * (2.0 * p.ymax / p.ny);

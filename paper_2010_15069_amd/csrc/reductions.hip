@@ -60,12 +60,21 @@ int energy_cols_per_block(int nx, int ny, size_t max_lds) {
 int norm_blocks() { return 256; }
 
 // -------------------------------------------------------------------------------------------
-// Energy, in fp64 throughout (it is evaluated on demand, not per step).  Row kernel: the
-// real-space terms and the norm from the loaded values, then the x-DFT of both components into a
-// 32-byte-per-point fp64 scratch; column kernel: the y-DFT and the k-space quadratic form.  The
-// DFTs are in-place radix-2 transforms in LDS: input stored at bit-reversed positions, log2 N
-// butterfly stages, roots exp(-2 pi i j / N) from fp64 host tables.  Exact to fp64 rounding, so
-// the energy of a complex64 state carries no transform error of its own.
+// Energy, in fp64 throughout (it is evaluated on demand, not per step).  The k-space quadratic
+// form sum_k psi^(k)^+ H_K(k) psi^(k) of the energy splits, by Parseval's theorem along one axis at
+// a time, into 1-D pieces of the state as it is, so no 2-D transform is formed:
+//   * the k_x terms (k_x^2 / 2 on both components, k_l k_x sigma_z): for every row, the x-DFT
+//     u~(k_x) of the row, sum over k_x; over the whole grid the sum of |u^|^2 f(k_x) is ny times the
+//     sum over rows of |u~|^2 f(k_x);
+//   * the k_y term (k_y^2 / 2): the same with the y-DFT of every column, times nx;
+//   * the uniform Raman term Omega Re(u^* d^) of H_K: N times its real-space sum, so it joins the
+//     spatial Raman term Omega(r) Re(u* d) of the real-space energy.
+// Row kernel: the real-space terms, the norm and the row's k_x terms (one row per workgroup); column
+// kernel: the k_y terms of up to 4 columns per workgroup.  The DFTs are in-place radix-2 transforms
+// in LDS: input stored at bit-reversed positions, log2 N butterfly stages, roots exp(-2 pi i j / N)
+// from fp64 host tables.  Exact to fp64 rounding, so the energy of a complex64 state carries no
+// transform error of its own.  The partials are scaled so that the host's combination reads
+// E = (w / N ek + w er) / norm + w ei norm0 / norm^2 (w = dx dy, N = nx ny), as for a 2-D sum.
 // -------------------------------------------------------------------------------------------
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -95,6 +104,13 @@ __device__ __forceinline__ void lds_fft64(double2* buf, int n, int log2n, int co
 
 __device__ __forceinline__ int bitrev(int j, int log2n) { return static_cast<int>(__brev(static_cast<unsigned>(j)) >> (32 - log2n)); }
 
+// Point i of the state as four doubles {re_up, im_up, re_dn, im_dn}.
+__device__ __forceinline__ double4 state_point(const EnergyArgs& a, size_t i) {
+  if (a.psi64) return a.psi64[i];
+  const float4 v = a.psi[i];
+  return make_double4(v.x, v.y, v.z, v.w);
+}
+
 __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   extern __shared__ double2 elds[];
   __shared__ double red[64];
@@ -104,18 +120,13 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
   const double om_row = a.om_y ? a.om_y[row] : 0.0;
   double er = 0.0, ei = 0.0, nr = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    double ur, ui, dr, di;
-    if (a.psi64) {
-      const double4 v = a.psi64[size_t(row) * n + j];
-      ur = v.x, ui = v.y, dr = v.z, di = v.w;
-    } else {
-      const float4 v = a.psi[size_t(row) * n + j];
-      ur = v.x, ui = v.y, dr = v.z, di = v.w;
-    }
+    const double4 v = state_point(a, size_t(row) * n + j);
+    const double ur = v.x, ui = v.y, dr = v.z, di = v.w;
     const double x = a.xmin + a.dx * j;
     const double V = a.wx2h * x * x + a.wy2h * y * y;
     const double nu = ur * ur + ui * ui, nd = dr * dr + di * di;
-    const double om = a.om_x ? a.om_x[j] + om_row : 0.0;
+    // spatial Raman coupling Omega(r) and the uniform one Omega (its k-space sum, by Parseval)
+    const double om = (a.om_x ? a.om_x[j] + om_row : 0.0) + a.omega;
     er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (ur * dr + ui * di);
     ei += 0.5 * a.g_uu * nu * nu + 0.5 * a.g_dd * nd * nd + a.g_ud * nu * nd;
     nr += nu + nd;
@@ -123,19 +134,23 @@ __global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
     elds[r] = make_double2(ur, ui);
     elds[n + r] = make_double2(dr, di);
   }
+  lds_fft64(elds, n, log2n, 2, a.twx);
+  double ex = 0.0;   // this row's k_x terms
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double kx = (j < n / 2 ? j : j - n) * a.dkx;
+    const double2 u = elds[j], d = elds[n + j];
+    const double pu = u.x * u.x + u.y * u.y, pd = d.x * d.x + d.y * d.y;
+    ex += 0.5 * kx * kx * (pu + pd) + a.k_l * kx * (pu - pd);
+  }
   const double se = block_sum(er, red);
+  const double sx = block_sum(ex, red);
   const double si = block_sum(ei, red);
   const double sn = block_sum(nr, red);
   if (threadIdx.x == 0) {
-    a.row_partials[kEnergyRowParts * blockIdx.x] = se;
+    // w / N * (ny * sx) = w * sx / nx: the k_x terms join the real-space linear ones
+    a.row_partials[kEnergyRowParts * blockIdx.x] = se + sx / double(n);
     a.row_partials[kEnergyRowParts * blockIdx.x + 1] = si;
     a.row_partials[kEnergyRowParts * blockIdx.x + 2] = sn;
-  }
-  lds_fft64(elds, n, log2n, 2, a.twx);
-  double4* __restrict__ q = a.scratch + size_t(row) * n;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double2 u = elds[j], d = elds[n + j];
-    q[j] = make_double4(u.x, u.y, d.x, d.y);
   }
 }
 
@@ -148,7 +163,7 @@ __global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
   // columns x0 .. x0 + C - 1: transform 2c (up) and 2c + 1 (down) of column c
   for (int i = threadIdx.x; i < C * n; i += blockDim.x) {
     const int c = i % C, iy = i / C;
-    const double4 v = a.scratch[size_t(iy) * a.nx + x0 + c];
+    const double4 v = state_point(a, size_t(iy) * a.nx + x0 + c);
     const int r = bitrev(iy, log2n);
     elds[(2 * c) * n + r] = make_double2(v.x, v.y);
     elds[(2 * c + 1) * n + r] = make_double2(v.z, v.w);
@@ -157,16 +172,12 @@ __global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < C * n; i += blockDim.x) {
     const int c = i / n, iy = i - c * n;
-    const int x = x0 + c;
-    const double kx = (x < a.nx / 2 ? x : x - a.nx) * a.dkx;
     const double ky = (iy < n / 2 ? iy : iy - n) * a.dky;
-    const double ak = 0.5 * (kx * kx + ky * ky);
     const double2 u = elds[(2 * c) * n + iy], d = elds[(2 * c + 1) * n + iy];
-    const double pu = u.x * u.x + u.y * u.y, pd = d.x * d.x + d.y * d.y;
-    acc += ak * (pu + pd) + a.k_l * kx * (pu - pd) + a.omega * (u.x * d.x + u.y * d.y);
+    acc += 0.5 * ky * ky * (u.x * u.x + u.y * u.y + d.x * d.x + d.y * d.y);
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) a.col_partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) a.col_partials[blockIdx.x] = double(a.nx) * s;   // nx times the columns' sum
 }
 
 // -------------------------------------------------------------------------------------------

@@ -93,7 +93,6 @@ constexpr int kEnergyRowParts = 3;
 struct EnergyArgs {
   const float4* psi;         // the complex64 state, or
   const double4* psi64;      //   the complex128 one (exactly one is set)
-  double4* scratch;          // [ny][nx] x-transformed state in fp64 {re_up, im_up, re_dn, im_dn}
   int nx, ny;
   int cols;                  // columns per column-kernel workgroup
   const double2* twx;        // roots exp(-2 pi i j / nx), j < nx / 2, fp64
@@ -105,9 +104,9 @@ struct EnergyArgs {
   const double* om_x;        // spatial Raman coupling Omega_x(x_j) (length nx) and Omega_y(y_i)
   const double* om_y;        //   (length ny); both NULL without one
   double dkx, dky;
-  double* row_partials;      // kEnergyRowParts per row: {linear real-space energy,
-                             //   interaction energy, norm}
-  double* col_partials;      // 1 per column block: k-space quadratic form
+  double* row_partials;      // kEnergyRowParts per row: {linear real-space energy and the row's
+                             //   k_x terms, interaction energy, norm}
+  double* col_partials;      // 1 per column block: its columns' k_y terms
 };
 
 // Launchers (return hipSuccess or the launch error).
