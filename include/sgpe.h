@@ -154,6 +154,41 @@ sgpe_status sgpe_norm(sgpe_ctx* ctx, double* norm);
  * Sec. 3.2 could not be applied). */
 sgpe_status sgpe_synchronize(sgpe_ctx* ctx);
 
+/* Stopping rules and result of sgpe_relax_imag (below). */
+typedef enum { SGPE_RELAX_TARGET = 0, SGPE_RELAX_DELTA = 1 } sgpe_relax_rule;
+
+typedef struct sgpe_relax_result {
+  int64_t steps;        /* steps at the last check read: the one that met the rule, else the last */
+  int64_t steps_taken;  /* steps applied to the state when the call returns */
+  int64_t checks;       /* checks read, check 0 included */
+  double energy;        /* energy per particle at the last check read */
+  double energy_prev;   /* at the check before it (NaN for check 0) */
+  int32_t met;          /* 1 if the rule was met */
+  int32_t reserved;     /* 0 */
+} sgpe_relax_result;
+
+/* Ground state by imaginary-time propagation (Sec. 3.2: imaginary time approaches the ground state
+ * asymptotically, the norm restored after every step; Sec. 6 finds its ground states this way),
+ * run until an energy rule is met.  The paper fixes no stopping rule; these are the library's:
+ *   SGPE_RELAX_TARGET: stop at the first check with |E - target| <= tol |target|;
+ *   SGPE_RELAX_DELTA:  stop at the first check with |E_k - E_(k-1)| < tol |E_k| (target unused).
+ * Check 0 is the energy of the state as it is; check k > 0 follows min(k check_every, max_steps)
+ * steps of the context's scheme (as sgpe_step_imag), so max_steps caps the steps.  Each check's
+ * energy is that of sgpe_energy (same kernels, the partials combined on the device: equal up to
+ * the order of the final fp64 sums).  The host reads check k while up to two further chunks of
+ * check_every steps are already queued, so the device never waits for the host between chunks; when
+ * check k meets the rule those chunks still run, and the state the call leaves has
+ * out->steps_taken >= out->steps steps (at most 2 check_every more).  energies (host, may be NULL
+ * with energies_cap = 0) receives the energy of check k at index k for k < energies_cap.
+ * Synchronises before returning.  The ring of checks in flight (4 device doubles, their pinned host
+ * copies and 4 events) is allocated on the first call and kept by the context.
+ * Errors: SGPE_EINVAL (NULL out, check_every < 1, max_steps < 0, tol negative or not finite, an
+ * unknown rule, a non-finite target with SGPE_RELAX_TARGET, energies NULL with energies_cap > 0,
+ * energies_cap < 0), SGPE_ESTATE (no state), SGPE_ENOMEM, SGPE_EDEVICE, SGPE_ENONFINITE (a check's
+ * energy, or an imaginary-time norm, not finite: the call stops there and out holds that check). */
+sgpe_status sgpe_relax_imag(sgpe_ctx* ctx, int64_t check_every, int64_t max_steps, int32_t rule, double target,
+                            double tol, double* energies, int64_t energies_cap, sgpe_relax_result* out);
+
 /* Measurement helper: run n real-time (imag = 0) or imaginary-time (imag = 1) steady-state
  * steps with a HIP event pair around every kernel launch, and return the mean duration in
  * milliseconds of the row pass (x transforms + real-space exponential) and of the column pass

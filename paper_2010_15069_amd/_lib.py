@@ -42,6 +42,16 @@ class Schedule(ctypes.Structure):
                 ("col_points", ctypes.c_int32), ("row_tile", ctypes.c_int32)]
 
 
+class RelaxResult(ctypes.Structure):
+    """sgpe_relax_result: where sgpe_relax_imag stopped (see include/sgpe.h)."""
+    _fields_ = [("steps", ctypes.c_int64), ("steps_taken", ctypes.c_int64), ("checks", ctypes.c_int64),
+                ("energy", ctypes.c_double), ("energy_prev", ctypes.c_double), ("met", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+RELAX_RULES = {"target": 0, "delta": 1}
+
+
 class SgpeError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = int(status)
@@ -63,7 +73,7 @@ EXPORTS = [
     "sgpe_batch_set_schedule", "sgpe_batch_autotune", "sgpe_batch_use_persistent",
     "sgpe_set_raman_profile", "sgpe_add_noise", "sgpe_phase_separation", "sgpe_population_radius",
     "sgpe_winding", "sgpe_set_splitting", "sgpe_create_ex", "sgpe_probe_exchange", "sgpe_energy_noalloc",
-    "sgpe_probe_placement",
+    "sgpe_probe_placement", "sgpe_relax_imag",
 ]
 
 
@@ -160,6 +170,8 @@ def _lib():
                                  P(ctypes.c_double)], st),
         "sgpe_energy_noalloc": ([vp, vp], st),
         "sgpe_probe_placement": ([i32, i32, i32, P(ctypes.c_uint32)], st),
+        "sgpe_relax_imag": ([vp, ctypes.c_int64, ctypes.c_int64, i32, ctypes.c_double, ctypes.c_double,
+                             P(ctypes.c_double), ctypes.c_int64, P(RelaxResult)], st),
     })
     for name, (args, res) in batch_sigs.items():
         f = getattr(lib, name)

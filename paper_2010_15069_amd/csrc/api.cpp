@@ -811,6 +811,9 @@ void sgpe_destroy(sgpe_ctx* c) {
   for (void* ptr : c->allocations) (void)hipFree(ptr);
   if (c->host_part) (void)hipHostFree(c->host_part);
   if (c->status_host) (void)hipHostFree(c->status_host);
+  if (c->relax_host) (void)hipHostFree(c->relax_host);
+  for (hipEvent_t ev : c->relax_ev)
+    if (ev) (void)hipEventDestroy(ev);
   (void)hipGetLastError();
   delete c;
 }

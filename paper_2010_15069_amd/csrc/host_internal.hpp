@@ -64,6 +64,11 @@ struct sgpe_ctx {
   std::vector<void*> allocations;
   double* host_part = nullptr;   // pinned host copy of reduction partials, grown on demand
   size_t host_part_n = 0;
+  // sgpe_relax_imag's ring of energy checks in flight (allocated on its first call): the energies
+  // on the device, their pinned host copies, and an event after each copy
+  double* relax_dev = nullptr;
+  double* relax_host = nullptr;
+  hipEvent_t relax_ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace sgpe_host {
@@ -93,6 +98,9 @@ sgpe_status fetch_partials(sgpe_ctx* c, const double* dev, size_t n, const doubl
 // use; waits for the stream's queued work before overwriting them.
 sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y);
 sgpe_status sync_and_latch(sgpe_ctx* c);
+// Enqueue n >= 0 steps of the context's scheme (imaginary time if imag) on its stream; with ev, a
+// HIP event pair around every pass (the default scheme in complex64 only).
+sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev);
 // The context's latched status after the stream has been synchronised: folds in the status word
 // the step kernels set on a non-finite norm.
 sgpe_status latched_status(sgpe_ctx* c);

@@ -7,9 +7,10 @@
 // up to kMaxAxis of each (every grid the library accepts).  Each device the library runs on holds
 // its own copy until the process ends.  Host code never passes the array's
 // name to a kernel or a copy: on a device's first call the address of that device's copy is looked
-// up (hipGetSymbolAddress, with the device current) and kept, and only that address is used.  A
-// finishing kernel sums the partials in a fixed order and writes the energy to the caller's device
-// memory, so the call is asynchronous on the context's stream and never synchronises.
+// up (hipGetSymbolAddress, with the device current) and kept, and only that address is used.  The
+// finishing kernel of the energy (launch_energy_finish) sums the partials in a fixed order and
+// writes the energy to the caller's device memory, so the call is asynchronous on the context's
+// stream and never synchronises.
 //
 // Every call on a device shares that device's array and leaves its contents behind; the energy
 // kernels overwrite every partial the finishing kernel later reads, so nothing needs clearing
@@ -37,29 +38,6 @@ static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
-// One wave: sums each kind of partial in a fixed order (lane-strided, then a fixed butterfly) and
-// evaluates the energy per particle exactly as sgpe_energy does on the host.
-__global__ void __launch_bounds__(64) energy_finish_kernel(const double* __restrict__ row_parts, int nrows,
-                                                           const double* __restrict__ col_parts, int ncols, double w,
-                                                           double inv_npts, double norm0, double* __restrict__ out) {
-  const int lane = threadIdx.x;
-  double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
-  for (int b = lane; b < nrows; b += 64) {
-    er += row_parts[sgpe::kEnergyRowParts * b];
-    ei += row_parts[sgpe::kEnergyRowParts * b + 1];
-    nr += row_parts[sgpe::kEnergyRowParts * b + 2];
-  }
-  for (int b = lane; b < ncols; b += 64) ek += col_parts[b];
-  er = sgpe::wave_sum(er);
-  ei = sgpe::wave_sum(ei);
-  nr = sgpe::wave_sum(nr);
-  ek = sgpe::wave_sum(ek);
-  if (lane == 0) {
-    const double nrm = w * nr;
-    out[0] = (w * inv_npts * ek + w * er) / nrm + w * ei * norm0 / (nrm * nrm);
-  }
-}
-
 std::mutex g_mu;
 double* g_scratch[kMaxDevices] = {};
 
@@ -86,7 +64,6 @@ extern "C" sgpe_status sgpe_energy_noalloc(sgpe_ctx* c, double* e_dev) {
   if (!e_dev) return SGPE_EINVAL;
   if (!c->has_state) return SGPE_ESTATE;
   const sgpe_params& p = c->p;
-  const size_t npts = size_t(p.nx) * size_t(p.ny);
   double* base = device_scratch(c->device);
   if (!base) return SGPE_EDEVICE;
   constexpr int RP = sgpe::kEnergyRowParts;
@@ -96,12 +73,7 @@ extern "C" sgpe_status sgpe_energy_noalloc(sgpe_ctx* c, double* e_dev) {
   const int ncols = p.nx / a.cols;
   if (size_t(p.ny) > kMaxAxis || size_t(ncols) > kMaxAxis) return SGPE_ENOMEM;   // beyond the static array
   hipError_t e = sgpe::launch_energy(a, c->stream);
-  if (e == hipSuccess) {
-    const double w = (2.0 * p.xmax / p.nx) * (2.0 * p.ymax / p.ny);
-    hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(64), 0, c->stream, row_parts, p.ny, col_parts, ncols, w,
-                       1.0 / double(npts), p.norm0, e_dev);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess) e = sgpe::launch_energy_finish(a, p.norm0, e_dev, c->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return sgpe_host::status_of(e);

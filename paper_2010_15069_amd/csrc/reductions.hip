@@ -197,6 +197,38 @@ __global__ void __launch_bounds__(256) norm_kernel(const Q* __restrict__ psi, lo
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// One wave combines the energy kernels' partials on the device: each kind summed in a fixed order
+// (lane-strided, then a fixed butterfly), then the energy per particle of the state rescaled to
+// norm0, E = (w / N ek + w er) / norm + w ei norm0 / norm^2 with norm = w nr.
+__global__ void __launch_bounds__(64) energy_finish_kernel(const double* __restrict__ row_parts, int nrows,
+                                                           const double* __restrict__ col_parts, int ncols, double w,
+                                                           double inv_npts, double norm0, double* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
+  for (int b = lane; b < nrows; b += 64) {
+    er += row_parts[kEnergyRowParts * b];
+    ei += row_parts[kEnergyRowParts * b + 1];
+    nr += row_parts[kEnergyRowParts * b + 2];
+  }
+  for (int b = lane; b < ncols; b += 64) ek += col_parts[b];
+  er = wave_sum(er);
+  ei = wave_sum(ei);
+  nr = wave_sum(nr);
+  ek = wave_sum(ek);
+  if (lane == 0) {
+    const double nrm = w * nr;
+    out[0] = (w * inv_npts * ek + w * er) / nrm + w * ei * norm0 / (nrm * nrm);
+  }
+}
+
+hipError_t launch_energy_finish(const EnergyArgs& a, double norm0, double* out, hipStream_t s) {
+  const double w = a.dx * a.dy;
+  const double inv_npts = 1.0 / (double(a.nx) * double(a.ny));
+  hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(64), 0, s, a.row_partials, a.ny, a.col_partials,
+                     a.nx / a.cols, w, inv_npts, norm0, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
   const size_t row_lds = size_t(2) * a.nx * sizeof(double2);
   const size_t col_lds = size_t(2) * a.cols * a.ny * sizeof(double2);

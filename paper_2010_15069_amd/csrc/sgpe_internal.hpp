@@ -139,6 +139,9 @@ hipError_t launch_row_batch(const RowArgs& shape, const RowArgs* tab, int count,
 hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count, int norm_mode, int points,
                             hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
+// The energy per particle from the partials launch_energy wrote (a's buffers), combined on the
+// device in a fixed order and written to out (one double, device memory).
+hipError_t launch_energy_finish(const EnergyArgs& a, double norm0, double* out, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 hipError_t launch_norm(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 

@@ -6,7 +6,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import Schedule, SgpeParams, check, lib
+from ._lib import RELAX_RULES, RelaxResult, Schedule, SgpeParams, check, lib
 
 
 class Solver:
@@ -78,6 +78,27 @@ class Solver:
 
     def synchronize(self):
         check(self._lib.sgpe_synchronize(self._ctx), "sgpe_synchronize")
+
+    def relax_imag(self, check_every=50, max_steps=200000, target=None, tol=1e-6, rule=None,
+                   record_energies=False) -> dict:
+        """Imaginary-time steps until an energy rule is met (sgpe_relax_imag): rule "target" (the
+        default when a target energy is given) stops at |E - target| <= tol |target|, rule "delta"
+        at |E_k - E_(k-1)| < tol |E_k|, the energy checked every `check_every` steps.  Returns the
+        result fields, and with record_energies the energy of every check read."""
+        rule = rule or ("target" if target is not None else "delta")
+        n_checks = 1 + (int(max_steps) + int(check_every) - 1) // int(check_every)
+        energies = np.full(n_checks, np.nan) if record_energies else None
+        res = RelaxResult()
+        ptr = energies.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if record_energies else None
+        check(self._lib.sgpe_relax_imag(self._ctx, int(check_every), int(max_steps), RELAX_RULES[rule],
+                                        float(target if target is not None else 0.0), float(tol), ptr,
+                                        n_checks if record_energies else 0, ctypes.byref(res)),
+              "sgpe_relax_imag")
+        out = {f: getattr(res, f) for f, _ in RelaxResult._fields_ if f != "reserved"}
+        out["met"] = bool(out["met"])
+        if record_energies:
+            out["energies"] = energies[:res.checks]
+        return out
 
     # -- observables -----------------------------------------------------------------------
     def energy(self) -> float:

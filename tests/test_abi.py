@@ -182,6 +182,9 @@ def test_new_entry_points_reject_null_and_invalid_arguments(lib):
         assert lib.sgpe_create_ex(ctypes.byref(p), prec, None, None, ctypes.byref(out)) == 1
         assert out.value is None
     assert lib.sgpe_create_ex(ctypes.byref(p), 1, None, None, None) == 1
+    from paper_2010_15069_amd._lib import RelaxResult
+    res = RelaxResult()
+    assert lib.sgpe_relax_imag(None, 50, 100, 0, -1.0, 1e-6, None, 0, ctypes.byref(res)) == 1
 
 
 def test_header_documents_precision_and_splitting_enums():
@@ -203,7 +206,8 @@ def _comment_before(decl_name):
 @pytest.mark.parametrize("name", ["sgpe_create", "sgpe_create_ex", "sgpe_set_psi", "sgpe_get_psi",
                                   "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
                                   "sgpe_synchronize", "sgpe_set_splitting", "sgpe_set_raman_profile",
-                                  "sgpe_add_noise", "sgpe_phase_separation", "sgpe_winding"])
+                                  "sgpe_add_noise", "sgpe_phase_separation", "sgpe_winding",
+                                  "sgpe_relax_imag"])
 def test_boundary_calls_cite_the_paper(name):
     # every call of the solver boundary names the passage that defines what it computes
     doc = _comment_before(name)
