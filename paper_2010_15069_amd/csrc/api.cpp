@@ -110,15 +110,6 @@ sgpe_status raman_tables(sgpe_ctx* c, const double* om_x, const double* om_y) {
 }
 
 // Forward roots exp(-2 pi i j / n), j < n / 2, in fp64 (energy kernels).
-std::vector<double2> twiddles64(int n) {
-  std::vector<double2> t(n / 2 > 0 ? n / 2 : 1);
-  for (int j = 0; j < n / 2; ++j) {
-    const double a = -2.0 * M_PI * double(j) / double(n);
-    t[j] = make_double2(std::cos(a), std::sin(a));
-  }
-  return t;
-}
-
 // Roots exp(-2 pi i j / n) rounded once to fp32 as {cos, sin, eta, 0}, where
 // 1 + eta = 1 / (cos^2 + sin^2) of the rounded pair (evaluated in fp64): the step kernels'
 // forward transform multiplies by the rounded root, their exact inverse by conj(root)(1 + eta),
@@ -507,9 +498,10 @@ EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_part
   a.psi64 = c->psi64;
   a.nx = p.nx;
   a.ny = p.ny;
+  a.rows = sgpe::energy_rows_per_block(p.nx, p.ny);
   a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
-  a.twx = c->twd_x;
-  a.twy = c->twd_y;
+  a.twx = c->twp64_x;
+  a.twy = c->twp64_y;
   a.xmin = -p.xmax;
   a.dx = 2.0 * p.xmax / p.nx;
   a.ymin = -p.ymax;
@@ -742,12 +734,9 @@ sgpe_status sgpe_create_ex(const sgpe_params* p, int32_t precision, void* hip_st
   }
   if (c128) c->psi64 = static_cast<double4*>(state);
   else c->psi = static_cast<float4*>(state);
-  if ((st = upload(c, &c->twd_x, twiddles64(p->nx))) != SGPE_OK) return fail(st);
-  if ((st = upload(c, &c->twd_y, twiddles64(p->ny))) != SGPE_OK) return fail(st);
-  if (c128) {
-    if ((st = upload(c, &c->twp64_x, twiddles_plain<double>(p->nx))) != SGPE_OK) return fail(st);
-    if ((st = upload(c, &c->twp64_y, twiddles_plain<double>(p->ny))) != SGPE_OK) return fail(st);
-  } else {
+  if ((st = upload(c, &c->twp64_x, twiddles_plain<double>(p->nx))) != SGPE_OK) return fail(st);
+  if ((st = upload(c, &c->twp64_y, twiddles_plain<double>(p->ny))) != SGPE_OK) return fail(st);
+  if (!c128) {
     if ((st = upload(c, &c->twp_x, twiddles_plain(p->nx))) != SGPE_OK) return fail(st);
     if ((st = upload(c, &c->twp_y, twiddles_plain(p->ny))) != SGPE_OK) return fail(st);
   }
@@ -986,7 +975,7 @@ sgpe_status sgpe_energy(sgpe_ctx* c, double* out) {
   const sgpe_params& p = c->p;
   const size_t npts = size_t(p.nx) * size_t(p.ny);
   const double dx = 2.0 * p.xmax / p.nx, dy = 2.0 * p.ymax / p.ny;
-  const int nrb = p.ny;  // one row per row-kernel workgroup
+  const int nrb = p.ny / sgpe::energy_rows_per_block(p.nx, p.ny);   // row blocks
   constexpr int RP = sgpe::kEnergyRowParts;
   EnergyArgs a = energy_args(c, c->epart, c->epart + RP * nrb);
   const int ncb = p.nx / a.cols;

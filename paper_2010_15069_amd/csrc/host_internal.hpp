@@ -18,8 +18,6 @@ struct sgpe_ctx {
   float4* psi = nullptr;
   bool own_psi = false;
   float4* scratch = nullptr;
-  double2* twd_x = nullptr; // fp64 roots exp(-2 pi i j / nx), j < nx / 2 (energy kernels)
-  double2* twd_y = nullptr;
   float4* twp_x = nullptr;  // fp32-rounded roots with modulus corrections (step kernels)
   float4* twp_y = nullptr;
   // K tables, index = 2*imag + half  (half: h = dt/2, else h = dt)
@@ -45,7 +43,7 @@ struct sgpe_ctx {
   // fp32 tables are then unused (the schedule fields above apply, with no prefetch)
   int prec = 0;             // sgpe_precision
   double4* psi64 = nullptr;
-  double4* twp64_x = nullptr;
+  double4* twp64_x = nullptr;  // fp64 roots (every context: the energy kernels transform in fp64)
   double4* twp64_y = nullptr;
   double4* kx64[4] = {nullptr, nullptr, nullptr, nullptr};
   double2* ky64[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -86,8 +84,8 @@ sgpe_schedule get_schedule(const sgpe_ctx* c);
 sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
 sgpe_status check_ctx(sgpe_ctx* c);
-// Arguments of the energy kernels for the context's state, with the given fp64 scratch (nx*ny
-// points) and partial buffers (kEnergyRowParts per row, then one per column block).
+// Arguments of the energy kernels for the context's state, with the given partial buffers
+// (kEnergyRowParts per row block, then one per column block).
 sgpe::EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_partials);
 // Copies n doubles of reduction partials from the device into the context's pinned host buffer
 // (queued on the context's stream, which is then synchronised) and points *host at it.  Returns

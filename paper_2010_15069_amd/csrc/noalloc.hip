@@ -3,8 +3,8 @@
 //
 // sgpe_energy writes the energy kernels' partial sums to a device buffer the context allocated and
 // brings them back through a pinned host buffer it grows on demand.  Here they live in one static
-// device array, `scratch`, of a fixed size: kEnergyRowParts per row and one per column block, for
-// up to kMaxAxis of each (every grid the library accepts).  Each device the library runs on holds
+// device array, `scratch`, of a fixed size: kEnergyRowParts per row block and one per column block,
+// for up to kMaxAxis of each (every grid the library accepts).  Each device the library runs on holds
 // its own copy until the process ends.  Host code never passes the array's
 // name to a kernel or a copy: on a device's first call the address of that device's copy is looked
 // up (hipGetSymbolAddress, with the device current) and kept, and only that address is used.  The
@@ -28,7 +28,7 @@
 namespace {
 
 constexpr size_t kMaxAxis = 4096;
-// kEnergyRowParts partials per row, then one per column block
+// kEnergyRowParts partials per row block, then one per column block
 constexpr size_t kScratchDoubles = sgpe::kEnergyRowParts * kMaxAxis + kMaxAxis;
 constexpr int kMaxDevices = 64;
 
@@ -70,8 +70,8 @@ extern "C" sgpe_status sgpe_energy_noalloc(sgpe_ctx* c, double* e_dev) {
   double* row_parts = base;
   double* col_parts = row_parts + RP * kMaxAxis;
   const sgpe::EnergyArgs a = sgpe_host::energy_args(c, row_parts, col_parts);
-  const int ncols = p.nx / a.cols;
-  if (size_t(p.ny) > kMaxAxis || size_t(ncols) > kMaxAxis) return SGPE_ENOMEM;   // beyond the static array
+  const int nrows = p.ny / a.rows, ncols = p.nx / a.cols;
+  if (size_t(nrows) > kMaxAxis || size_t(ncols) > kMaxAxis) return SGPE_ENOMEM;   // beyond the static array
   hipError_t e = sgpe::launch_energy(a, c->stream);
   if (e == hipSuccess) e = sgpe::launch_energy_finish(a, p.norm0, e_dev, c->stream);
   if (e != hipSuccess) {

@@ -1,5 +1,8 @@
 // HIP kernels of the split-step solver for gfx950: energy and norm reductions, and the
 // workgroup geometry shared by all passes.
+#include <algorithm>
+
+#include "col_body.hpp"
 #include "fft_device.hpp"
 #include "sgpe_internal.hpp"
 
@@ -47,14 +50,30 @@ int col_default_cols(int nx, int ny, int points, size_t max_lds) {
   return c;
 }
 
-// Energy kernels (fp64, radix-2 in LDS): one row per row-kernel workgroup (2 nx double2 of LDS);
-// up to 4 columns per column-kernel workgroup (2 ny double2 each) as LDS allows.
-bool energy_fits(int nx, int ny, size_t max_lds) { return size_t(2) * nx * 16 <= max_lds && size_t(2) * ny * 16 <= max_lds; }
+// Energy kernels (fp64, register-resident transforms, 16 points per lane up to the line length):
+// T = N / 16 lanes per component of a line, two components per lane pair.  Row kernel: 128 / T rows
+// per workgroup (at least one; 512 threads at 4096 points).  Column kernel: 128 / T columns per
+// workgroup (at least one), fewer where the grid has fewer.  Both interleave their transforms in
+// LDS slot by slot, N + N/16 double2 slots each.
+int energy_points(int n) { return n >= 16 ? 16 : n; }
+
+size_t energy_lds_bytes(int n, int lines) { return size_t(2) * lines * size_t(n + n / 16) * 16; }
+
+int energy_rows_per_block(int nx, int ny) {
+  const int t = nx / energy_points(nx);
+  return std::max(1, std::min(ny, 128 / t));
+}
 
 int energy_cols_per_block(int nx, int ny, size_t max_lds) {
-  int c = 4;
-  while (c > 1 && (size_t(2) * c * ny * 16 > max_lds || nx % c != 0)) c >>= 1;
+  const int t = ny / energy_points(ny);
+  int c = std::max(1, std::min(nx, 128 / t));
+  while (c > 1 && energy_lds_bytes(ny, c) > max_lds) c >>= 1;
   return c;
+}
+
+bool energy_fits(int nx, int ny, size_t max_lds) {
+  return energy_lds_bytes(nx, energy_rows_per_block(nx, ny)) <= max_lds &&
+         energy_lds_bytes(ny, energy_cols_per_block(nx, ny, max_lds)) <= max_lds;
 }
 
 int norm_blocks() { return 256; }
@@ -69,115 +88,120 @@ int norm_blocks() { return 256; }
 //   * the k_y term (k_y^2 / 2): the same with the y-DFT of every column, times nx;
 //   * the uniform Raman term Omega Re(u^* d^) of H_K: N times its real-space sum, so it joins the
 //     spatial Raman term Omega(r) Re(u* d) of the real-space energy.
-// Row kernel: the real-space terms, the norm and the row's k_x terms (one row per workgroup); column
-// kernel: the k_y terms of up to 4 columns per workgroup.  The DFTs are in-place radix-2 transforms
-// in LDS: input stored at bit-reversed positions, log2 N butterfly stages, roots exp(-2 pi i j / N)
-// from fp64 host tables.  Exact to fp64 rounding, so the energy of a complex64 state carries no
-// transform error of its own.  The partials are scaled so that the host's combination reads
-// E = (w / N ek + w er) / norm + w ei norm0 / norm^2 (w = dx dy, N = nx ny), as for a 2-D sum.
+// Row kernel: the real-space terms, the norm and the rows' k_x terms; column kernel: the columns'
+// k_y terms.  The DFTs are the step kernels' register-resident forward transform (fwd_pass: radix-16
+// stages exchanged through LDS, natural order in and out) instantiated in fp64 with the roots
+// rounded once to fp64, on the state widened to fp64 as it is loaded, so the energy of a complex64
+// state carries no transform error of its own.  Each lane holds one component of one line.  The
+// partials are scaled so that the
+// host's combination reads E = (w / N ek + w er) / norm + w ei norm0 / norm^2 (w = dx dy,
+// N = nx ny), as for a 2-D sum.
 // -------------------------------------------------------------------------------------------
-__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
+extern __shared__ __align__(16) unsigned char energy_lds[];
 
-// `count` independent length-N transforms stored one after another in `buf` (each already in
-// bit-reversed order); all threads of the workgroup take part.
-__device__ __forceinline__ void lds_fft64(double2* buf, int n, int log2n, int count, const double2* __restrict__ w) {
-  const int half_total = count * (n >> 1);
-  for (int s = 1; s <= log2n; ++s) {
-    const int half = 1 << (s - 1);
-    const int tw_step = n >> s;  // root index stride: exp(-2 pi i k / 2^s) = w[k n / 2^s]
-    __syncthreads();
-    for (int b = threadIdx.x; b < half_total; b += blockDim.x) {
-      const int tr = b / (n >> 1);
-      const int q = b - tr * (n >> 1);
-      const int k = q & (half - 1);
-      const int i0 = tr * n + ((q >> (s - 1)) << s) + k;
-      const double2 a0 = buf[i0];
-      const double2 a1 = zmul(buf[i0 + half], w[k * tw_step]);
-      buf[i0] = make_double2(a0.x + a1.x, a0.y + a1.y);
-      buf[i0 + half] = make_double2(a0.x - a1.x, a0.y - a1.y);
-    }
+// The lane's component of state point i (Q: float4 for a complex64 state, double4 for complex128),
+// widened to fp64.
+template <class Q>
+__device__ __forceinline__ double2 energy_load(const EnergyArgs& a, size_t i, int comp) {
+  if constexpr (sizeof(Q) == sizeof(double4)) {
+    return reinterpret_cast<const double2*>(a.psi64)[2 * i + comp];
+  } else {
+    const float2 v = reinterpret_cast<const float2*>(a.psi)[2 * i + comp];
+    return make_double2(v.x, v.y);
   }
-  __syncthreads();
 }
 
-__device__ __forceinline__ int bitrev(int j, int log2n) { return static_cast<int>(__brev(static_cast<unsigned>(j)) >> (32 - log2n)); }
+__device__ __forceinline__ int energy_freq(int j, int n) { return j < n / 2 ? j : j - n; }
 
 // Point i of the state as four doubles {re_up, im_up, re_dn, im_dn}.
-__device__ __forceinline__ double4 state_point(const EnergyArgs& a, size_t i) {
-  if (a.psi64) return a.psi64[i];
-  const float4 v = a.psi[i];
-  return make_double4(v.x, v.y, v.z, v.w);
+template <class Q>
+__device__ __forceinline__ double4 energy_point(const EnergyArgs& a, size_t i) {
+  if constexpr (sizeof(Q) == sizeof(double4)) {
+    return a.psi64[i];
+  } else {
+    const float4 v = a.psi[i];
+    return make_double4(v.x, v.y, v.z, v.w);
+  }
 }
 
-__global__ void __launch_bounds__(256) energy_row_kernel(EnergyArgs a) {
-  extern __shared__ double2 elds[];
+template <int N, class Q>
+__global__ void __launch_bounds__(512) energy_row_kernel(EnergyArgs a) {
+  constexpr int P = N >= 16 ? 16 : N;
+  constexpr int T = N / P;
   __shared__ double red[64];
-  const int n = a.nx, log2n = __builtin_ctz(a.nx);
-  const int row = blockIdx.x;
+  const int tid = threadIdx.x, comp = tid & 1, pair = tid >> 1;
+  const int t = pair & (T - 1), r = pair / T;
+  const int row = blockIdx.x * a.rows + r;
+  const size_t row0 = size_t(row) * N;
+  // The real-space terms and the norm, point by point with both components in one load (a loop of
+  // few registers of its own; the transform's loads below then find the row in the L2).
   const double y = a.ymin + a.dy * row;
   const double om_row = a.om_y ? a.om_y[row] : 0.0;
   double er = 0.0, ei = 0.0, nr = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double4 v = state_point(a, size_t(row) * n + j);
-    const double ur = v.x, ui = v.y, dr = v.z, di = v.w;
+#pragma unroll 2
+  for (int j = tid & (2 * T - 1); j < N; j += 2 * T) {
+    const double4 q = energy_point<Q>(a, row0 + j);
     const double x = a.xmin + a.dx * j;
     const double V = a.wx2h * x * x + a.wy2h * y * y;
-    const double nu = ur * ur + ui * ui, nd = dr * dr + di * di;
+    const double nu = q.x * q.x + q.y * q.y, nd = q.z * q.z + q.w * q.w;
     // spatial Raman coupling Omega(r) and the uniform one Omega (its k-space sum, by Parseval)
     const double om = (a.om_x ? a.om_x[j] + om_row : 0.0) + a.omega;
-    er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (ur * dr + ui * di);
+    er += V * (nu + nd) + 0.5 * a.delta * (nu - nd) + om * (q.x * q.z + q.y * q.w);
     ei += 0.5 * a.g_uu * nu * nu + 0.5 * a.g_dd * nd * nd + a.g_ud * nu * nd;
     nr += nu + nd;
-    const int r = bitrev(j, log2n);
-    elds[r] = make_double2(ur, ui);
-    elds[n + r] = make_double2(dr, di);
   }
-  lds_fft64(elds, n, log2n, 2, a.twx);
-  double ex = 0.0;   // this row's k_x terms
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double kx = (j < n / 2 ? j : j - n) * a.dkx;
-    const double2 u = elds[j], d = elds[n + j];
-    const double pu = u.x * u.x + u.y * u.y, pd = d.x * d.x + d.y * d.y;
-    ex += 0.5 * kx * kx * (pu + pd) + a.k_l * kx * (pu - pd);
+  // keep the transform's loads (and their registers) after the loop above
+  asm volatile("" ::: "memory");
+  double2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = energy_load<Q>(a, row0 + t + T * m, comp);
+  TwPlain<N, P, double> tr;
+  load_twiddles<N>(tr, t, a.twx);
+  const LdsView<double2> lds{reinterpret_cast<double2*>(energy_lds) + 2 * r + comp, 1 + __builtin_ctz(a.rows)};
+  fwd_pass<N>(v, lds, t, tr);
+  const double kl = comp == 0 ? a.k_l : -a.k_l;
+  double ex = 0.0;   // the rows' k_x terms
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const double kx = energy_freq(t + T * m, N) * a.dkx;
+    ex += (0.5 * kx * kx + kl * kx) * (v[m].x * v[m].x + v[m].y * v[m].y);
   }
   const double se = block_sum(er, red);
   const double sx = block_sum(ex, red);
   const double si = block_sum(ei, red);
   const double sn = block_sum(nr, red);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     // w / N * (ny * sx) = w * sx / nx: the k_x terms join the real-space linear ones
-    a.row_partials[kEnergyRowParts * blockIdx.x] = se + sx / double(n);
+    a.row_partials[kEnergyRowParts * blockIdx.x] = se + sx / double(N);
     a.row_partials[kEnergyRowParts * blockIdx.x + 1] = si;
     a.row_partials[kEnergyRowParts * blockIdx.x + 2] = sn;
   }
 }
 
-__global__ void __launch_bounds__(256) energy_col_kernel(EnergyArgs a) {
-  extern __shared__ double2 elds[];
+template <int N, class Q>
+__global__ void __launch_bounds__(512) energy_col_kernel(EnergyArgs a) {
+  constexpr int P = N >= 16 ? 16 : N;
+  constexpr int T = N / P;
   __shared__ double red[64];
-  const int n = a.ny, log2n = __builtin_ctz(a.ny);
   const int C = a.cols;
-  const int x0 = blockIdx.x * C;
-  // columns x0 .. x0 + C - 1: transform 2c (up) and 2c + 1 (down) of column c
-  for (int i = threadIdx.x; i < C * n; i += blockDim.x) {
-    const int c = i % C, iy = i / C;
-    const double4 v = state_point(a, size_t(iy) * a.nx + x0 + c);
-    const int r = bitrev(iy, log2n);
-    elds[(2 * c) * n + r] = make_double2(v.x, v.y);
-    elds[(2 * c + 1) * n + r] = make_double2(v.z, v.w);
-  }
-  lds_fft64(elds, n, log2n, 2 * C, a.twy);
+  const int tid = threadIdx.x, comp = tid & 1, pair = tid >> 1;
+  const int cc = pair & (C - 1), t = pair / C;
+  const int x = col_group(blockIdx.x, gridDim.x) * C + cc;
+  double2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = energy_load<Q>(a, size_t(t + T * m) * a.nx + x, comp);
+  TwPlain<N, P, double> tr;
+  load_twiddles<N>(tr, t, a.twy);
+  const LdsView<double2> lds{reinterpret_cast<double2*>(energy_lds) + 2 * cc + comp, 1 + __builtin_ctz(C)};
+  fwd_pass<N>(v, lds, t, tr);
   double acc = 0.0;
-  for (int i = threadIdx.x; i < C * n; i += blockDim.x) {
-    const int c = i / n, iy = i - c * n;
-    const double ky = (iy < n / 2 ? iy : iy - n) * a.dky;
-    const double2 u = elds[(2 * c) * n + iy], d = elds[(2 * c + 1) * n + iy];
-    acc += 0.5 * ky * ky * (u.x * u.x + u.y * u.y + d.x * d.x + d.y * d.y);
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const double ky = energy_freq(t + T * m, N) * a.dky;
+    acc += 0.5 * ky * ky * (v[m].x * v[m].x + v[m].y * v[m].y);
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) a.col_partials[blockIdx.x] = double(a.nx) * s;   // nx times the columns' sum
+  if (tid == 0) a.col_partials[blockIdx.x] = double(a.nx) * s;   // nx times the columns' sum
 }
 
 // -------------------------------------------------------------------------------------------
@@ -224,19 +248,58 @@ __global__ void __launch_bounds__(64) energy_finish_kernel(const double* __restr
 hipError_t launch_energy_finish(const EnergyArgs& a, double norm0, double* out, hipStream_t s) {
   const double w = a.dx * a.dy;
   const double inv_npts = 1.0 / (double(a.nx) * double(a.ny));
-  hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(64), 0, s, a.row_partials, a.ny, a.col_partials,
+  hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(64), 0, s, a.row_partials, a.ny / a.rows, a.col_partials,
                      a.nx / a.cols, w, inv_npts, norm0, out);
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
-  const size_t row_lds = size_t(2) * a.nx * sizeof(double2);
-  const size_t col_lds = size_t(2) * a.cols * a.ny * sizeof(double2);
-  hipLaunchKernelGGL(energy_row_kernel, dim3(a.ny), dim3(256), row_lds, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(energy_col_kernel, dim3(a.nx / a.cols), dim3(256), col_lds, s, a);
+template <int N>
+hipError_t launch_energy_row(const EnergyArgs& a, hipStream_t s) {
+  constexpr int T = N / (N >= 16 ? 16 : N);
+  const dim3 grid(a.ny / a.rows), block(2 * T * a.rows);
+  const size_t lds = energy_lds_bytes(N, a.rows);
+  if (a.psi64) hipLaunchKernelGGL((energy_row_kernel<N, double4>), grid, block, lds, s, a);
+  else hipLaunchKernelGGL((energy_row_kernel<N, float4>), grid, block, lds, s, a);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_energy_col(const EnergyArgs& a, hipStream_t s) {
+  constexpr int T = N / (N >= 16 ? 16 : N);
+  const dim3 grid(a.nx / a.cols), block(2 * T * a.cols);
+  const size_t lds = energy_lds_bytes(N, a.cols);
+  if (a.psi64) hipLaunchKernelGGL((energy_col_kernel<N, double4>), grid, block, lds, s, a);
+  else hipLaunchKernelGGL((energy_col_kernel<N, float4>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (a.nx) {
+    case 16: e = launch_energy_row<16>(a, s); break;
+    case 32: e = launch_energy_row<32>(a, s); break;
+    case 64: e = launch_energy_row<64>(a, s); break;
+    case 128: e = launch_energy_row<128>(a, s); break;
+    case 256: e = launch_energy_row<256>(a, s); break;
+    case 512: e = launch_energy_row<512>(a, s); break;
+    case 1024: e = launch_energy_row<1024>(a, s); break;
+    case 2048: e = launch_energy_row<2048>(a, s); break;
+    case 4096: e = launch_energy_row<4096>(a, s); break;
+    default: break;
+  }
+  if (e != hipSuccess) return e;
+  switch (a.ny) {
+    case 16: return launch_energy_col<16>(a, s);
+    case 32: return launch_energy_col<32>(a, s);
+    case 64: return launch_energy_col<64>(a, s);
+    case 128: return launch_energy_col<128>(a, s);
+    case 256: return launch_energy_col<256>(a, s);
+    case 512: return launch_energy_col<512>(a, s);
+    case 1024: return launch_energy_col<1024>(a, s);
+    case 2048: return launch_energy_col<2048>(a, s);
+    case 4096: return launch_energy_col<4096>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {

@@ -94,9 +94,10 @@ struct EnergyArgs {
   const float4* psi;         // the complex64 state, or
   const double4* psi64;      //   the complex128 one (exactly one is set)
   int nx, ny;
-  int cols;                  // columns per column-kernel workgroup
-  const double2* twx;        // roots exp(-2 pi i j / nx), j < nx / 2, fp64
-  const double2* twy;        // the same for ny
+  int rows;                  // rows per row-kernel workgroup (energy_rows_per_block)
+  int cols;                  // columns per column-kernel workgroup (energy_cols_per_block)
+  const double4* twx;        // the fp64 step-kernel roots of length nx ({cos, sin, 0, 0} of 2 pi j / nx)
+  const double4* twy;        // the same for ny
   double xmin, dx, ymin, dy;
   double wx2h, wy2h;         // wx^2/2, wy^2/2
   double delta, g_uu, g_dd, g_ud;
@@ -104,8 +105,8 @@ struct EnergyArgs {
   const double* om_x;        // spatial Raman coupling Omega_x(x_j) (length nx) and Omega_y(y_i)
   const double* om_y;        //   (length ny); both NULL without one
   double dkx, dky;
-  double* row_partials;      // kEnergyRowParts per row: {linear real-space energy and the row's
-                             //   k_x terms, interaction energy, norm}
+  double* row_partials;      // kEnergyRowParts per row block: {linear real-space energy and the
+                             //   rows' k_x terms, interaction energy, norm}
   double* col_partials;      // 1 per column block: its columns' k_y terms
 };
 
@@ -226,7 +227,9 @@ int row_rows_per_block(int nx, int ny, int points, size_t max_lds);
 int col_default_cols(int nx, int ny, int points, size_t max_lds);
 bool col_cols_supported(int nx, int ny, int cols, int iters, int points, size_t max_lds);
 bool energy_fits(int nx, int ny, size_t max_lds);
+int energy_rows_per_block(int nx, int ny);
 int energy_cols_per_block(int nx, int ny, size_t max_lds);
+size_t energy_lds_bytes(int n, int lines);
 size_t row_lds_bytes(int nx, int rows);
 size_t col_lds_bytes(int ny, int cols);
 size_t col_lds_bytes_c128(int ny, int cols, int points);
