@@ -316,7 +316,8 @@ def ground_state_learned(torch, stream, model, check_every=50, max_steps=200000)
 def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_every=50):
     """Held-out parameter sets (seed 2 of the sweep distribution at 256^2), each relaxed from the
     plain Thomas-Fermi start and from the learned start, all sets of one arm in one batch, the
-    energy checked every 50 steps.  E_ref per set: the lower of the two arms' final energies.
+    energy of every set checked every 50 steps (sgpe_batch_energies: one launch per kernel for the
+    whole batch).  E_ref per set: the lower of the two arms' final energies.
     Reported per arm: steps and batch wall time until each set is within 1e-6 (medians)."""
     import numpy as np
     from paper_2010_15069_amd import Batch, surrogate
@@ -332,7 +333,7 @@ def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_ever
         trace, clock = [], []
         for _ in range(steps // check_every):
             b.step_imag(check_every)
-            trace.append([b.energy(i) for i in range(len(ps))])
+            trace.append(b.energies())
             clock.append(time.perf_counter() - t0)
         b.close()
         return np.array(trace), np.array(clock)

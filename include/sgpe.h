@@ -304,7 +304,7 @@ sgpe_status sgpe_probe_placement(int32_t gx, int32_t gy, int32_t threads, uint32
  * loops, harnesses that forbid hipMalloc): the same energy per particle, written as one double to
  * e_dev (device memory, caller-owned), asynchronously on the context's stream.  The call allocates
  * nothing and never synchronises: the energy kernels' partial sums live in a static device array of
- * 128 KiB (three per row and one per column block, up to 4096 of each: every grid the library
+ * 128 KiB (three per row block and one per column block, up to 4096 of each: every grid the library
  * accepts), which every GPU the library runs on holds until the process ends.  Every call on a device
  * shares that array; calls that overlap on one device (several streams or threads) race on it and
  * must be ordered by the caller.  The result equals sgpe_energy's up to the order of the final fp64
@@ -385,6 +385,18 @@ sgpe_status sgpe_batch_set_psi(sgpe_batch* batch, int32_t index, const double* p
 sgpe_status sgpe_batch_get_psi(sgpe_batch* batch, int32_t index, double* psi);
 sgpe_status sgpe_batch_energy(sgpe_batch* batch, int32_t index, double* e_per_particle);
 sgpe_status sgpe_batch_norm(sgpe_batch* batch, int32_t index, double* norm);
+
+/* The energy per particle (as sgpe_energy: the Gross-Pitaevskii functional of Eqs. (H1)-(H4) of
+ * the state rescaled to norm0) of every instance at once, into e[i] for instance i (host array of
+ * sgpe_batch_size doubles).  Each class is one launch of each energy kernel over all its members
+ * (grid y = member), their partials combined on the device; then one copy and one
+ * synchronisation of the batch stream, instead of one per instance.  Equal to sgpe_batch_energy's
+ * values up to the order of the final fp64 sums.  The argument tables and a device / pinned array of
+ * one double per instance are allocated on the first call and kept by the batch.
+ * Errors: SGPE_EINVAL (NULL), SGPE_ESTATE (an instance without a state), SGPE_ENOMEM, SGPE_EDEVICE,
+ * SGPE_ENONFINITE (an energy not finite, or an instance's latched status; every e[i] is written and
+ * a non-finite energy latches in its instance). */
+sgpe_status sgpe_batch_energies(sgpe_batch* batch, double* e);
 
 /* n steps of every instance (all must have a state: else SGPE_ESTATE); asynchronous on the batch
  * stream. */

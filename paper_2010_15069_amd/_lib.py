@@ -73,7 +73,7 @@ EXPORTS = [
     "sgpe_batch_set_schedule", "sgpe_batch_autotune", "sgpe_batch_use_persistent",
     "sgpe_set_raman_profile", "sgpe_add_noise", "sgpe_phase_separation", "sgpe_population_radius",
     "sgpe_winding", "sgpe_set_splitting", "sgpe_create_ex", "sgpe_probe_exchange", "sgpe_energy_noalloc",
-    "sgpe_probe_placement", "sgpe_relax_imag",
+    "sgpe_probe_placement", "sgpe_relax_imag", "sgpe_batch_energies",
 ]
 
 
@@ -172,6 +172,7 @@ def _lib():
         "sgpe_probe_placement": ([i32, i32, i32, P(ctypes.c_uint32)], st),
         "sgpe_relax_imag": ([vp, ctypes.c_int64, ctypes.c_int64, i32, ctypes.c_double, ctypes.c_double,
                              P(ctypes.c_double), ctypes.c_int64, P(RelaxResult)], st),
+        "sgpe_batch_energies": ([vp, P(ctypes.c_double)], st),
     })
     for name, (args, res) in batch_sigs.items():
         f = getattr(lib, name)

@@ -498,6 +498,8 @@ EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_part
   a.psi64 = c->psi64;
   a.nx = p.nx;
   a.ny = p.ny;
+  a.norm0 = p.norm0;
+  a.result = nullptr;
   a.rows = sgpe::energy_rows_per_block(p.nx, p.ny);
   a.cols = sgpe::energy_cols_per_block(p.nx, p.ny, c->max_lds);
   a.twx = c->twp64_x;

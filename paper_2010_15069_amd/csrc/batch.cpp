@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -42,6 +43,7 @@ struct BatchClass {
   std::vector<int> members;
   RowArgs* row_tab = nullptr;   // device, [ROWTAB_N][count]
   ColArgs* col_tab = nullptr;   // device, [COLTAB_N][count]
+  sgpe::EnergyArgs* e_tab = nullptr;   // device, [count]: the members' energy arguments
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
 };
@@ -75,6 +77,9 @@ struct sgpe_batch {
   unsigned* p_abort_host_dev = nullptr;
   int p_grid = 0;                   // workgroups of the persistent launch (all co-resident)
   unsigned p_spin_limit = sgpe::kPersistSpinLimit;
+  // sgpe_batch_energies: every instance's energy on the device, and its pinned host copy
+  double* e_dev = nullptr;
+  double* e_host = nullptr;
 };
 
 namespace {
@@ -348,6 +353,7 @@ void sgpe_batch_destroy(sgpe_batch* b) {
     if (k.stream) (void)hipStreamSynchronize(k.stream);
     if (k.row_tab) (void)hipFree(k.row_tab);
     if (k.col_tab) (void)hipFree(k.col_tab);
+    if (k.e_tab) (void)hipFree(k.e_tab);
     if (k.done) (void)hipEventDestroy(k.done);
     if (k.stream) (void)hipStreamDestroy(k.stream);
   }
@@ -361,6 +367,8 @@ void sgpe_batch_destroy(sgpe_batch* b) {
                     static_cast<void*>(b->p_words), static_cast<void*>(b->p_cls_dev)})
     if (ptr) (void)hipFree(ptr);
   if (b->p_abort_host) (void)hipHostFree(b->p_abort_host);
+  if (b->e_dev) (void)hipFree(b->e_dev);
+  if (b->e_host) (void)hipHostFree(b->e_host);
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->enter) (void)hipEventDestroy(b->enter);
   if (b->leave) (void)hipEventDestroy(b->leave);
@@ -407,6 +415,67 @@ sgpe_status sgpe_batch_step_imag(sgpe_batch* b, int64_t n) { return b ? run(b, n
 sgpe_status sgpe_batch_energy(sgpe_batch* b, int32_t index, double* e) {
   if (!valid_index(b, index)) return SGPE_EINVAL;
   return sgpe_energy(b->inst[index], e);
+}
+
+sgpe_status sgpe_batch_energies(sgpe_batch* b, double* e) {
+  if (!b || !e) return SGPE_EINVAL;
+  if (hipSetDevice(b->device) != hipSuccess) return hip_status(hipErrorInvalidDevice);
+  for (sgpe_ctx* c : b->inst)
+    if (!c->has_state) return SGPE_ESTATE;
+  const size_t n = b->inst.size();
+  if (!b->e_dev) {
+    void* d = nullptr;
+    void* h = nullptr;
+    if (hipMalloc(&d, n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return SGPE_ENOMEM;
+    }
+    if (hipHostMalloc(&h, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(d);
+      return SGPE_ENOMEM;
+    }
+    b->e_dev = static_cast<double*>(d);
+    b->e_host = static_cast<double*>(h);
+  }
+  for (auto& k : b->cls) {
+    if (!k.e_tab) {   // the members' arguments: their states, tables and partial buffers are fixed
+      std::vector<sgpe::EnergyArgs> tab;
+      for (int m : k.members) {
+        sgpe_ctx* c = b->inst[size_t(m)];
+        sgpe::EnergyArgs a = energy_args(c, c->epart, c->epart + sgpe::kEnergyRowParts * c->p.ny);
+        a.result = b->e_dev + m;
+        tab.push_back(a);
+      }
+      void* d = nullptr;
+      if (hipMalloc(&d, tab.size() * sizeof(sgpe::EnergyArgs)) != hipSuccess) {
+        (void)hipGetLastError();
+        return SGPE_ENOMEM;
+      }
+      if (hipMemcpy(d, tab.data(), tab.size() * sizeof(sgpe::EnergyArgs), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d);
+        return SGPE_EDEVICE;
+      }
+      k.e_tab = static_cast<sgpe::EnergyArgs*>(d);
+    }
+    const sgpe_ctx* c0 = b->inst[size_t(k.members[0])];
+    const hipError_t err = sgpe::launch_energy_batch(k.e_tab, int(k.members.size()), k.nx, k.ny,
+                                                     sgpe::energy_rows_per_block(k.nx, k.ny),
+                                                     sgpe::energy_cols_per_block(k.nx, k.ny, c0->max_lds), b->stream);
+    if (err != hipSuccess) return hip_status(err);
+  }
+  hipError_t err = hipMemcpyAsync(b->e_host, b->e_dev, n * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
+  if (err != hipSuccess) return hip_status(err);
+  sgpe_status out = SGPE_OK;
+  for (size_t i = 0; i < n; ++i) {
+    e[i] = b->e_host[i];
+    sgpe_ctx* c = b->inst[i];
+    if (!std::isfinite(e[i])) c->latched = SGPE_ENONFINITE;
+    if (latched_status(c) != SGPE_OK && out == SGPE_OK) out = c->latched;
+  }
+  return out;
 }
 
 sgpe_status sgpe_batch_norm(sgpe_batch* b, int32_t index, double* n) {

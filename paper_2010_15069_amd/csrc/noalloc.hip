@@ -73,7 +73,7 @@ extern "C" sgpe_status sgpe_energy_noalloc(sgpe_ctx* c, double* e_dev) {
   const int nrows = p.ny / a.rows, ncols = p.nx / a.cols;
   if (size_t(nrows) > kMaxAxis || size_t(ncols) > kMaxAxis) return SGPE_ENOMEM;   // beyond the static array
   hipError_t e = sgpe::launch_energy(a, c->stream);
-  if (e == hipSuccess) e = sgpe::launch_energy_finish(a, p.norm0, e_dev, c->stream);
+  if (e == hipSuccess) e = sgpe::launch_energy_finish(a, e_dev, c->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return sgpe_host::status_of(e);

@@ -50,23 +50,25 @@ int col_default_cols(int nx, int ny, int points, size_t max_lds) {
   return c;
 }
 
-// Energy kernels (fp64, register-resident transforms, 16 points per lane up to the line length):
-// T = N / 16 lanes per component of a line, two components per lane pair.  Row kernel: 128 / T rows
-// per workgroup (at least one; 512 threads at 4096 points).  Column kernel: 128 / T columns per
-// workgroup (at least one), fewer where the grid has fewer.  Both interleave their transforms in
-// LDS slot by slot, N + N/16 double2 slots each.
-int energy_points(int n) { return n >= 16 ? 16 : n; }
+// Energy kernels (fp64, register-resident transforms): 8 points per lane below 1024 points, 16
+// from there; T = N / points lanes per component of a line, two components per lane pair.  Lines per
+// workgroup: up to 128 / T (a workgroup of at most 256 threads, 512 at 4096 points), but no more
+// than keeps ~256 workgroups on the grid (small grids are latency-bound: more workgroups, each
+// shorter).  Both kernels interleave their transforms in LDS slot by slot, N + N/16 double2 slots
+// each.
+int energy_points(int n) { return n >= 1024 ? 16 : 8; }
 
 size_t energy_lds_bytes(int n, int lines) { return size_t(2) * lines * size_t(n + n / 16) * 16; }
 
-int energy_rows_per_block(int nx, int ny) {
-  const int t = nx / energy_points(nx);
-  return std::max(1, std::min(ny, 128 / t));
+static int energy_lines_per_block(int n, int count) {
+  const int t = n / energy_points(n);
+  return std::max(1, std::min(128 / t, count / 256));
 }
 
+int energy_rows_per_block(int nx, int ny) { return energy_lines_per_block(nx, ny); }
+
 int energy_cols_per_block(int nx, int ny, size_t max_lds) {
-  const int t = ny / energy_points(ny);
-  int c = std::max(1, std::min(nx, 128 / t));
+  int c = energy_lines_per_block(ny, nx);
   while (c > 1 && energy_lds_bytes(ny, c) > max_lds) c >>= 1;
   return c;
 }
@@ -124,14 +126,18 @@ __device__ __forceinline__ double4 energy_point(const EnergyArgs& a, size_t i) {
   }
 }
 
+template <int N>
+constexpr int energy_points_c() { return N >= 1024 ? 16 : 8; }
+
+// Rows block*rows .. block*rows + rows - 1 of the state a describes.
 template <int N, class Q>
-__global__ void __launch_bounds__(512) energy_row_kernel(EnergyArgs a) {
-  constexpr int P = N >= 16 ? 16 : N;
+__device__ __forceinline__ void energy_row_body(const EnergyArgs& a, int block) {
+  constexpr int P = energy_points_c<N>();
   constexpr int T = N / P;
   __shared__ double red[64];
   const int tid = threadIdx.x, comp = tid & 1, pair = tid >> 1;
   const int t = pair & (T - 1), r = pair / T;
-  const int row = blockIdx.x * a.rows + r;
+  const int row = block * a.rows + r;
   const size_t row0 = size_t(row) * N;
   // The real-space terms and the norm, point by point with both components in one load (a loop of
   // few registers of its own; the transform's loads below then find the row in the L2).
@@ -172,21 +178,35 @@ __global__ void __launch_bounds__(512) energy_row_kernel(EnergyArgs a) {
   const double sn = block_sum(nr, red);
   if (tid == 0) {
     // w / N * (ny * sx) = w * sx / nx: the k_x terms join the real-space linear ones
-    a.row_partials[kEnergyRowParts * blockIdx.x] = se + sx / double(N);
-    a.row_partials[kEnergyRowParts * blockIdx.x + 1] = si;
-    a.row_partials[kEnergyRowParts * blockIdx.x + 2] = sn;
+    a.row_partials[kEnergyRowParts * block] = se + sx / double(N);
+    a.row_partials[kEnergyRowParts * block + 1] = si;
+    a.row_partials[kEnergyRowParts * block + 2] = sn;
   }
 }
 
 template <int N, class Q>
-__global__ void __launch_bounds__(512) energy_col_kernel(EnergyArgs a) {
-  constexpr int P = N >= 16 ? 16 : N;
+__global__ void __launch_bounds__(512) energy_row_kernel(EnergyArgs a) {
+  energy_row_body<N, Q>(a, blockIdx.x);
+}
+
+// Batched: grid y = the members of a batch class, each with its own arguments.
+template <int N, class Q>
+__global__ void __launch_bounds__(512) energy_row_kernel_batch(const EnergyArgs* __restrict__ tab) {
+  const EnergyArgs a = tab[blockIdx.y];
+  energy_row_body<N, Q>(a, blockIdx.x);
+}
+
+// Columns of column block `block` (of a.nx / a.cols; the blocks spread over the XCDs as the column
+// pass spreads its tiles).
+template <int N, class Q>
+__device__ __forceinline__ void energy_col_body(const EnergyArgs& a, int block) {
+  constexpr int P = energy_points_c<N>();
   constexpr int T = N / P;
   __shared__ double red[64];
   const int C = a.cols;
   const int tid = threadIdx.x, comp = tid & 1, pair = tid >> 1;
   const int cc = pair & (C - 1), t = pair / C;
-  const int x = col_group(blockIdx.x, gridDim.x) * C + cc;
+  const int x = col_group(block, a.nx / C) * C + cc;
   double2 v[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = energy_load<Q>(a, size_t(t + T * m) * a.nx + x, comp);
@@ -201,7 +221,18 @@ __global__ void __launch_bounds__(512) energy_col_kernel(EnergyArgs a) {
     acc += 0.5 * ky * ky * (v[m].x * v[m].x + v[m].y * v[m].y);
   }
   const double s = block_sum(acc, red);
-  if (tid == 0) a.col_partials[blockIdx.x] = double(a.nx) * s;   // nx times the columns' sum
+  if (tid == 0) a.col_partials[block] = double(a.nx) * s;   // nx times the columns' sum
+}
+
+template <int N, class Q>
+__global__ void __launch_bounds__(512) energy_col_kernel(EnergyArgs a) {
+  energy_col_body<N, Q>(a, blockIdx.x);
+}
+
+template <int N, class Q>
+__global__ void __launch_bounds__(512) energy_col_kernel_batch(const EnergyArgs* __restrict__ tab) {
+  const EnergyArgs a = tab[blockIdx.y];
+  energy_col_body<N, Q>(a, blockIdx.x);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -221,41 +252,49 @@ __global__ void __launch_bounds__(256) norm_kernel(const Q* __restrict__ psi, lo
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// One wave combines the energy kernels' partials on the device: each kind summed in a fixed order
-// (lane-strided, then a fixed butterfly), then the energy per particle of the state rescaled to
-// norm0, E = (w / N ek + w er) / norm + w ei norm0 / norm^2 with norm = w nr.
-__global__ void __launch_bounds__(64) energy_finish_kernel(const double* __restrict__ row_parts, int nrows,
-                                                           const double* __restrict__ col_parts, int ncols, double w,
-                                                           double inv_npts, double norm0, double* __restrict__ out) {
-  const int lane = threadIdx.x;
+// One workgroup combines the energy kernels' partials on the device: each kind summed in a fixed
+// order (thread-strided, then block_sum's fixed tree), then the energy per particle of the state
+// rescaled to norm0, E = (w / N ek + w er) / norm + w ei norm0 / norm^2 with norm = w nr.
+__device__ __forceinline__ void energy_finish_body(const EnergyArgs& a, double* out) {
+  __shared__ double red[64];
+  const int nrows = a.ny / a.rows, ncols = a.nx / a.cols;
   double er = 0.0, ei = 0.0, nr = 0.0, ek = 0.0;
-  for (int b = lane; b < nrows; b += 64) {
-    er += row_parts[kEnergyRowParts * b];
-    ei += row_parts[kEnergyRowParts * b + 1];
-    nr += row_parts[kEnergyRowParts * b + 2];
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nrows; b += blockDim.x) {
+    er += a.row_partials[kEnergyRowParts * b];
+    ei += a.row_partials[kEnergyRowParts * b + 1];
+    nr += a.row_partials[kEnergyRowParts * b + 2];
   }
-  for (int b = lane; b < ncols; b += 64) ek += col_parts[b];
-  er = wave_sum(er);
-  ei = wave_sum(ei);
-  nr = wave_sum(nr);
-  ek = wave_sum(ek);
-  if (lane == 0) {
+#pragma unroll 4
+  for (int b = threadIdx.x; b < ncols; b += blockDim.x) ek += a.col_partials[b];
+  er = block_sum(er, red);
+  ei = block_sum(ei, red);
+  nr = block_sum(nr, red);
+  ek = block_sum(ek, red);
+  if (threadIdx.x == 0) {
+    const double w = a.dx * a.dy;
     const double nrm = w * nr;
-    out[0] = (w * inv_npts * ek + w * er) / nrm + w * ei * norm0 / (nrm * nrm);
+    out[0] = (w / (double(a.nx) * double(a.ny)) * ek + w * er) / nrm + w * ei * a.norm0 / (nrm * nrm);
   }
 }
 
-hipError_t launch_energy_finish(const EnergyArgs& a, double norm0, double* out, hipStream_t s) {
-  const double w = a.dx * a.dy;
-  const double inv_npts = 1.0 / (double(a.nx) * double(a.ny));
-  hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(64), 0, s, a.row_partials, a.ny / a.rows, a.col_partials,
-                     a.nx / a.cols, w, inv_npts, norm0, out);
+__global__ void __launch_bounds__(256) energy_finish_kernel(EnergyArgs a, double* __restrict__ out) {
+  energy_finish_body(a, out);
+}
+
+__global__ void __launch_bounds__(256) energy_finish_kernel_batch(const EnergyArgs* __restrict__ tab) {
+  const EnergyArgs a = tab[blockIdx.x];
+  energy_finish_body(a, a.result);
+}
+
+hipError_t launch_energy_finish(const EnergyArgs& a, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(256), 0, s, a, out);
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t launch_energy_row(const EnergyArgs& a, hipStream_t s) {
-  constexpr int T = N / (N >= 16 ? 16 : N);
+  constexpr int T = N / energy_points_c<N>();
   const dim3 grid(a.ny / a.rows), block(2 * T * a.rows);
   const size_t lds = energy_lds_bytes(N, a.rows);
   if (a.psi64) hipLaunchKernelGGL((energy_row_kernel<N, double4>), grid, block, lds, s, a);
@@ -265,7 +304,7 @@ hipError_t launch_energy_row(const EnergyArgs& a, hipStream_t s) {
 
 template <int N>
 hipError_t launch_energy_col(const EnergyArgs& a, hipStream_t s) {
-  constexpr int T = N / (N >= 16 ? 16 : N);
+  constexpr int T = N / energy_points_c<N>();
   const dim3 grid(a.nx / a.cols), block(2 * T * a.cols);
   const size_t lds = energy_lds_bytes(N, a.cols);
   if (a.psi64) hipLaunchKernelGGL((energy_col_kernel<N, double4>), grid, block, lds, s, a);
@@ -300,6 +339,54 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
     case 4096: return launch_energy_col<4096>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int N>
+hipError_t launch_energy_row_batch(const EnergyArgs* tab, int count, int ny, int rows, hipStream_t s) {
+  constexpr int T = N / energy_points_c<N>();
+  hipLaunchKernelGGL((energy_row_kernel_batch<N, float4>), dim3(ny / rows, count), dim3(2 * T * rows),
+                     energy_lds_bytes(N, rows), s, tab);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_energy_col_batch(const EnergyArgs* tab, int count, int nx, int cols, hipStream_t s) {
+  constexpr int T = N / energy_points_c<N>();
+  hipLaunchKernelGGL((energy_col_kernel_batch<N, float4>), dim3(nx / cols, count), dim3(2 * T * cols),
+                     energy_lds_bytes(N, cols), s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_batch(const EnergyArgs* tab, int count, int nx, int ny, int rows, int cols, hipStream_t s) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (nx) {
+    case 16: e = launch_energy_row_batch<16>(tab, count, ny, rows, s); break;
+    case 32: e = launch_energy_row_batch<32>(tab, count, ny, rows, s); break;
+    case 64: e = launch_energy_row_batch<64>(tab, count, ny, rows, s); break;
+    case 128: e = launch_energy_row_batch<128>(tab, count, ny, rows, s); break;
+    case 256: e = launch_energy_row_batch<256>(tab, count, ny, rows, s); break;
+    case 512: e = launch_energy_row_batch<512>(tab, count, ny, rows, s); break;
+    case 1024: e = launch_energy_row_batch<1024>(tab, count, ny, rows, s); break;
+    case 2048: e = launch_energy_row_batch<2048>(tab, count, ny, rows, s); break;
+    case 4096: e = launch_energy_row_batch<4096>(tab, count, ny, rows, s); break;
+    default: break;
+  }
+  if (e != hipSuccess) return e;
+  switch (ny) {
+    case 16: e = launch_energy_col_batch<16>(tab, count, nx, cols, s); break;
+    case 32: e = launch_energy_col_batch<32>(tab, count, nx, cols, s); break;
+    case 64: e = launch_energy_col_batch<64>(tab, count, nx, cols, s); break;
+    case 128: e = launch_energy_col_batch<128>(tab, count, nx, cols, s); break;
+    case 256: e = launch_energy_col_batch<256>(tab, count, nx, cols, s); break;
+    case 512: e = launch_energy_col_batch<512>(tab, count, nx, cols, s); break;
+    case 1024: e = launch_energy_col_batch<1024>(tab, count, nx, cols, s); break;
+    case 2048: e = launch_energy_col_batch<2048>(tab, count, nx, cols, s); break;
+    case 4096: e = launch_energy_col_batch<4096>(tab, count, nx, cols, s); break;
+    default: e = hipErrorInvalidValue; break;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(energy_finish_kernel_batch, dim3(count), dim3(256), 0, s, tab);
+  return hipGetLastError();
 }
 
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {

@@ -57,7 +57,7 @@ sgpe_status relax_buffers(sgpe_ctx* c) {
 // The energy check of the state as the stream leaves it, into ring slot `slot`.
 hipError_t enqueue_check(sgpe_ctx* c, const sgpe::EnergyArgs& a, int slot) {
   hipError_t e = sgpe::launch_energy(a, c->stream);
-  if (e == hipSuccess) e = sgpe::launch_energy_finish(a, c->p.norm0, c->relax_dev + slot, c->stream);
+  if (e == hipSuccess) e = sgpe::launch_energy_finish(a, c->relax_dev + slot, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->relax_host + slot, c->relax_dev + slot, sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipEventRecord(c->relax_ev[slot], c->stream);

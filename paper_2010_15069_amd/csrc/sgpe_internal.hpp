@@ -108,6 +108,8 @@ struct EnergyArgs {
   double* row_partials;      // kEnergyRowParts per row block: {linear real-space energy and the
                              //   rows' k_x terms, interaction energy, norm}
   double* col_partials;      // 1 per column block: its columns' k_y terms
+  double norm0;              // the norm the energy per particle refers to
+  double* result;            // batched launches: where the finishing kernel writes this energy
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -142,7 +144,11 @@ hipError_t launch_col_batch(const ColArgs& shape, const ColArgs* tab, int count,
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t s);
 // The energy per particle from the partials launch_energy wrote (a's buffers), combined on the
 // device in a fixed order and written to out (one double, device memory).
-hipError_t launch_energy_finish(const EnergyArgs& a, double norm0, double* out, hipStream_t s);
+hipError_t launch_energy_finish(const EnergyArgs& a, double* out, hipStream_t s);
+// The energies of `count` complex64 states of one grid shape, one launch per kernel: tab (device)
+// holds each state's arguments (rows and cols as energy_rows/cols_per_block give them for that
+// shape), and each energy is written to its tab[i].result.
+hipError_t launch_energy_batch(const EnergyArgs* tab, int count, int nx, int ny, int rows, int cols, hipStream_t s);
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 hipError_t launch_norm(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
 

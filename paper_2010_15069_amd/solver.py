@@ -281,6 +281,13 @@ class Batch:
         check(self._lib.sgpe_batch_energy(self._b, int(i), ctypes.byref(v)), "sgpe_batch_energy")
         return v.value
 
+    def energies(self):
+        """Every instance's energy per particle at once (sgpe_batch_energies), as a numpy array."""
+        out = np.empty(len(self), dtype=np.float64)
+        check(self._lib.sgpe_batch_energies(self._b, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              "sgpe_batch_energies")
+        return out
+
     def norm(self, i) -> float:
         v = ctypes.c_double()
         check(self._lib.sgpe_batch_norm(self._b, int(i), ctypes.byref(v)), "sgpe_batch_norm")

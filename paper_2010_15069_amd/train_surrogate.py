@@ -63,7 +63,7 @@ def steps_to_tolerance(params, starts, ref_steps, every=50, tol=1e-6):
     t0 = time.perf_counter()
     for k in range(ref_steps // every):
         b.step_imag(every)
-        trace.append([b.energy(i) for i in range(len(params))])
+        trace.append(b.energies())
         if (k + 1) % 100 == 0:
             log(f"  {(k + 1) * every}/{ref_steps} steps ({time.perf_counter() - t0:.0f} s)")
     b.close()

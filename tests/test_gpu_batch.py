@@ -125,6 +125,43 @@ def test_batch_sweep_instances_against_oracle(sgpe):
     b.close()
 
 
+def test_batch_energies_at_once_match_one_by_one(sgpe):
+    # every class (square and ragged grids, a spatial Raman coupling) in one launch per kernel
+    ps = mixed_params()
+    print("case: mixed batch of 6, energies() vs energy(i)", flush=True)
+    b = sgpe.Batch(ps)
+    with pytest.raises(sgpe.SgpeError, match="SGPE_ESTATE"):
+        b.energies()            # no state yet
+    for i, psi in enumerate(states(ps)):
+        b.set_psi(i, psi)
+    for n in (0, 15):
+        if n:
+            b.step_imag(n)
+        e_all = b.energies()
+        e_one = np.array([b.energy(i) for i in range(len(ps))])
+        np.testing.assert_allclose(e_all, e_one, rtol=1e-13, atol=0)
+    # the sweep workload's sizes, against the oracle
+    qs = sweep_instances(seed=4, sizes=(128, 256), per_size=3)
+    q0 = [initial_state(p, "tf", seed=i) for i, p in enumerate(qs)]
+    c = sgpe.Batch(qs)
+    for i, psi in enumerate(q0):
+        c.set_psi(i, psi)
+    e = c.energies()
+    for i in (0, 4):
+        o = OracleGPE(qs[i], workers=WORKERS)
+        o.set_psi(q0[i])
+        eo = o.energy()
+        assert abs(e[i] - eo) <= 1e-6 * abs(eo), i
+    # a non-finite instance: every value is written, the call reports it
+    bad = q0[1] * 1e20
+    c.set_psi(1, bad)
+    c.step_imag(2)
+    with pytest.raises(sgpe.SgpeError, match="SGPE_ENONFINITE"):
+        c.energies()
+    b.close()
+    c.close()
+
+
 def test_batch_errors(sgpe):
     ps = mixed_params()[:2]
     b = sgpe.Batch(ps)

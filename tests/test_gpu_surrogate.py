@@ -33,7 +33,7 @@ def _trace(params, starts, steps, every=50):
     tr = []
     for _ in range(steps // every):
         b.step_imag(every)
-        tr.append([b.energy(i) for i in range(len(params))])
+        tr.append(b.energies())
     b.close()
     return np.array(tr)
 

@@ -56,7 +56,7 @@ def test_spatial_raman_and_ragged_grid(env):
 
 
 def test_large_and_extreme_grids(env):
-    # the static array holds only partial sums (three per row, one per column block), so every grid
+    # the static array holds only partial sums (three per row block, one per column block), so every grid
     # the library accepts fits: a full-size 2048 x 1024 grid and a 4096-point axis
     torch, lib = env
     from paper_2010_15069_amd import Solver
