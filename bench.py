@@ -461,15 +461,16 @@ def exchange_floor():
     row or column, both components per lane)."""
     from paper_2010_15069_amd import probe_exchange
     out = []
-    for n in (512, 1024, 2048):
+    for n in (256, 512, 1024, 2048):
         configs = []
         for L, rt, ct in [(1, 1, 2), (1, 1, 4), (1, 1, 8), (2, 2, 2), (2, 2, 4), (4, 4, 1), (4, 4, 2),
                           (8, 8, 1)]:
             if 2 * rt * (n // 16) > 1024 or 2 * ct * (n // 16) > 1024:
                 continue
             configs.append((L, rt, ct, False))
-        for L, rt, ct in [(1, 1, 1), (1, 2, 4), (1, 4, 4), (4, 1, 1), (4, 4, 4), (8, 1, 1), (8, 2, 2), (8, 4, 4)]:
-            configs.append((L, rt, ct, True))
+        if n >= 512:   # a wave per line needs 512..2048 points
+            for L, rt, ct in [(1, 1, 1), (1, 2, 4), (1, 4, 4), (4, 1, 1), (4, 4, 4), (8, 1, 1), (8, 2, 2), (8, 4, 4)]:
+                configs.append((L, rt, ct, True))
         for L, rt, ct, wl in configs:
             for wt in (True, False):
                 r, c, pr = probe_exchange(n, n, L, rt, ct, wt, wl, reps=40)
