@@ -140,15 +140,37 @@ class SpectralConv2d(torch.nn.Module):
         return torch.fft.irfft2(out, s=(h, w))
 
 
+class Pointwise(torch.nn.Module):
+    """A 1x1 convolution (the same linear map at every grid point) computed as one channels-last
+    matrix product (B H W, cin) @ (cin, cout) + bias: a GEMM on the matrix cores under bfloat16
+    autocast, where the library's 1x1 convolution fell back to a slow direct kernel on this device
+    (~1 s of a 256-set prediction).  Parameters as a Conv2d(cin, cout, 1) holds them, (cout, cin,
+    1, 1) and (cout,), with its initialisation.  The output is an NCHW view of channels-last memory,
+    so the next pointwise layer reads it without a copy."""
+
+    def __init__(self, cin: int, cout: int):
+        super().__init__()
+        conv = torch.nn.Conv2d(cin, cout, 1)
+        self.weight = conv.weight
+        self.bias = conv.bias
+
+    def forward(self, u: torch.Tensor) -> torch.Tensor:
+        b, c, h, w = u.shape
+        x = u.permute(0, 2, 3, 1).reshape(b * h * w, c)
+        wt = self.weight.reshape(self.weight.shape[0], c).t().contiguous()
+        y = torch.addmm(self.bias, x, wt)
+        return y.reshape(b, h, w, -1).permute(0, 3, 1, 2)
+
+
 class FNO2d(torch.nn.Module):
     def __init__(self, width: int = 32, modes: int = 16, layers: int = 4):
         super().__init__()
         self.width, self.modes, self.layers = width, modes, layers
-        self.lift = torch.nn.Conv2d(IN_CHANNELS, width, 1)
+        self.lift = Pointwise(IN_CHANNELS, width)
         self.spectral = torch.nn.ModuleList([SpectralConv2d(width, width, modes) for _ in range(layers)])
-        self.pointwise = torch.nn.ModuleList([torch.nn.Conv2d(width, width, 1) for _ in range(layers)])
-        self.proj1 = torch.nn.Conv2d(width, 128, 1)
-        self.proj2 = torch.nn.Conv2d(128, 4, 1)
+        self.pointwise = torch.nn.ModuleList([Pointwise(width, width) for _ in range(layers)])
+        self.proj1 = Pointwise(width, 128)
+        self.proj2 = Pointwise(128, 4)
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
         dev = x.device.type
