@@ -19,9 +19,9 @@
 // not depend on where a group runs: the barrier counts the group's workgroups, whatever their XCD.
 //
 // The barrier: after a workgroup's __syncthreads, its first thread makes the workgroup's writes
-// visible device-wide (an agent-scope fence; the state stores go through the L2 as they are
+// visible device-wide (an agent-scope release fence; the state stores go through the L2 as they are
 // issued), adds one to its group's counter and waits until the counter reaches the phase's target,
-// then fences again so that its reads see every other workgroup's writes.  The wait is bounded:
+// then takes an agent-scope acquire fence so that its reads see every other workgroup's writes.  The wait is bounded:
 // after spin_limit polls a workgroup gives up, sets an abort word that every waiting workgroup also
 // polls, records the failure in host-visible memory and returns; every workgroup then leaves at its
 // next barrier, and the host reports SGPE_EDEVICE.  A small kernel zeroes the counters and the abort
@@ -56,10 +56,12 @@ __device__ __forceinline__ bool persist_barrier(const PersistArgs& a, unsigned n
     const unsigned grp = blockIdx.x % kPersistGroups;
     const unsigned members = (gridDim.x - grp + kPersistGroups - 1) / kPersistGroups;
     unsigned* count = a.barrier + kPersistWordStride * grp;
-    __threadfence();
+    // release before arriving, acquire after the wait: on this part an agent-scope release is an L2
+    // write-back and an acquire an L2 invalidate, so a full fence on both sides would do each twice
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool ok = persist_wait(a, count, members * nb);
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok_s = ok ? 1 : 0;
   }
   __syncthreads();
