@@ -56,7 +56,7 @@ int col_default_cols(int nx, int ny, int points, size_t max_lds) {
 // than keeps ~256 workgroups on the grid (small grids are latency-bound: more workgroups, each
 // shorter).  Both kernels interleave their transforms in LDS slot by slot, N + N/16 double2 slots
 // each.
-int energy_points(int n) { return n >= 1024 ? 16 : 8; }
+__host__ __device__ constexpr int energy_points(int n) { return n >= 1024 ? 16 : 8; }
 
 size_t energy_lds_bytes(int n, int lines) { return size_t(2) * lines * size_t(n + n / 16) * 16; }
 
@@ -91,13 +91,12 @@ int norm_blocks() { return 256; }
 //   * the uniform Raman term Omega Re(u^* d^) of H_K: N times its real-space sum, so it joins the
 //     spatial Raman term Omega(r) Re(u* d) of the real-space energy.
 // Row kernel: the real-space terms, the norm and the rows' k_x terms; column kernel: the columns'
-// k_y terms.  The DFTs are the step kernels' register-resident forward transform (fwd_pass: radix-16
+// k_y terms.  The DFTs are the step kernels' register-resident forward transform (fwd_pass: radix-P
 // stages exchanged through LDS, natural order in and out) instantiated in fp64 with the roots
 // rounded once to fp64, on the state widened to fp64 as it is loaded, so the energy of a complex64
 // state carries no transform error of its own.  Each lane holds one component of one line.  The
-// partials are scaled so that the
-// host's combination reads E = (w / N ek + w er) / norm + w ei norm0 / norm^2 (w = dx dy,
-// N = nx ny), as for a 2-D sum.
+// partials are scaled so that their combination reads E = (w / N ek + w er) / norm
+// + w ei norm0 / norm^2 (w = dx dy, N = nx ny), as for a 2-D sum.
 // -------------------------------------------------------------------------------------------
 extern __shared__ __align__(16) unsigned char energy_lds[];
 
@@ -126,13 +125,10 @@ __device__ __forceinline__ double4 energy_point(const EnergyArgs& a, size_t i) {
   }
 }
 
-template <int N>
-constexpr int energy_points_c() { return N >= 1024 ? 16 : 8; }
-
 // Rows block*rows .. block*rows + rows - 1 of the state a describes.
 template <int N, class Q>
 __device__ __forceinline__ void energy_row_body(const EnergyArgs& a, int block) {
-  constexpr int P = energy_points_c<N>();
+  constexpr int P = energy_points(N);
   constexpr int T = N / P;
   __shared__ double red[64];
   const int tid = threadIdx.x, comp = tid & 1, pair = tid >> 1;
@@ -200,7 +196,7 @@ __global__ void __launch_bounds__(512) energy_row_kernel_batch(const EnergyArgs*
 // pass spreads its tiles).
 template <int N, class Q>
 __device__ __forceinline__ void energy_col_body(const EnergyArgs& a, int block) {
-  constexpr int P = energy_points_c<N>();
+  constexpr int P = energy_points(N);
   constexpr int T = N / P;
   __shared__ double red[64];
   const int C = a.cols;
@@ -294,7 +290,7 @@ hipError_t launch_energy_finish(const EnergyArgs& a, double* out, hipStream_t s)
 
 template <int N>
 hipError_t launch_energy_row(const EnergyArgs& a, hipStream_t s) {
-  constexpr int T = N / energy_points_c<N>();
+  constexpr int T = N / energy_points(N);
   const dim3 grid(a.ny / a.rows), block(2 * T * a.rows);
   const size_t lds = energy_lds_bytes(N, a.rows);
   if (a.psi64) hipLaunchKernelGGL((energy_row_kernel<N, double4>), grid, block, lds, s, a);
@@ -304,7 +300,7 @@ hipError_t launch_energy_row(const EnergyArgs& a, hipStream_t s) {
 
 template <int N>
 hipError_t launch_energy_col(const EnergyArgs& a, hipStream_t s) {
-  constexpr int T = N / energy_points_c<N>();
+  constexpr int T = N / energy_points(N);
   const dim3 grid(a.nx / a.cols), block(2 * T * a.cols);
   const size_t lds = energy_lds_bytes(N, a.cols);
   if (a.psi64) hipLaunchKernelGGL((energy_col_kernel<N, double4>), grid, block, lds, s, a);
@@ -343,7 +339,7 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t s) {
 
 template <int N>
 hipError_t launch_energy_row_batch(const EnergyArgs* tab, int count, int ny, int rows, hipStream_t s) {
-  constexpr int T = N / energy_points_c<N>();
+  constexpr int T = N / energy_points(N);
   hipLaunchKernelGGL((energy_row_kernel_batch<N, float4>), dim3(ny / rows, count), dim3(2 * T * rows),
                      energy_lds_bytes(N, rows), s, tab);
   return hipGetLastError();
@@ -351,7 +347,7 @@ hipError_t launch_energy_row_batch(const EnergyArgs* tab, int count, int ny, int
 
 template <int N>
 hipError_t launch_energy_col_batch(const EnergyArgs* tab, int count, int nx, int cols, hipStream_t s) {
-  constexpr int T = N / energy_points_c<N>();
+  constexpr int T = N / energy_points(N);
   hipLaunchKernelGGL((energy_col_kernel_batch<N, float4>), dim3(nx / cols, count), dim3(2 * T * cols),
                      energy_lds_bytes(N, cols), s, tab);
   return hipGetLastError();
