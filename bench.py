@@ -229,7 +229,9 @@ def _load_surrogate(torch):
     model = surrogate.load(WEIGHTS, "cuda")
     # warm-up at the batch sizes used below (library plans and kernel choices are per shape)
     for count in (1, 64):
-        surrogate.predict(model, sweep_instances(seed=3, sizes=(256,), per_size=count), "cuda")
+        qs = sweep_instances(seed=3, sizes=(256,), per_size=count)
+        surrogate.predict(model, qs, "cuda")
+        surrogate.predict_device(model, qs, "cuda")
     torch.cuda.synchronize()
     return model
 
@@ -291,8 +293,9 @@ def _aitken_estimate(trace, spacing=5000):
 
 def ground_state_learned(torch, stream, model, check_every=50, max_steps=200000):
     """The ground-state time-to-solution of the same workload from the learned start: the timed
-    region holds the input encoding, the network's forward pass, set_psi and the checked steps
-    (one sgpe_relax_imag call, check 0 being the predicted state itself)."""
+    region holds the input encoding, the network's forward pass, the state handed to the solver on
+    the device (sgpe_set_psi_device) and the checked steps (one sgpe_relax_imag call, check 0 being
+    the predicted state itself)."""
     from paper_2010_15069_amd import Solver, surrogate
     from workloads import initial_state, preset
     ref = json.load(open(os.path.join(ROOT, "tests", "golden", "ground_energy.json")))
@@ -303,9 +306,9 @@ def ground_state_learned(torch, stream, model, check_every=50, max_steps=200000)
     s.relax_imag(check_every=check_every, max_steps=2 * check_every, rule="delta", tol=0.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    psi0 = surrogate.predict(model, [p], "cuda")[0]
+    psi0 = surrogate.predict_device(model, [p], "cuda")[0]     # stays on the device
     t_inf = time.perf_counter() - t0
-    s.set_psi(psi0)
+    s.set_psi_device(psi0)
     r = s.relax_imag(check_every=check_every, max_steps=max_steps, target=e_ref, tol=1e-6)
     el = time.perf_counter() - t0
     s.close()
@@ -324,12 +327,15 @@ def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_ever
     from workloads import initial_state, sweep_instances
     ps = sweep_instances(seed=2, sizes=(256,), per_size=n_sets)
 
-    def arm(starts_fn):
+    def arm(starts_fn, on_device=False):
         b = Batch(ps, stream=stream.cuda_stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, psi in enumerate(starts_fn()):
-            b.set_psi(i, psi)
+            if on_device:
+                b.set_psi_device(i, psi)
+            else:
+                b.set_psi(i, psi)
         trace, clock = [], []
         for _ in range(steps // check_every):
             b.step_imag(check_every)
@@ -339,7 +345,7 @@ def learned_start_sweep(torch, stream, model, n_sets=64, steps=60000, check_ever
         return np.array(trace), np.array(clock)
 
     tr_p, ck_p = arm(lambda: [initial_state(p, "tf", seed=10000 + i) for i, p in enumerate(ps)])
-    tr_l, ck_l = arm(lambda: surrogate.predict(model, ps, "cuda"))
+    tr_l, ck_l = arm(lambda: surrogate.predict_device(model, ps, "cuda"), on_device=True)
     e_ref = np.minimum(tr_p[-1], tr_l[-1])
 
     def first(trace, clock):

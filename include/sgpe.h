@@ -122,6 +122,16 @@ void sgpe_destroy(sgpe_ctx* ctx);
  * unchanged). */
 sgpe_status sgpe_set_psi(sgpe_ctx* ctx, const double* psi_host);
 
+/* sgpe_set_psi from device memory: the order parameter (Psi_up, Psi_down) of Sec. 3.1 on the grid
+ * of Sec. 3.2, already in the context's own device layout -- [ny][nx] of {re_up, im_up, re_dn,
+ * im_dn}, float32 for SGPE_C64 and float64 for SGPE_C128 (16 * nx * ny or 32 * nx * ny bytes),
+ * 16-byte aligned, on the context's device.  The caller keeps ownership and must have finished
+ * writing it (its producer ordered before this call).  The values are checked on the device first
+ * (one pass counting non-finite values), then copied into the state as they are; nothing is rounded
+ * or rescaled.  Synchronises.  Clears a latched status.  Errors: SGPE_EINVAL (NULL or misaligned),
+ * SGPE_ENONFINITE (a NaN/Inf; the state is unchanged), SGPE_EDEVICE. */
+sgpe_status sgpe_set_psi_device(sgpe_ctx* ctx, const void* psi_dev);
+
 /* Copy the order parameter (Sec. 3.1) out in the layout of sgpe_set_psi, into the caller's
  * array of 4 * nx * ny doubles.  Synchronises the stream.  Errors: SGPE_EINVAL (NULL), SGPE_ESTATE
  * (no state), SGPE_ENONFINITE (a non-finite value in the state, or a latched status; the values
@@ -379,9 +389,10 @@ sgpe_status sgpe_batch_class_info(const sgpe_batch* batch, int32_t k, int32_t* n
 /* the class of instance `index` */
 sgpe_status sgpe_batch_instance_class(const sgpe_batch* batch, int32_t index, int32_t* k);
 
-/* Per instance, as sgpe_set_psi / sgpe_get_psi / sgpe_energy / sgpe_norm (index out of range:
- * SGPE_EINVAL). */
+/* Per instance, as sgpe_set_psi / sgpe_set_psi_device / sgpe_get_psi / sgpe_energy / sgpe_norm
+ * (index out of range: SGPE_EINVAL). */
 sgpe_status sgpe_batch_set_psi(sgpe_batch* batch, int32_t index, const double* psi);
+sgpe_status sgpe_batch_set_psi_device(sgpe_batch* batch, int32_t index, const void* psi_dev);
 sgpe_status sgpe_batch_get_psi(sgpe_batch* batch, int32_t index, double* psi);
 sgpe_status sgpe_batch_energy(sgpe_batch* batch, int32_t index, double* e_per_particle);
 sgpe_status sgpe_batch_norm(sgpe_batch* batch, int32_t index, double* norm);

@@ -73,7 +73,8 @@ EXPORTS = [
     "sgpe_batch_set_schedule", "sgpe_batch_autotune", "sgpe_batch_use_persistent",
     "sgpe_set_raman_profile", "sgpe_add_noise", "sgpe_phase_separation", "sgpe_population_radius",
     "sgpe_winding", "sgpe_set_splitting", "sgpe_create_ex", "sgpe_probe_exchange", "sgpe_energy_noalloc",
-    "sgpe_probe_placement", "sgpe_relax_imag", "sgpe_batch_energies",
+    "sgpe_probe_placement", "sgpe_relax_imag", "sgpe_batch_energies", "sgpe_set_psi_device",
+    "sgpe_batch_set_psi_device",
 ]
 
 
@@ -173,6 +174,8 @@ def _lib():
         "sgpe_relax_imag": ([vp, ctypes.c_int64, ctypes.c_int64, i32, ctypes.c_double, ctypes.c_double,
                              P(ctypes.c_double), ctypes.c_int64, P(RelaxResult)], st),
         "sgpe_batch_energies": ([vp, P(ctypes.c_double)], st),
+        "sgpe_set_psi_device": ([vp, vp], st),
+        "sgpe_batch_set_psi_device": ([vp, i32, vp], st),
     })
     for name, (args, res) in batch_sigs.items():
         f = getattr(lib, name)

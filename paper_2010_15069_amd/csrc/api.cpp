@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <type_traits>
 #include <cstring>
 #include <new>
@@ -876,6 +877,36 @@ sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {
   c->has_state = true;
   c->latched = SGPE_OK;
   if (c->status_host) __atomic_store_n(c->status_host, 0u, __ATOMIC_RELEASE);   // the stream is idle
+  return SGPE_OK;
+}
+
+sgpe_status sgpe_set_psi_device(sgpe_ctx* c, const void* d) {
+  sgpe_status st = check_ctx(c);
+  if (st != SGPE_OK) return st;
+  if (!d || reinterpret_cast<uintptr_t>(d) % 16 != 0) return SGPE_EINVAL;
+  const long long npts = (long long)c->p.nx * c->p.ny;
+  const int nb = sgpe::norm_blocks();
+  const bool c128 = c->prec == SGPE_C128;
+  hipError_t e = c128 ? sgpe::launch_nonfinite(static_cast<const double4*>(d), npts, c->npart, nb, c->stream)
+                      : sgpe::launch_nonfinite(static_cast<const float4*>(d), npts, c->npart, nb, c->stream);
+  if (e != hipSuccess) return status_of(e);
+  const double* part = nullptr;
+  if ((st = fetch_partials(c, c->npart, size_t(nb), &part)) != SGPE_OK) return st;   // synchronises
+  double bad = 0.0;
+  for (int b = 0; b < nb; ++b) bad += part[b];
+  if (bad != 0.0) return SGPE_ENONFINITE;   // the state is unchanged
+  // the stream is idle: no step kernel can set the status word any more
+  if (c->status_host) __atomic_store_n(c->status_host, 0u, __ATOMIC_RELEASE);
+  void* dst = c128 ? static_cast<void*>(c->psi64) : static_cast<void*>(c->psi);
+  const size_t bytes = size_t(npts) * (c128 ? sizeof(double4) : sizeof(float4));
+  e = dst == d ? hipSuccess : hipMemcpyAsync(dst, d, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return SGPE_EDEVICE;
+  }
+  c->has_state = true;
+  c->latched = SGPE_OK;
   return SGPE_OK;
 }
 

@@ -404,6 +404,11 @@ sgpe_status sgpe_batch_set_psi(sgpe_batch* b, int32_t index, const double* psi) 
   return sgpe_set_psi(b->inst[index], psi);
 }
 
+sgpe_status sgpe_batch_set_psi_device(sgpe_batch* b, int32_t index, const void* psi_dev) {
+  if (!valid_index(b, index)) return SGPE_EINVAL;
+  return sgpe_set_psi_device(b->inst[index], psi_dev);
+}
+
 sgpe_status sgpe_batch_get_psi(sgpe_batch* b, int32_t index, double* psi) {
   if (!valid_index(b, index)) return SGPE_EINVAL;
   return sgpe_get_psi(b->inst[index], psi);

@@ -69,6 +69,13 @@ struct sgpe_ctx {
   hipEvent_t relax_ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+namespace sgpe {
+// Per workgroup of nblocks (sgpe::norm_blocks()), the count of points of psi (npts, device memory)
+// with a non-finite value, as doubles in partials.
+hipError_t launch_nonfinite(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+hipError_t launch_nonfinite(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s);
+}  // namespace sgpe
+
 namespace sgpe_host {
 
 constexpr int kMaxPartials = 4096;   // norm partials per column pass (one per workgroup)

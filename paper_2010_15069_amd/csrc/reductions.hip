@@ -385,6 +385,31 @@ hipError_t launch_energy_batch(const EnergyArgs* tab, int count, int nx, int ny,
   return hipGetLastError();
 }
 
+// Count of non-finite values per workgroup (as doubles, in the norm's partial buffer): the check of a
+// state handed over in device memory.
+template <class Q>
+__global__ void __launch_bounds__(256) nonfinite_kernel(const Q* __restrict__ psi, long long n,
+                                                        double* __restrict__ partials) {
+  __shared__ double red[64];
+  double bad = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const Q w = psi[i];
+    bad += (isfinite(w.x) && isfinite(w.y) && isfinite(w.z) && isfinite(w.w)) ? 0.0 : 1.0;
+  }
+  const double s = block_sum(bad, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+hipError_t launch_nonfinite(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel<float4>, dim3(nblocks), dim3(256), 0, s, psi, npts, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const double4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel<double4>, dim3(nblocks), dim3(256), 0, s, psi, npts, partials);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm(const float4* psi, long long npts, double* partials, int nblocks, hipStream_t s) {
   hipLaunchKernelGGL(norm_kernel<float4>, dim3(nblocks), dim3(256), 0, s, psi, npts, partials);
   return hipGetLastError();

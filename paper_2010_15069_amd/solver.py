@@ -62,6 +62,17 @@ class Solver:
         check(self._lib.sgpe_set_psi(self._ctx, a.ctypes.data_as(ctypes.c_void_p)), "sgpe_set_psi")
         return self
 
+    def set_psi_device(self, t):
+        """The state from a device tensor in the context's own layout (sgpe_set_psi_device): shape
+        (ny, nx, 4) of (re_up, im_up, re_dn, im_dn), float32 (complex64 context) or float64
+        (complex128), contiguous.  The tensor's current stream is synchronised first, so whatever
+        produced it has finished."""
+        _check_device_state(t, self.ny, self.nx, self.precision)
+        import torch
+        torch.cuda.current_stream(t.device).synchronize()
+        check(self._lib.sgpe_set_psi_device(self._ctx, ctypes.c_void_p(t.data_ptr())), "sgpe_set_psi_device")
+        return self
+
     def get_psi(self):
         out = np.empty((2, self.ny, self.nx), dtype=np.complex128)
         check(self._lib.sgpe_get_psi(self._ctx, out.ctypes.data_as(ctypes.c_void_p)), "sgpe_get_psi")
@@ -257,6 +268,16 @@ class Batch:
         check(self._lib.sgpe_batch_set_psi(self._b, int(i), a.ctypes.data_as(ctypes.c_void_p)), "sgpe_batch_set_psi")
         return self
 
+    def set_psi_device(self, i, t):
+        """Instance i's state from a device tensor, as Solver.set_psi_device (complex64)."""
+        ny, nx = self._shapes[i]
+        _check_device_state(t, ny, nx, "c64")
+        import torch
+        torch.cuda.current_stream(t.device).synchronize()
+        check(self._lib.sgpe_batch_set_psi_device(self._b, int(i), ctypes.c_void_p(t.data_ptr())),
+              "sgpe_batch_set_psi_device")
+        return self
+
     def get_psi(self, i):
         ny, nx = self._shapes[i]
         out = np.empty((2, ny, nx), dtype=np.complex128)
@@ -327,6 +348,14 @@ class Batch:
         ms = (ctypes.c_double * max(1, len(self.classes())))()
         check(self._lib.sgpe_batch_autotune(self._b, int(steps), ms), "sgpe_batch_autotune")
         return list(ms)
+
+
+def _check_device_state(t, ny, nx, precision):
+    import torch
+    want = torch.float64 if precision == "c128" else torch.float32
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.is_contiguous()
+            and tuple(t.shape) == (ny, nx, 4)):
+        raise ValueError(f"expected a contiguous {want} device tensor of shape ({ny}, {nx}, 4)")
 
 
 def device_count() -> int:

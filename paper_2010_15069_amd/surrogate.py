@@ -263,3 +263,16 @@ def predict(model: FNO2d, params_list, device) -> list:
     """Initial states (complex128, normalised) for a list of same-grid parameter sets."""
     with torch.no_grad():
         return to_psi(model(encode_on(params_list, device)), params_list)
+
+
+def predict_device(model: FNO2d, params_list, device) -> torch.Tensor:
+    """Initial states for a list of same-grid parameter sets, left on the device in the solver's
+    complex64 layout: (B, ny, nx, 4) float32 of (re_up, im_up, re_dn, im_dn), each set normalised to
+    its norm0 (the sum in fp64).  For Solver.set_psi_device / Batch.set_psi_device."""
+    with torch.no_grad():
+        out = model(encode_on(params_list, device)).float()          # (B, 4, ny, nx)
+        _, _, dx, dy = grid_axes(params_list[0])
+        nrm = (out.double() ** 2).sum(dim=(1, 2, 3)) * (dx * dy)
+        norm0 = torch.tensor([p.norm0 for p in params_list], dtype=torch.float64, device=out.device)
+        scale = torch.sqrt(norm0 / nrm.clamp_min(1e-300)).float()
+        return (out * scale[:, None, None, None]).permute(0, 2, 3, 1).contiguous()

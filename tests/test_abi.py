@@ -185,6 +185,8 @@ def test_new_entry_points_reject_null_and_invalid_arguments(lib):
     from paper_2010_15069_amd._lib import RelaxResult
     res = RelaxResult()
     assert lib.sgpe_relax_imag(None, 50, 100, 0, -1.0, 1e-6, None, 0, ctypes.byref(res)) == 1
+    assert lib.sgpe_set_psi_device(None, None) == 1
+    assert lib.sgpe_batch_set_psi_device(None, 0, None) == 1
 
 
 def test_header_documents_precision_and_splitting_enums():
@@ -207,7 +209,7 @@ def _comment_before(decl_name):
                                   "sgpe_step_real", "sgpe_step_imag", "sgpe_energy", "sgpe_norm",
                                   "sgpe_synchronize", "sgpe_set_splitting", "sgpe_set_raman_profile",
                                   "sgpe_add_noise", "sgpe_phase_separation", "sgpe_winding",
-                                  "sgpe_relax_imag"])
+                                  "sgpe_relax_imag", "sgpe_set_psi_device"])
 def test_boundary_calls_cite_the_paper(name):
     # every call of the solver boundary names the passage that defines what it computes
     doc = _comment_before(name)
