@@ -125,8 +125,9 @@ sgpe_status sgpe_set_psi(sgpe_ctx* ctx, const double* psi_host);
 /* sgpe_set_psi from device memory: the order parameter (Psi_up, Psi_down) of Sec. 3.1 on the grid
  * of Sec. 3.2, already in the context's own device layout -- [ny][nx] of {re_up, im_up, re_dn,
  * im_dn}, float32 for SGPE_C64 and float64 for SGPE_C128 (16 * nx * ny or 32 * nx * ny bytes),
- * 16-byte aligned, on the context's device.  The caller keeps ownership and must have finished
- * writing it (its producer ordered before this call).  The values are checked on the device first
+ * 16-byte aligned, on the context's device, and either the context's own state buffer or disjoint
+ * from it.  The caller keeps ownership and must have finished writing it (its producer ordered
+ * before this call).  The values are checked on the device first
  * (one pass counting non-finite values), then copied into the state as they are; nothing is rounded
  * or rescaled.  Synchronises.  Clears a latched status.  Errors: SGPE_EINVAL (NULL or misaligned),
  * SGPE_ENONFINITE (a NaN/Inf; the state is unchanged), SGPE_EDEVICE. */
