@@ -193,9 +193,9 @@ typedef struct sgpe_relax_result {
  * with energies_cap = 0) receives the energy of check k at index k for k < energies_cap.
  * Synchronises before returning.  The ring of checks in flight (4 device doubles, their pinned host
  * copies and 4 events) is allocated on the first call and kept by the context.
- * Errors: SGPE_EINVAL (NULL out, check_every < 1, max_steps < 0, tol negative or not finite, an
- * unknown rule, a non-finite target with SGPE_RELAX_TARGET, energies NULL with energies_cap > 0,
- * energies_cap < 0), SGPE_ESTATE (no state), SGPE_ENOMEM, SGPE_EDEVICE, SGPE_ENONFINITE (a check's
+ * Errors: SGPE_EINVAL (NULL out, check_every < 1, max_steps < 0, either above 2^61, tol negative
+ * or not finite, an unknown rule, a non-finite target with SGPE_RELAX_TARGET, energies NULL with
+ * energies_cap > 0, energies_cap < 0), SGPE_ESTATE (no state), SGPE_ENOMEM, SGPE_EDEVICE, SGPE_ENONFINITE (a check's
  * energy, or an imaginary-time norm, not finite: the call stops there and out holds that check). */
 sgpe_status sgpe_relax_imag(sgpe_ctx* ctx, int64_t check_every, int64_t max_steps, int32_t rule, double target,
                             double tol, double* energies, int64_t energies_cap, sgpe_relax_result* out);

@@ -71,7 +71,10 @@ extern "C" sgpe_status sgpe_relax_imag(sgpe_ctx* c, int64_t check_every, int64_t
                                        sgpe_relax_result* out) {
   sgpe_status st = sgpe_host::check_ctx(c);
   if (st != SGPE_OK) return st;
-  if (!out || check_every < 1 || max_steps < 0 || !std::isfinite(tol) || tol < 0.0 || energies_cap < 0 ||
+  // (k check_every stays below 2^63 for every check k up to max_steps / check_every + 1)
+  constexpr int64_t kMaxCount = int64_t(1) << 61;
+  if (!out || check_every < 1 || max_steps < 0 || check_every > kMaxCount || max_steps > kMaxCount ||
+      !std::isfinite(tol) || tol < 0.0 || energies_cap < 0 ||
       (energies_cap > 0 && !energies) || (rule != SGPE_RELAX_TARGET && rule != SGPE_RELAX_DELTA) ||
       (rule == SGPE_RELAX_TARGET && !std::isfinite(target)))
     return SGPE_EINVAL;

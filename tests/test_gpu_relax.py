@@ -113,6 +113,8 @@ def test_invalid_arguments(api):
     e = (ctypes.c_double * 4)()
     bad = [(0, 100, 1, 0.0, 0.0, None, 0, ctypes.byref(res)),            # check_every < 1
            (10, -1, 1, 0.0, 0.0, None, 0, ctypes.byref(res)),            # max_steps < 0
+           (1 << 62, 100, 1, 0.0, 0.0, None, 0, ctypes.byref(res)),      # check_every above 2^61
+           (10, 1 << 62, 1, 0.0, 0.0, None, 0, ctypes.byref(res)),       # max_steps above 2^61
            (10, 100, 2, 0.0, 0.0, None, 0, ctypes.byref(res)),           # unknown rule
            (10, 100, 0, float("nan"), 1e-6, None, 0, ctypes.byref(res)),  # target not finite
            (10, 100, 1, 0.0, -1.0, None, 0, ctypes.byref(res)),          # tol < 0
