@@ -622,9 +622,12 @@ def main():
         # sweeps (2K + 2 sweeps for K steps); no spread to report
         "step_ms_median": med, "step_ms_mad": mad if len(per) > 1 else None,
         "timed_calls": len(per),
-        "note": f"the timed region is {len(per)} step_imag call(s) of at most {args.batch} steps; each call runs "
-                f"2n + 2 sweeps for n steps (the first x transform with half K, and the last inverse x "
-                f"transform, belong to the call)",
+        "note": f"the timed region is {len(per)} step_imag call(s) of at most {args.batch} steps, after the "
+                f"untimed warm-up call; consecutive calls continue one fused schedule: each call leaves its "
+                f"last half-step (K(dt/2) and the inverse x transform) to the next call, whose first sweep "
+                f"merges it with its own first K(dt/2), so the timed calls run 2 sweeps per step; the first "
+                f"timed sweep completes the warm-up's pending half-step, and the one the last timed call "
+                f"leaves is completed after the timed region (by the energy read)",
         "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts * value / (HBM_PEAK_GBS * 1e9),
         "steady_state": {"step_ms": steady_ms, "split_steps_per_s": 1e3 / steady_ms,
                          "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts / (steady_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),

@@ -141,7 +141,15 @@ sgpe_status sgpe_get_psi(sgpe_ctx* ctx, double* psi_host);
 
 /* Advance n >= 0 real-time steps (Sec. 3.2).  Asynchronous on the context's stream.  The
  * fused schedule is K(dt/2) [R(dt) K(dt)]^(n-1) R(dt) K(dt/2); its result equals n separate
- * K(dt/2) R(dt) K(dt/2) steps up to rounding.  Errors: SGPE_EINVAL (n < 0), SGPE_ESTATE. */
+ * K(dt/2) R(dt) K(dt/2) steps up to rounding.  Consecutive calls continue one schedule: on a
+ * complex64 context with the default splitting and a state it allocated itself, a call leaves its
+ * last K(dt/2) and inverse x-transform pending, and the next step call of the same kind merges them
+ * with its own first K(dt/2), so calls of n1 and n2 steps give bit for bit what one call of
+ * n1 + n2 steps gives.  Every other call on the context (get_psi, energy, norm, the observables,
+ * synchronize, a step of the other kind, a schedule or splitting change, ...) completes the
+ * pending half-step first, so no caller sees the difference.  A context on a caller's state buffer
+ * (psi_dev at create) completes every call, so the buffer always holds the documented layout.
+ * Errors: SGPE_EINVAL (n < 0), SGPE_ESTATE. */
 sgpe_status sgpe_step_real(sgpe_ctx* ctx, int64_t n);
 
 /* Advance n >= 0 imaginary-time steps, rescaling the total norm to norm0 after each one

@@ -382,15 +382,33 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
   hipStream_t s = c->stream;
   hipError_t e;
   RowArgs ra = row_args(c);
-  e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_iters, c->row_points, s);
+  // A tail of the other kind (or any tail before a timed profile) completes first.  A tail of this
+  // kind continues: the merged K(dt) below completes the previous call's last step and begins this
+  // call's first, exactly as inside one call (in imaginary time its NORM_DOT partials give the
+  // norm at that step boundary, and the first row pass rescales by it).
+  const int kind = imag ? 2 : 1;
+  if (c->tail_pending != 0 && (c->tail_pending != kind || ev)) {
+    const sgpe_status st = flush_tail(c);
+    if (st != SGPE_OK) return st;
+  }
+  const bool cont = c->tail_pending == kind;
+  c->tail_pending = 0;
+  if (cont) {
+    e = sgpe::launch_col(col_args(c, imag, false), imag ? sgpe::NORM_DOT : sgpe::NORM_NONE, c->col_iters,
+                         c->col_points, s);
+  } else {
+    e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_iters, c->row_points, s);
+    if (e == hipSuccess)
+      e = sgpe::launch_col(col_args(c, imag, true), sgpe::NORM_NONE, c->col_iters, c->col_points, s);
+  }
   if (e != hipSuccess) return status_of(e);
-  e = sgpe::launch_col(col_args(c, imag, true), sgpe::NORM_NONE, c->col_iters, c->col_points, s);
-  if (e != hipSuccess) return status_of(e);
+  // a context on a caller's state buffer, and a timed profile, complete every call
+  const bool defer = c->own_psi && !ev;
   size_t evi = 0;
   for (int64_t i = 1; i <= n; ++i) {
     RowArgs r = ra;
     r.scale = inv_n;
-    if (imag && i > 1) {
+    if (imag && (i > 1 || cont)) {
       r.partials = c->partials;
       r.n_partials = col_groups(c);
     }
@@ -399,10 +417,15 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
     if (e != hipSuccess) return status_of(e);
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
     const bool last = (i == n);
+    if (last && defer) break;   // the last K(dt/2) and the inverse x-transform wait (flush_tail)
     const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
     e = sgpe::launch_col(col_args(c, imag, last), nm, c->col_iters, c->col_points, s);
     if (e != hipSuccess) return status_of(e);
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
+  }
+  if (defer) {
+    c->tail_pending = kind;
+    return SGPE_OK;
   }
   RowArgs r = ra;
   r.scale = inv_n;
@@ -411,6 +434,26 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
     r.n_partials = col_groups(c);
   }
   e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_iters, c->row_points, s);
+  return status_of(e);
+}
+
+// The tail a step call of the default schedule left: the last step's K(dt/2) (with the
+// imaginary-time norm partials of the finished step) and the inverse x-transform (with its
+// rescaling), exactly as the call would have ended.
+sgpe_status flush_tail(sgpe_ctx* c) {
+  if (c->tail_pending == 0) return SGPE_OK;
+  const bool imag = c->tail_pending == 2;
+  c->tail_pending = 0;
+  hipError_t e = sgpe::launch_col(col_args(c, imag, true), imag ? sgpe::NORM_SQ : sgpe::NORM_NONE, c->col_iters,
+                                  c->col_points, c->stream);
+  if (e != hipSuccess) return status_of(e);
+  RowArgs r = row_args(c);
+  r.scale = float(1.0 / (double(c->p.nx) * double(c->p.ny)));
+  if (imag) {
+    r.partials = c->partials;
+    r.n_partials = col_groups(c);
+  }
+  e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_iters, c->row_points, c->stream);
   return status_of(e);
 }
 
@@ -526,13 +569,18 @@ EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_part
   return a;
 }
 
-sgpe_status check_ctx(sgpe_ctx* c) {
+sgpe_status check_ctx_no_flush(sgpe_ctx* c) {
   if (!c) return SGPE_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) {
     (void)hipGetLastError();
     return SGPE_EDEVICE;
   }
   return SGPE_OK;
+}
+
+sgpe_status check_ctx(sgpe_ctx* c) {
+  const sgpe_status st = check_ctx_no_flush(c);
+  return st != SGPE_OK ? st : flush_tail(c);
 }
 
 sgpe_status latched_status(sgpe_ctx* c) {
@@ -812,6 +860,7 @@ void sgpe_destroy(sgpe_ctx* c) {
 
 sgpe_status sgpe_set_col_tile(sgpe_ctx* c, int32_t columns) {
   if (!c || c->prec == SGPE_C128) return SGPE_EINVAL;
+  if (const sgpe_status st = check_ctx(c); st != SGPE_OK) return st;   // the pending tail, old schedule
   if (columns == 0) {
     default_schedule(c);
     return SGPE_OK;
@@ -834,6 +883,7 @@ sgpe_status sgpe_get_schedule(sgpe_ctx* c, sgpe_schedule* out) {
 
 sgpe_status sgpe_set_schedule(sgpe_ctx* c, const sgpe_schedule* s) {
   if (!c) return SGPE_EINVAL;
+  if (const sgpe_status st = check_ctx(c); st != SGPE_OK) return st;   // the pending tail, old schedule
   if (c->prec == SGPE_C128) {
     if (!s) {
       default_schedule_c128(c);
@@ -849,7 +899,7 @@ sgpe_status sgpe_set_schedule(sgpe_ctx* c, const sgpe_schedule* s) {
 }
 
 sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {
-  sgpe_status st = check_ctx(c);
+  sgpe_status st = check_ctx_no_flush(c);
   if (st != SGPE_OK) return st;
   if (!h) return SGPE_EINVAL;
   const size_t nx = size_t(c->p.nx), ny = size_t(c->p.ny), npts = nx * ny;
@@ -875,13 +925,14 @@ sgpe_status sgpe_set_psi(sgpe_ctx* c, const double* h) {
     return SGPE_EDEVICE;
   }
   c->has_state = true;
+  c->tail_pending = 0;
   c->latched = SGPE_OK;
   if (c->status_host) __atomic_store_n(c->status_host, 0u, __ATOMIC_RELEASE);   // the stream is idle
   return SGPE_OK;
 }
 
 sgpe_status sgpe_set_psi_device(sgpe_ctx* c, const void* d) {
-  sgpe_status st = check_ctx(c);
+  sgpe_status st = check_ctx(c);   // a pending tail completes: d may be the state buffer itself
   if (st != SGPE_OK) return st;
   if (!d || reinterpret_cast<uintptr_t>(d) % 16 != 0) return SGPE_EINVAL;
   const long long npts = (long long)c->p.nx * c->p.ny;
@@ -906,6 +957,7 @@ sgpe_status sgpe_set_psi_device(sgpe_ctx* c, const void* d) {
     return SGPE_EDEVICE;
   }
   c->has_state = true;
+  c->tail_pending = 0;
   c->latched = SGPE_OK;
   return SGPE_OK;
 }
@@ -950,7 +1002,7 @@ sgpe_status sgpe_get_psi(sgpe_ctx* c, double* h) {
 }
 
 static sgpe_status step_common(sgpe_ctx* c, int64_t n, bool imag) {
-  sgpe_status st = check_ctx(c);
+  sgpe_status st = check_ctx_no_flush(c);
   if (st != SGPE_OK) return st;
   if (n < 0) return SGPE_EINVAL;
   if (!c->has_state) return SGPE_ESTATE;
@@ -988,6 +1040,7 @@ sgpe_status sgpe_norm(sgpe_ctx* c, double* out) {
 
 sgpe_status sgpe_set_splitting(sgpe_ctx* c, int32_t order, int32_t real_space) {
   if (!c) return SGPE_EINVAL;
+  if (const sgpe_status st = check_ctx(c); st != SGPE_OK) return st;   // the pending tail, old scheme
   if ((order != SGPE_SPLIT_KRK && order != SGPE_SPLIT_RKR) ||
       (real_space != SGPE_RSPLIT_FROZEN && real_space != SGPE_RSPLIT_NLN))
     return SGPE_EINVAL;

@@ -62,6 +62,11 @@ struct sgpe_ctx {
   std::vector<void*> allocations;
   double* host_part = nullptr;   // pinned host copy of reduction partials, grown on demand
   size_t host_part_n = 0;
+  // A step call of the default complex64 schedule on a state the context owns leaves its last
+  // step's K(dt/2) and the inverse x-transform pending (1: real time, 2: imaginary time, 0: none);
+  // the next step call of the same kind merges them with its own first K(dt/2), and every other
+  // entry point completes them first (flush_tail, from check_ctx).
+  int tail_pending = 0;
   // sgpe_relax_imag's ring of energy checks in flight (allocated on its first call): the energies
   // on the device, their pinned host copies, and an event after each copy
   double* relax_dev = nullptr;
@@ -90,7 +95,13 @@ sgpe_schedule get_schedule(const sgpe_ctx* c);
 // Row-pass arguments with the real-space coefficients of a sub-step h (h <= 0: h = dt).
 sgpe::RowArgs row_args(const sgpe_ctx* c, double h = 0.0);
 sgpe::ColArgs col_args(const sgpe_ctx* c, bool imag, bool half);
+// Validates the context and makes its device current, then completes a pending step tail, so
+// that the state is in its documented layout: every entry point but the step calls uses this one.
 sgpe_status check_ctx(sgpe_ctx* c);
+// The same without completing the pending tail (the step calls, which may merge it).
+sgpe_status check_ctx_no_flush(sgpe_ctx* c);
+// Enqueue the pending step tail, if any (see sgpe_ctx::tail_pending).
+sgpe_status flush_tail(sgpe_ctx* c);
 // Arguments of the energy kernels for the context's state, with the given partial buffers
 // (kEnergyRowParts per row block, then one per column block).
 sgpe::EnergyArgs energy_args(const sgpe_ctx* c, double* row_partials, double* col_partials);

@@ -91,7 +91,8 @@ extern "C" sgpe_status sgpe_relax_imag(sgpe_ctx* c, int64_t check_every, int64_t
   auto enqueue = [&]() -> sgpe_status {
     const int64_t k = queued;
     if (k > 0) {
-      const sgpe_status s = sgpe_host::run_steps(c, steps_at(k) - steps_at(k - 1), true, nullptr);
+      sgpe_status s = sgpe_host::run_steps(c, steps_at(k) - steps_at(k - 1), true, nullptr);
+      if (s == SGPE_OK) s = sgpe_host::flush_tail(c);   // the check reads the completed state
       if (s != SGPE_OK) return s;
     }
     const hipError_t e = enqueue_check(c, a, int(k % kRing));

@@ -50,6 +50,7 @@ def test_delta_rule_matches_checks_made_one_call_at_a_time(api, precision):
     assert steps <= r["steps_taken"] <= steps + 2 * every and r["steps_taken"] % every == 0
     for _ in range((r["steps_taken"] - steps) // every):
         b.step_imag(every)
+        b.synchronize()      # each of the driver's chunks is completed for its energy check
     assert np.array_equal(a.get_psi(), b.get_psi())
     a.close()
     b.close()
