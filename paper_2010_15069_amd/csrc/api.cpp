@@ -369,6 +369,11 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag);
 
 sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev) {
   if (n == 0) return SGPE_OK;
+  if (c->prec == SGPE_C128 || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
+    // these schedules complete every call; a tail of the default schedule completes first
+    const sgpe_status st = flush_tail(c);
+    if (st != SGPE_OK) return st;
+  }
   if (c->prec == SGPE_C128) {
     if (ev) return SGPE_ESTATE;
     return run_steps_c128(c, n, imag);
