@@ -142,7 +142,7 @@ sgpe_status sgpe_get_psi(sgpe_ctx* ctx, double* psi_host);
 /* Advance n >= 0 real-time steps (Sec. 3.2).  Asynchronous on the context's stream.  The
  * fused schedule is K(dt/2) [R(dt) K(dt)]^(n-1) R(dt) K(dt/2); its result equals n separate
  * K(dt/2) R(dt) K(dt/2) steps up to rounding.  Consecutive calls continue one schedule: on a
- * complex64 context with the default splitting and a state it allocated itself, a call leaves its
+ * context with the default splitting and a state it allocated itself, a call leaves its
  * last K(dt/2) and inverse x-transform pending, and the next step call of the same kind merges them
  * with its own first K(dt/2), so calls of n1 and n2 steps give bit for bit what one call of
  * n1 + n2 steps gives.  Every other call on the context (get_psi, energy, norm, the observables,

@@ -337,19 +337,39 @@ static sgpe_status run_steps_c128(sgpe_ctx* c, int64_t n, bool imag) {
   const double npts = double(c->p.nx) * double(c->p.ny);
   hipStream_t s = c->stream;
   sgpe::RowArgsT<double> ra = row_args_t<double>(c, 0.0);
-  hipError_t e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_points, s);
-  if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, true), sgpe::NORM_NONE, c->col_points, s);
+  // a pending tail of this kind continues as in run_steps; one of the other kind completes first
+  const int kind = imag ? 2 : 1;
+  if (c->tail_pending != 0 && c->tail_pending != kind) {
+    const sgpe_status st = flush_tail(c);
+    if (st != SGPE_OK) return st;
+  }
+  const bool cont = c->tail_pending == kind;
+  c->tail_pending = 0;
+  hipError_t e;
+  if (cont) {
+    e = sgpe::launch_col(col_args_t<double>(c, imag, false), imag ? sgpe::NORM_DOT : sgpe::NORM_NONE, c->col_points,
+                         s);
+  } else {
+    e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_points, s);
+    if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, true), sgpe::NORM_NONE, c->col_points, s);
+  }
+  const bool defer = c->own_psi;
   for (int64_t i = 1; i <= n && e == hipSuccess; ++i) {
     sgpe::RowArgsT<double> r = ra;
     r.scale = 1.0 / npts;
-    if (imag && i > 1) {
+    if (imag && (i > 1 || cont)) {
       r.partials = c->partials;
       r.n_partials = col_groups(c);
     }
     e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, c->row_points, s);
     const bool last = (i == n);
+    if (last && defer) break;   // the last K(dt/2) and the inverse x-transform wait (flush_tail)
     const int nm = imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE;
     if (e == hipSuccess) e = sgpe::launch_col(col_args_t<double>(c, imag, last), nm, c->col_points, s);
+  }
+  if (e == hipSuccess && defer) {
+    c->tail_pending = kind;
+    return SGPE_OK;
   }
   if (e == hipSuccess) {
     sgpe::RowArgsT<double> r = ra;
@@ -369,8 +389,8 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag);
 
 sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev) {
   if (n == 0) return SGPE_OK;
-  if (c->prec == SGPE_C128 || c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
-    // these schedules complete every call; a tail of the default schedule completes first
+  if (c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
+    // the variants complete every call; a tail of the default schedule completes first
     const sgpe_status st = flush_tail(c);
     if (st != SGPE_OK) return st;
   }
@@ -442,15 +462,26 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
   return status_of(e);
 }
 
-// The tail a step call of the default schedule left: the last step's K(dt/2) (with the
+// The tail a step call of the default schedule left (either precision): the last step's K(dt/2) (with the
 // imaginary-time norm partials of the finished step) and the inverse x-transform (with its
 // rescaling), exactly as the call would have ended.
 sgpe_status flush_tail(sgpe_ctx* c) {
   if (c->tail_pending == 0) return SGPE_OK;
   const bool imag = c->tail_pending == 2;
   c->tail_pending = 0;
-  hipError_t e = sgpe::launch_col(col_args(c, imag, true), imag ? sgpe::NORM_SQ : sgpe::NORM_NONE, c->col_iters,
-                                  c->col_points, c->stream);
+  const int nm = imag ? sgpe::NORM_SQ : sgpe::NORM_NONE;
+  if (c->prec == SGPE_C128) {
+    hipError_t e = sgpe::launch_col(col_args_t<double>(c, imag, true), nm, c->col_points, c->stream);
+    if (e != hipSuccess) return status_of(e);
+    sgpe::RowArgsT<double> r = row_args_t<double>(c, 0.0);
+    r.scale = 1.0 / (double(c->p.nx) * double(c->p.ny));
+    if (imag) {
+      r.partials = c->partials;
+      r.n_partials = col_groups(c);
+    }
+    return status_of(sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_points, c->stream));
+  }
+  hipError_t e = sgpe::launch_col(col_args(c, imag, true), nm, c->col_iters, c->col_points, c->stream);
   if (e != hipSuccess) return status_of(e);
   RowArgs r = row_args(c);
   r.scale = float(1.0 / (double(c->p.nx) * double(c->p.ny)));

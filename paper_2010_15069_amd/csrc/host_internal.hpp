@@ -62,7 +62,7 @@ struct sgpe_ctx {
   std::vector<void*> allocations;
   double* host_part = nullptr;   // pinned host copy of reduction partials, grown on demand
   size_t host_part_n = 0;
-  // A step call of the default complex64 schedule on a state the context owns leaves its last
+  // A step call of the default schedule (either precision) on a state the context owns leaves its last
   // step's K(dt/2) and the inverse x-transform pending (1: real time, 2: imaginary time, 0: none);
   // the next step call of the same kind merges them with its own first K(dt/2), and every other
   // entry point completes them first (flush_tail, from check_ctx).

@@ -19,14 +19,15 @@ def env():
     return torch, m
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
 @pytest.mark.parametrize("kind", ["imag", "real"])
-def test_split_calls_equal_one_call(env, kind):
+def test_split_calls_equal_one_call(env, kind, precision):
     torch, m = env
     p = preset("ground_256", nx=128, ny=128)
     psi = initial_state(p, "tf", seed=5)
-    print(f"case: 128^2 {kind}, 7 + 13 + 1 steps vs 21", flush=True)
-    a = m.Solver(p).set_psi(psi)
-    b = m.Solver(p).set_psi(psi)
+    print(f"case: 128^2 {precision} {kind}, 7 + 13 + 1 steps vs 21", flush=True)
+    a = m.Solver(p, precision=precision).set_psi(psi)
+    b = m.Solver(p, precision=precision).set_psi(psi)
     step_a = a.step_imag if kind == "imag" else a.step_real
     step_b = b.step_imag if kind == "imag" else b.step_real
     step_a(7)
