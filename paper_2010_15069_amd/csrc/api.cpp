@@ -462,9 +462,9 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
   return status_of(e);
 }
 
-// The tail a step call of the default schedule left (either precision): the last step's K(dt/2) (with the
-// imaginary-time norm partials of the finished step) and the inverse x-transform (with its
-// rescaling), exactly as the call would have ended.
+// The tail a step call of the default schedule left (either precision): the last step's K(dt/2)
+// (with the imaginary-time norm partials of the finished step) and the inverse x-transform (with
+// its rescaling), exactly as the call would have ended.
 sgpe_status flush_tail(sgpe_ctx* c) {
   if (c->tail_pending == 0) return SGPE_OK;
   const bool imag = c->tail_pending == 2;
