@@ -1,8 +1,9 @@
 """Learned initial state for imaginary-time relaxation: a small Fourier neural operator (FNO).
 
 It maps the problem's parameters on the grid to a two-component order parameter that starts the
-plain split-step relaxation closer to the ground state.  The solver stays the judge: a predicted
-state is only a starting point, and the imaginary-time steps that follow are the ordinary ones.
+plain split-step relaxation closer to the ground state.  The solver has the last word: a
+predicted state is only a starting point, and the imaginary-time steps that follow are the
+ordinary ones.
 
 Model (one instance of the neural-operator family: lift, Fourier layers, project):
   * input channels on the n x n grid: V / max V, g / 100, Omega / 3, delta / 0.5, x / xmax,
