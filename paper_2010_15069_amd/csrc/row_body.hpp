@@ -214,6 +214,13 @@ __device__ __forceinline__ void row_apply_r(C (&v)[P], const RowArgsT<R>& a, int
 template <int N, bool IMAG, bool FULL, int P, class C, class R>
 __device__ __forceinline__ void row_apply_r_nln(C (&v)[P], const RowArgsT<R>& a, int row, int t, bool up,
                                                 const R (&hbx_r)[P], R hb_row) {
+  if constexpr (!FULL && !IMAG) {
+    // Real time with a diagonal linear part: the three factors are phases, which commute and leave
+    // both densities as they are, so their product is the one phase of the frozen form with the
+    // input's densities -- the same exponent, evaluated once instead of three times.
+    row_apply_r<N, IMAG, FULL>(v, a, row, t, up, hbx_r, hb_row);
+    return;
+  }
   constexpr int T = N / P;
   RCoef<R> c;
   c.sgn = up ? R(1) : R(-1);
