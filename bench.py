@@ -618,8 +618,9 @@ def main():
             "grid": [p.ny, p.nx], "components": 2, "dt": p_imag.dt, "dt_real": p.dt,
             "batch": args.batch,
         },
-        # one batch (K <= batch): a single timed call, whose time includes the call boundary's
-        # sweeps (2K + 2 sweeps for K steps); no spread to report
+        # one batch (K <= batch): a single timed call, whose time includes the call's start and end
+        # after and before a synchronisation (it continues the warm-up's schedule: 2K sweeps for K
+        # steps); no spread to report
         "step_ms_median": med, "step_ms_mad": mad if len(per) > 1 else None,
         "timed_calls": len(per),
         "note": f"the timed region is {len(per)} step_imag call(s) of at most {args.batch} steps, after the "
@@ -629,6 +630,9 @@ def main():
                 f"timed sweep completes the warm-up's pending half-step, and the one the last timed call "
                 f"leaves is completed after the timed region (by the energy read)",
         "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts * value / (HBM_PEAK_GBS * 1e9),
+        # the same rate priced at one sweep per step (32 B per point: each value read and written
+        # once), the floor no two-pass 2-D transform reaches; reported beside the two-sweep figure
+        "hbm_roofline_frac_step_one_sweep": BYTES_PER_POINT_STEP // 2 * npts * value / (HBM_PEAK_GBS * 1e9),
         "steady_state": {"step_ms": steady_ms, "split_steps_per_s": 1e3 / steady_ms,
                          "hbm_roofline_frac_step": BYTES_PER_POINT_STEP * npts / (steady_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                          "method": "(time of step_imag(1200) - time of step_imag(200)) / 1000, one event pair each"},
