@@ -142,7 +142,8 @@ sgpe_status sgpe_get_psi(sgpe_ctx* ctx, double* psi_host);
 /* Advance n >= 0 real-time steps (Sec. 3.2).  Asynchronous on the context's stream.  The
  * fused schedule is K(dt/2) [R(dt) K(dt)]^(n-1) R(dt) K(dt/2); its result equals n separate
  * K(dt/2) R(dt) K(dt/2) steps up to rounding.  Consecutive calls continue one schedule: on a
- * context with the default splitting and a state it allocated itself, a call leaves its
+ * context with the K-R-K splitting (either real-space form) on a complex64 state, or the default
+ * splitting on a complex128 one, and a state it allocated itself, a call leaves its
  * last K(dt/2) and inverse x-transform pending, and the next step call of the same kind merges them
  * with its own first K(dt/2), so calls of n1 and n2 steps give bit for bit what one call of
  * n1 + n2 steps gives.  Every other call on the context (get_psi, energy, norm, the observables,
@@ -235,9 +236,11 @@ sgpe_status sgpe_profile_kernels(sgpe_ctx* ctx, int32_t imag, int64_t n,
  * conserves); otherwise it is first order in the mean-field coupling, and N L N keeps the step
  * second order.  Imaginary time normalises after
  * every step in every variant.  Cost per step: two sweeps, except R-K-R in imaginary time (three:
- * the norm is needed between the two R halves of consecutive steps).  The variants run the
- * general row pass without prefetching; sgpe_profile_steps and sgpe_profile_kernels measure the
- * default only and return SGPE_ESTATE under a variant.  Takes effect for the next step call.
+ * the norm is needed between the two R halves of consecutive steps).  On a complex64 state K-R-K
+ * with N L N runs the default's fused schedule with N L N in its row pass, so consecutive step calls
+ * continue it as they do the default's; R-K-R runs a general row pass and completes every call.
+ * sgpe_profile_steps and sgpe_profile_kernels measure the default only and return SGPE_ESTATE
+ * under a variant.  Takes effect for the next step call.
  * Errors: SGPE_EINVAL (NULL context, unknown value). */
 typedef enum { SGPE_SPLIT_KRK = 0, SGPE_SPLIT_RKR = 1 } sgpe_split_order;
 typedef enum { SGPE_RSPLIT_FROZEN = 0, SGPE_RSPLIT_NLN = 1 } sgpe_real_space_split;

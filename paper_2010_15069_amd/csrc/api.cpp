@@ -389,7 +389,11 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag);
 
 sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>* ev) {
   if (n == 0) return SGPE_OK;
-  if (c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
+  const bool variant = c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN;
+  // K-R-K with R = N L N differs from the default only inside the row pass's R: on a complex64
+  // state it runs the fused schedule below with that row pass (and continues across calls)
+  const bool krk_nln = c->split_order == SGPE_SPLIT_KRK && c->split_rs == SGPE_RSPLIT_NLN && c->prec != SGPE_C128;
+  if (variant && !krk_nln) {
     // the variants complete every call; a tail of the default schedule completes first
     const sgpe_status st = flush_tail(c);
     if (st != SGPE_OK) return st;
@@ -398,10 +402,11 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
     if (ev) return SGPE_ESTATE;
     return run_steps_c128(c, n, imag);
   }
-  if (c->split_order != SGPE_SPLIT_KRK || c->split_rs != SGPE_RSPLIT_FROZEN) {
+  if (variant) {
     if (ev) return SGPE_ESTATE;
-    return run_steps_variant(c, n, imag);
+    if (!krk_nln) return run_steps_variant(c, n, imag);
   }
+  const int step_mode = krk_nln ? sgpe::ROW_STEP_NLN : sgpe::ROW_STEP;
   const double npts = double(c->p.nx) * double(c->p.ny);
   const float inv_n = float(1.0 / npts);  // exact: a power of two
   hipStream_t s = c->stream;
@@ -438,7 +443,7 @@ sgpe_status run_steps(sgpe_ctx* c, int64_t n, bool imag, std::vector<hipEvent_t>
       r.n_partials = col_groups(c);
     }
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
-    e = sgpe::launch_row(r, sgpe::ROW_STEP, imag, c->full2x2, c->row_iters, c->row_points, s);
+    e = sgpe::launch_row(r, step_mode, imag, c->full2x2, c->row_iters, c->row_points, s);
     if (e != hipSuccess) return status_of(e);
     if (ev) (void)hipEventRecord((*ev)[evi++], s);
     const bool last = (i == n);
@@ -493,9 +498,8 @@ sgpe_status flush_tail(sgpe_ctx* c) {
   return status_of(e);
 }
 
-// The splitting variants (sgpe_set_splitting), built from the general row pass:
-//   K-R-K with R as N L N:  row FWD; col K(dt/2); n x [row (inv-x, scale, R(dt), fwd-x); col K]; row INV
-//     -- the fused schedule above with the general row pass in place of the step row pass;
+// The R-K-R splitting variants (sgpe_set_splitting), built from the general row pass (K-R-K with
+// R as N L N is the fused schedule of run_steps with the ROW_STEP_NLN row pass):
 //   R-K-R, real time:       row (R(dt/2), fwd-x); n x [col K(dt); row (inv-x, R(dt/2), R(dt/2), fwd-x)],
 //                           the last row pass (inv-x, R(dt/2)) only;
 //   R-K-R, imaginary time:  the norm falls between the two R halves, so each step's row work takes
@@ -535,25 +539,6 @@ static sgpe_status run_steps_variant(sgpe_ctx* c, int64_t n, bool imag) {
   auto col = [&](bool half, int norm_mode) {
     if (e == hipSuccess) e = sgpe::launch_col(col_args(c, imag, half), norm_mode, c->col_iters, c->col_points, s);
   };
-  if (c->split_order == SGPE_SPLIT_KRK) {
-    RowArgs ra = row_args(c);
-    e = sgpe::launch_row(ra, sgpe::ROW_FWD, false, false, c->row_iters, c->row_points, s);
-    col(true, sgpe::NORM_NONE);
-    for (int64_t i = 1; i <= n; ++i) {
-      const bool scaled = imag && i > 1;
-      row(p.dt, sgpe::VAR_INV | sgpe::VAR_FWD, 1, scaled ? c->partials : nullptr, scaled ? col_groups(c) : 0, false);
-      const bool last = (i == n);
-      col(last, imag ? (last ? sgpe::NORM_SQ : sgpe::NORM_DOT) : sgpe::NORM_NONE);
-    }
-    RowArgs r = ra;
-    r.scale = inv_n;
-    if (imag) {
-      r.partials = c->partials;
-      r.n_partials = col_groups(c);
-    }
-    if (e == hipSuccess) e = sgpe::launch_row(r, sgpe::ROW_INV, false, false, c->row_iters, c->row_points, s);
-    return status_of(e);
-  }
   // R-K-R
   const double h = 0.5 * p.dt;
   row(h, sgpe::VAR_FWD, 1, nullptr, 0, false);

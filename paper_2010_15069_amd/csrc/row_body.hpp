@@ -282,6 +282,7 @@ __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
   const int rloc = pair / T;
   const int t = pair - rloc * T;
   const int row0 = wg * ITERS * a.rows_per_block + rloc;
+  constexpr bool STEP = MODE == ROW_STEP || MODE == ROW_STEP_NLN;
   const LdsView<C> lds{lds_raw + rloc * 2 * SLOTS + comp, 1};
   // element `pos` of this lane's component is at byte offset PB pos from the row start; 32-bit
   // offsets from a wave-uniform base
@@ -307,7 +308,7 @@ __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
   load_twiddles<N>(tr, t, a.tw);
   // spatial Raman tables: the x part is the same for every row of the workgroup
   R hbx_r[P], hby_r[ITERS];
-  if constexpr (FULL && MODE == ROW_STEP) {
+  if constexpr (FULL && STEP) {
 #pragma unroll
     for (int m = 0; m < P; ++m) hbx_r[m] = a.hbx[t + T * m];
 #pragma unroll
@@ -334,7 +335,11 @@ __device__ __forceinline__ void row_body(const RowArgsT<R>& a, int wg) {
       }
 #pragma unroll
       for (int m = 0; m < P; ++m) v[m] = vscale(v[m], s);
-      if constexpr (MODE == ROW_STEP) {
+      if constexpr (MODE == ROW_STEP_NLN) {
+        row_apply_r_nln<N, IMAG, FULL>(v, a, row0 + it * a.rows_per_block, t, comp == 0, hbx_r,
+                                       FULL ? hby_r[it] : R(0));
+        fwd_pass<N>(v, lds, t, tr);
+      } else if constexpr (MODE == ROW_STEP) {
         row_apply_r<N, IMAG, FULL>(v, a, row0 + it * a.rows_per_block, t, comp == 0, hbx_r,
                                    FULL ? hby_r[it] : R(0));
         fwd_pass<N>(v, lds, t, tr);

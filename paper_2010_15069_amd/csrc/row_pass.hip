@@ -73,10 +73,14 @@ static hipError_t row_launch_t(const RowArgs& a, const RowArgs* tab, int count, 
     }
     return hipGetLastError();
   } else if (tab) {
-    if (points == 16) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 16>), grid, block, lds, s, tab);
-    else if constexpr (N <= kMaxNSmallP) {
-      if (points == 8) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 8>), grid, block, lds, s, tab);
-      else hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 4>), grid, block, lds, s, tab);
+    if constexpr (MODE == ROW_STEP_NLN) {
+      return hipErrorInvalidValue;   // batches run the default split only
+    } else {
+      if (points == 16) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 16>), grid, block, lds, s, tab);
+      else if constexpr (N <= kMaxNSmallP) {
+        if (points == 8) hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 8>), grid, block, lds, s, tab);
+        else hipLaunchKernelGGL((row_kernel_batch<N, MODE, IMAG, FULL, 4>), grid, block, lds, s, tab);
+      }
     }
   } else if (points == 16) {
     if (iters == 2) hipLaunchKernelGGL((row_kernel<N, MODE, IMAG, FULL, 2, 16>), grid, block, lds, s, a);
@@ -99,6 +103,12 @@ static hipError_t row_launch_n(const RowArgs& a, const RowArgs* tab, int count, 
       if (imag) return full ? row_launch_t<N, ROW_STEP, true, true>(a, tab, count, iters, points, s)
                             : row_launch_t<N, ROW_STEP, true, false>(a, tab, count, iters, points, s);
       return full ? row_launch_t<N, ROW_STEP, false, true>(a, tab, count, iters, points, s)
+                  : row_launch_t<N, ROW_STEP, false, false>(a, tab, count, iters, points, s);
+    case ROW_STEP_NLN:
+      // real time with a diagonal linear part: N L N is exactly the frozen form's one phase
+      if (imag) return full ? row_launch_t<N, ROW_STEP_NLN, true, true>(a, tab, count, iters, points, s)
+                            : row_launch_t<N, ROW_STEP_NLN, true, false>(a, tab, count, iters, points, s);
+      return full ? row_launch_t<N, ROW_STEP_NLN, false, true>(a, tab, count, iters, points, s)
                   : row_launch_t<N, ROW_STEP, false, false>(a, tab, count, iters, points, s);
     case ROW_VAR:
       if (imag) return full ? row_launch_t<N, ROW_VAR, true, true>(a, tab, count, iters, points, s)

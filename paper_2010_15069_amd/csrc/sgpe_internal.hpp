@@ -21,6 +21,7 @@ enum RowMode : int {
   ROW_INV = 1,   // inverse x-FFT and scale (leave it: real space)
   ROW_STEP = 2,  // inverse x-FFT, scale, real-space exponential R(h), forward x-FFT
   ROW_VAR = 3,   // the general row pass of the splitting variants, steered by RowArgs::var_*
+  ROW_STEP_NLN = 4,  // ROW_STEP with R(h) = N(h/2) L(h) N(h/2) (the K-R-K schedule of that split)
 };
 
 // Stages of the general row pass (ROW_VAR), run in this order when their flag is set: inverse
